@@ -1,0 +1,87 @@
+// dilbm_internal.h -- device-visible structures of libdilbm (internal to the library).
+//
+// Memory layout of one solve in HBM:
+//   pop[2]        two population buffers, structure of arrays [9][ny][nx] of shifted,
+//                 scaled populations g_i = 36 (f_i - w_i rho0) in FP32 (or FP16 times
+//                 2^k); the factor 36 makes the D2Q9 weights exact integers.  The pull
+//                 scheme keeps post-collision values: node x at time t_n finds f_i in
+//                 pop[p][i][x - c_i].
+//   tile_count[2] per tile, number of bodies whose phi support may touch the tile
+//   tile_list[2]  per tile, `list_cap` body indices
+//   bstate[2]     body state SoA [5][nb]: x, y, ux, uy, omega (FP64)
+//   bconst        body constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
+//   acc[2]        FP64 force accumulators [(nb + 1) * 3]: Fx, Fy, T per body, then the
+//                 wall force in the last slot
+//   err           sticky error bits
+// Everything double-buffered is indexed by the step parity p: a step with parity p reads
+// slot p and writes slot 1 - p (bodies, lists) or both (populations).
+#pragma once
+
+#include <stdint.h>
+
+namespace dilbm {
+
+constexpr int kQ = 9;
+constexpr int kNumTileShapes = 5;
+constexpr int kTileTX[kNumTileShapes] = {64, 128, 256, 32, 16};
+constexpr int kTileTY[kNumTileShapes] = {4, 2, 1, 8, 16};
+constexpr int kBlockThreads = 256;       // every tile shape has 256 nodes
+constexpr int kBodyChunk = 64;           // bodies staged in LDS at a time
+constexpr int kMaxListCap = 1024;
+
+enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
+
+struct SolveDesc {
+  // geometry and tiling
+  int32_t nx, ny;
+  int32_t tx, ty;              // tile extent in nodes
+  int32_t tiles_x, tiles_y;
+  int64_t tile_base;           // first global tile index of this solve
+  int32_t body_base;           // first global body index of this solve
+  int32_t nbodies;
+  int32_t list_cap;
+  uint32_t wall_mask;
+  // chunk control (rewritten by the host before every chunk)
+  int32_t active_steps;        // step k of the chunk runs iff k < active_steps
+  int32_t parity0;             // parity of the solve's state at the chunk start
+  // FP32 node constants
+  float omega;                 // 1 / tau
+  float khalf;                 // 1 - 1 / (2 tau)
+  float rho0;
+  float rho36;                 // 36 rho0
+  float Gx, Gy;
+  float phi_k;                 // 4 / eps * log2(e): phi = 1 / (1 + 2^(-l * phi_k))
+  float lcut;                  // -cutoff * eps
+  float wall_h;
+  float kappa;                 // force scale of Eqs. (18)-(19)
+  float store_scale, store_inv;
+  int32_t storage;
+  // FP64 body constants
+  double rho0_d;
+  double gx, gy;
+  double eps_p, eps_p1, eps_w, eps_w1, xi;
+  double wall_h_d;
+  double support;              // cutoff * eps: phi support beyond the radius
+  // device buffers
+  void *pop[2];
+  int32_t *tile_count[2];
+  int32_t *tile_list[2];
+  double *bstate[2];
+  const double *bconst;
+  double *acc[2];
+  int32_t *err;
+};
+
+// A rectangle of nodes [x, x + w) x [y, y + h) inside one solve.
+struct Region {
+  int32_t x, y, w, h;
+};
+
+// Per-launch batch header, read by every kernel of a step.
+struct BatchHeader {
+  int64_t total_tiles;
+  int32_t total_bodies;
+  int32_t nsolves;
+};
+
+}  // namespace dilbm

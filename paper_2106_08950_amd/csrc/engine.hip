@@ -1,0 +1,1579 @@
+// engine.hip -- host runtime and C ABI of libdilbm.
+//
+// A Solve owns the device state of one DI-LBM problem (populations, tile lists, bodies,
+// force accumulators).  An Engine advances a set of member solves together: every step
+// is one k_collide launch over the tiles of all members and one k_bodies launch over
+// their bodies; K-step chunks are captured once into a HIP graph and replayed, while the
+// per-solve step counts and parities live in a small descriptor table that is uploaded
+// before every chunk.  dilbm_solver is an Engine with one member and its own device
+// memory; dilbm_pool is an Engine whose members are carved out of one device arena and
+// may join and leave between chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dilbm.h"
+#include "dilbm_internal.h"
+#include "kernels.h"
+
+namespace dilbm {
+
+// ---------------------------------------------------------------------------------------
+// errors
+
+struct Fail {
+  dilbm_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(dilbm_status st, const std::string &msg) { throw Fail{st, msg}; }
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      dilbm_status st_ = (e_ == hipErrorOutOfMemory) ? DILBM_ENOMEM : DILBM_EDEVICE;    \
+      fail(st_, std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    }                                                                                   \
+  } while (0)
+
+thread_local std::string g_thread_error;
+
+constexpr uint64_t kAlign = 256;
+inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------------------
+// first-fit arena over caller- or pool-owned device memory
+
+class Arena {
+ public:
+  Arena(char *base, uint64_t bytes) : base_(base), size_(bytes) {
+    if (bytes) free_[0] = bytes;
+  }
+  char *base() const { return base_; }
+  uint64_t size() const { return size_; }
+  bool alloc(uint64_t bytes, uint64_t *off) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes;
+        const uint64_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = align_up(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t free_bytes() const { return size_ - used_; }
+
+ private:
+  char *base_;
+  uint64_t size_;
+  uint64_t used_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+struct Mem {
+  void *ptr = nullptr;
+  uint64_t bytes = 0;
+  Arena *arena = nullptr;
+  uint64_t off = 0;
+};
+
+Mem mem_alloc(Arena *arena, uint64_t bytes) {
+  Mem m;
+  m.bytes = align_up(std::max<uint64_t>(bytes, kAlign));
+  if (arena) {
+    if (!arena->alloc(m.bytes, &m.off)) fail(DILBM_EAGAIN, "arena has no free block large enough");
+    m.arena = arena;
+    m.ptr = arena->base() + m.off;
+  } else {
+    HIPCHK(hipMalloc(&m.ptr, m.bytes));
+  }
+  return m;
+}
+
+void mem_free(Mem &m) {
+  if (!m.ptr) return;
+  if (m.arena)
+    m.arena->release(m.off, m.bytes);
+  else
+    (void)hipFree(m.ptr);
+  m = Mem{};
+}
+
+// ---------------------------------------------------------------------------------------
+// parameters and per-solve layout
+
+int max_tiles_for(int nx, int ny) {
+  int m = 0;
+  for (int s = 0; s < kNumTileShapes; ++s)
+    m = std::max(m, ((nx + kTileTX[s] - 1) / kTileTX[s]) * ((ny + kTileTY[s] - 1) / kTileTY[s]));
+  return m;
+}
+
+void validate(const dilbm_params *p) {
+  if (!p) fail(DILBM_EINVAL, "params is NULL");
+  if (p->abi_version != DILBM_ABI_VERSION) fail(DILBM_EABI, "abi_version mismatch");
+  if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536 ||
+      (int64_t)p->nx * p->ny >= (int64_t)1 << 31)
+    fail(DILBM_EINVAL, "nx, ny must be in [1, 65536] with nx*ny < 2^31");
+  auto fin = [](double v) { return std::isfinite(v); };
+  if (!(p->tau > 0.5) || !fin(p->tau)) fail(DILBM_EINVAL, "tau must be > 0.5");
+  if (!(p->rho0 > 0.0) || !fin(p->rho0)) fail(DILBM_EINVAL, "rho0 must be > 0");
+  if (!(p->interface_width > 0.0) || !fin(p->interface_width))
+    fail(DILBM_EINVAL, "interface_width must be > 0");
+  if (!(p->phi_cutoff > 0.0) || !fin(p->phi_cutoff)) fail(DILBM_EINVAL, "phi_cutoff must be > 0");
+  for (int i = 0; i < 2; ++i)
+    if (!fin(p->body_force[i]) || !fin(p->gravity[i]))
+      fail(DILBM_EINVAL, "body_force and gravity must be finite");
+  if (p->wall_mask & ~3u) fail(DILBM_EINVAL, "wall_mask has unknown bits");
+  if (p->wall_mask && (!(p->wall_half_thickness > 0.0) || !fin(p->wall_half_thickness)))
+    fail(DILBM_EINVAL, "wall_half_thickness must be > 0");
+  if (p->force_mode != 0 && p->force_mode != 1) fail(DILBM_EINVAL, "unknown force_mode");
+  if (!(p->coll_eps_p > 0) || !(p->coll_eps_p_overlap > 0) || !(p->coll_eps_w > 0) ||
+      !(p->coll_eps_w_overlap > 0) || !(p->coll_xi >= 0) || !fin(p->coll_xi))
+    fail(DILBM_EINVAL, "collision stiffnesses must be > 0 and xi >= 0");
+  if (p->storage != DILBM_STORE_FP32 && p->storage != DILBM_STORE_FP16)
+    fail(DILBM_EINVAL, "unknown storage");
+  if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)
+    fail(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24]");
+  if (p->list_capacity < 0 || p->list_capacity > kMaxListCap)
+    fail(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
+  if (p->tile < -1 || p->tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
+}
+
+void validate_bodies(int32_t n, const double *pos, const double *vel, const double *omega,
+                     const double *radius, const double *density) {
+  if (n < 0) fail(DILBM_EINVAL, "negative body count");
+  if (n > 0 && (!pos || !radius || !density))
+    fail(DILBM_EINVAL, "pos, radius and density are required");
+  for (int32_t b = 0; b < n; ++b) {
+    if (!std::isfinite(pos[2 * b]) || !std::isfinite(pos[2 * b + 1]))
+      fail(DILBM_EINVAL, "body position not finite");
+    if (!(radius[b] > 0.0) || !std::isfinite(radius[b])) fail(DILBM_EINVAL, "radius must be > 0");
+    if (!(density[b] > 0.0) || !std::isfinite(density[b]))
+      fail(DILBM_EINVAL, "density must be > 0");
+    if (vel && (!std::isfinite(vel[2 * b]) || !std::isfinite(vel[2 * b + 1])))
+      fail(DILBM_EINVAL, "body velocity not finite");
+    if (omega && !std::isfinite(omega[b])) fail(DILBM_EINVAL, "body spin not finite");
+  }
+}
+
+struct BodyLayout {
+  int cap = 1;
+  uint64_t counts = 0, lists = 0, bstate = 0, bconst = 0, acc = 0, total = 0;
+};
+
+BodyLayout body_layout(const dilbm_params &p, int nb) {
+  BodyLayout L;
+  L.cap = p.list_capacity > 0 ? p.list_capacity : std::max(1, std::min(nb, 128));
+  const uint64_t mt = (uint64_t)max_tiles_for(p.nx, p.ny);
+  uint64_t o = 0;
+  L.counts = o;
+  o += align_up(2 * mt * 4);
+  L.lists = o;
+  o += align_up(2 * mt * (uint64_t)L.cap * 4);
+  L.bstate = o;
+  o += align_up(2 * 5 * (uint64_t)std::max(nb, 1) * 8);
+  L.bconst = o;
+  o += align_up(5 * (uint64_t)std::max(nb, 1) * 8);
+  L.acc = o;
+  o += align_up(2 * 3 * (uint64_t)(nb + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+uint64_t pop_bytes(const dilbm_params &p) {
+  return align_up(2ull * kQ * (uint64_t)p.nx * p.ny * (p.storage == DILBM_STORE_FP16 ? 2 : 4));
+}
+
+// ---------------------------------------------------------------------------------------
+
+struct Solve {
+  dilbm_params prm{};
+  int nb = 0;
+  int shape = 0;
+  Mem pops, body;
+  BodyLayout L;
+  SolveDesc desc{};
+  int64_t steps_done = 0;  // steps enqueued
+  int64_t target = -1;     // pool: steps requested
+  int slot = -1;
+  int64_t ticket = -1;
+  bool forces_valid = false;
+  bool finished = false;   // pool: all steps enqueued, left the member set
+  hipEvent_t done_ev = nullptr;
+  dilbm_status poison = DILBM_OK;
+  std::string err;
+
+  int64_t remaining() const { return target < 0 ? INT64_MAX : target - steps_done; }
+  int parity() const { return (int)(steps_done & 1); }
+  int tiles() const { return desc.tiles_x * desc.tiles_y; }
+};
+
+void fill_desc(Solve &s) {
+  const dilbm_params &p = s.prm;
+  SolveDesc &d = s.desc;
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.tx = kTileTX[s.shape];
+  d.ty = kTileTY[s.shape];
+  d.tiles_x = (p.nx + d.tx - 1) / d.tx;
+  d.tiles_y = (p.ny + d.ty - 1) / d.ty;
+  d.nbodies = s.nb;
+  d.list_cap = s.L.cap;
+  d.wall_mask = p.wall_mask;
+  d.omega = (float)(1.0 / p.tau);
+  d.khalf = (float)(1.0 - 0.5 / p.tau);
+  d.rho0 = (float)p.rho0;
+  d.rho36 = (float)(36.0 * p.rho0);
+  d.Gx = (float)p.body_force[0];
+  d.Gy = (float)p.body_force[1];
+  d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
+  d.lcut = (float)(-p.phi_cutoff * p.interface_width);
+  d.wall_h = (float)p.wall_half_thickness;
+  d.kappa = p.force_mode == DILBM_FORCE_PAPER_LITERAL ? (float)(1.0 - 0.5 / p.tau) : 1.0f;
+  d.storage = p.storage;
+  const double sc = p.storage == DILBM_STORE_FP16 ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
+  d.store_scale = (float)sc;
+  d.store_inv = (float)(1.0 / sc);
+  d.rho0_d = p.rho0;
+  d.gx = p.gravity[0];
+  d.gy = p.gravity[1];
+  d.eps_p = p.coll_eps_p;
+  d.eps_p1 = p.coll_eps_p_overlap;
+  d.eps_w = p.coll_eps_w;
+  d.eps_w1 = p.coll_eps_w_overlap;
+  d.xi = p.coll_xi;
+  d.wall_h_d = p.wall_half_thickness;
+  d.support = p.phi_cutoff * p.interface_width;
+  const uint64_t half = (uint64_t)kQ * p.nx * p.ny * (p.storage == DILBM_STORE_FP16 ? 2 : 4);
+  char *pp = (char *)s.pops.ptr;
+  d.pop[0] = pp;
+  d.pop[1] = pp + half;
+  char *bb = (char *)s.body.ptr;
+  const uint64_t mt = (uint64_t)max_tiles_for(p.nx, p.ny);
+  d.tile_count[0] = (int32_t *)(bb + s.L.counts);
+  d.tile_count[1] = d.tile_count[0] + mt;
+  d.tile_list[0] = (int32_t *)(bb + s.L.lists);
+  d.tile_list[1] = d.tile_list[0] + mt * s.L.cap;
+  const uint64_t nbs = (uint64_t)std::max(s.nb, 1);
+  d.bstate[0] = (double *)(bb + s.L.bstate);
+  d.bstate[1] = d.bstate[0] + 5 * nbs;
+  d.bconst = (const double *)(bb + s.L.bconst);
+  d.acc[0] = (double *)(bb + s.L.acc);
+  d.acc[1] = d.acc[0] + 3 * (uint64_t)(s.nb + 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// Engine
+
+class Engine {
+ public:
+  Engine(int device, void *stream) : device_(device) {
+    HIPCHK(hipSetDevice(device));
+    if (stream) {
+      stream_ = (hipStream_t)stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+      own_stream_ = true;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+    HIPCHK(hipMalloc(&d_hdr_, sizeof(BatchHeader)));
+    HIPCHK(hipMalloc(&d_one_desc_, sizeof(SolveDesc) * 2));
+    HIPCHK(hipMalloc(&d_one_hdr_, sizeof(BatchHeader) * 2));
+    HIPCHK(hipHostMalloc(&h_one_, sizeof(SolveDesc) * 2 + sizeof(BatchHeader) * 2));
+    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&one_ev_[i], hipEventDisableTiming));
+    for (int i = 0; i < kRing; ++i) HIPCHK(hipEventCreateWithFlags(&ring_ev_[i], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&table_ev_, hipEventDisableTiming));
+    HIPCHK(hipDeviceGetAttribute(&num_cu_, hipDeviceAttributeMultiprocessorCount, device));
+  }
+
+  ~Engine() {
+    (void)hipSetDevice(device_);
+    (void)hipStreamSynchronize(stream_);
+    (void)hipStreamSynchronize(aux_);
+    clear_graphs();
+    for (auto &e : timing_ev_) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    (void)hipFree(d_descs_);
+    (void)hipFree(d_tile_solve_);
+    (void)hipFree(d_body_solve_);
+    (void)hipFree(d_err_);
+    (void)hipFree(d_hdr_);
+    (void)hipFree(d_one_desc_);
+    (void)hipFree(d_one_hdr_);
+    (void)hipFree(d_one_bodies_);
+    (void)hipHostFree(h_one_);
+    for (int i = 0; i < kRing; ++i) {
+      (void)hipHostFree(h_ring_[i]);
+      (void)hipEventDestroy(ring_ev_[i]);
+    }
+    (void)hipHostFree(h_tile_solve_);
+    (void)hipHostFree(h_body_solve_);
+    (void)hipHostFree(h_err_);
+    for (int i = 0; i < 2; ++i) (void)hipEventDestroy(one_ev_[i]);
+    (void)hipEventDestroy(table_ev_);
+    (void)hipStreamDestroy(aux_);
+    if (own_stream_) (void)hipStreamDestroy(stream_);
+  }
+
+  hipStream_t stream() const { return stream_; }
+  hipStream_t aux() const { return aux_; }
+  int device() const { return device_; }
+  int shape() const { return shape_; }
+  int storage() const { return storage_; }
+  void set_storage(int st) { storage_ = st; }
+  int graph_steps() const { return graph_steps_; }
+  void set_graph_steps(int k) {
+    if (k != graph_steps_) clear_graphs();
+    graph_steps_ = k;
+  }
+  const std::vector<Solve *> &members() const { return members_; }
+
+  // ---- membership ---------------------------------------------------------------------
+  void add(Solve *s) {
+    ensure_err_capacity();
+    int slot = -1;
+    for (int i = 0; i < (int)slot_used_.size(); ++i)
+      if (!slot_used_[i]) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) {
+      slot = (int)slot_used_.size();
+      slot_used_.push_back(false);
+      ensure_err_capacity();
+    }
+    slot_used_[slot] = true;
+    s->slot = slot;
+    s->desc.err = d_err_ + slot;
+    HIPCHK(launch_fill_i32(d_err_ + slot, 1, 0, stream_));
+    members_.push_back(s);
+    dirty_ = true;
+  }
+
+  // Leave the member set; the slot (and its error bits) stays reserved until release().
+  void leave(Solve *s) {
+    auto it = std::find(members_.begin(), members_.end(), s);
+    if (it != members_.end()) {
+      members_.erase(it);
+      dirty_ = true;
+    }
+  }
+
+  void remove(Solve *s) {
+    leave(s);
+    if (s->slot >= 0 && s->slot < (int)slot_used_.size()) slot_used_[s->slot] = false;
+    s->slot = -1;
+  }
+
+  void mark_dirty() { dirty_ = true; }
+
+  // ---- one-solve helpers (scratch descriptor) ----------------------------------------
+  // Upload s's descriptor (with parity0 = its current parity) into the scratch slot used by
+  // single-solve kernels on `st`; waits for the previous use of the staging buffer.
+  SolveDesc *one_desc(Solve &s, hipStream_t st, int which) {
+    HIPCHK(hipEventSynchronize(one_ev_[which]));
+    SolveDesc *h = (SolveDesc *)h_one_ + which;
+    *h = s.desc;
+    h->parity0 = s.parity();
+    h->active_steps = 1;
+    // one-solve launches number tiles and bodies from 0, not from the solve's place in
+    // the batch
+    h->tile_base = 0;
+    h->body_base = 0;
+    HIPCHK(hipMemcpyAsync(d_one_desc_ + which, h, sizeof(SolveDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(one_ev_[which], st));
+    return d_one_desc_ + which;
+  }
+
+  // Bin the bodies of s's current state into its current-parity lists.
+  void bin_current(Solve &s, hipStream_t st) {
+    const int p = s.parity();
+    HIPCHK(launch_fill_i32(s.desc.tile_count[p], max_tiles_for(s.prm.nx, s.prm.ny), 0, st));
+    if (s.nb == 0) return;
+    SolveDesc *dd = one_desc(s, st, 0);
+    if (s.nb > one_bodies_cap_) {
+      HIPCHK(hipStreamSynchronize(st));
+      (void)hipFree(d_one_bodies_);
+      d_one_bodies_ = nullptr;
+      HIPCHK(hipMalloc(&d_one_bodies_, sizeof(int32_t) * s.nb));
+      one_bodies_cap_ = s.nb;
+    }
+    HIPCHK(launch_fill_i32(d_one_bodies_, s.nb, 0, st));
+    BatchHeader *hh = (BatchHeader *)((SolveDesc *)h_one_ + 2);
+    HIPCHK(hipEventSynchronize(table_ev_));
+    hh->total_tiles = 0;
+    hh->total_bodies = s.nb;
+    hh->nsolves = 1;
+    HIPCHK(hipMemcpyAsync(d_one_hdr_, hh, sizeof(BatchHeader), hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(table_ev_, st));
+    HIPCHK(launch_bodies(true, std::max(1, (s.nb + 3) / 4), st, dd, d_one_bodies_, d_one_hdr_, 0));
+  }
+
+  void set_shape(int shape) {
+    if (shape == shape_) return;
+    shape_ = shape;
+    clear_graphs();
+    for (Solve *s : members_) {
+      s->shape = shape;
+      fill_desc(*s);
+      s->desc.err = d_err_ + s->slot;
+      bin_current(*s, stream_);
+    }
+    dirty_ = true;
+  }
+
+  // ---- chunks ---------------------------------------------------------------------------
+  // Enqueue up to K steps of every member (fewer for members with fewer left).  Returns
+  // the largest number of steps any member took.
+  int run_chunk(int K, bool allow_graph) {
+    if (members_.empty() || K <= 0) return 0;
+    if (dirty_) rebuild_tables();
+    int kmax = 0;
+    // descriptor upload through a ring of pinned staging buffers
+    const int r = ring_pos_;
+    ring_pos_ = (ring_pos_ + 1) % kRing;
+    HIPCHK(hipEventSynchronize(ring_ev_[r]));
+    ensure_ring(r);
+    SolveDesc *h = (SolveDesc *)h_ring_[r];
+    for (int i = 0; i < (int)slot_used_.size(); ++i) {
+      h[i] = SolveDesc{};
+      h[i].active_steps = 0;
+    }
+    for (Solve *s : members_) {
+      const int64_t a = std::min<int64_t>(K, s->remaining());
+      s->desc.active_steps = (int32_t)a;
+      s->desc.parity0 = s->parity();
+      h[s->slot] = s->desc;
+      kmax = std::max<int>(kmax, (int)a);
+    }
+    HIPCHK(hipMemcpyAsync(d_descs_, h, sizeof(SolveDesc) * slot_used_.size(),
+                          hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipEventRecord(ring_ev_[r], stream_));
+    if (kmax == 0) return 0;
+    if (timing_) {
+      launch_steps(kmax, true);
+    } else if (allow_graph && kmax == K && K > 1) {
+      hipGraphExec_t g = graph_for(K);
+      HIPCHK(hipGraphLaunch(g, stream_));
+    } else {
+      launch_steps(kmax, false);
+    }
+    for (Solve *s : members_) {
+      s->steps_done += s->desc.active_steps;
+      if (s->desc.active_steps > 0) s->forces_valid = true;
+    }
+    return kmax;
+  }
+
+  // Error bits of every slot (synchronous).
+  void read_errors() {
+    if (slot_used_.empty()) return;
+    HIPCHK(hipMemcpyAsync(h_err_, d_err_, sizeof(int32_t) * slot_used_.size(),
+                          hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+  }
+  int32_t err_of(const Solve &s) const { return h_err_[s.slot]; }
+  int32_t read_error_of(Solve &s, hipStream_t st) {
+    int32_t v = 0;
+    HIPCHK(hipMemcpyAsync(&h_err_[s.slot], d_err_ + s.slot, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    v = h_err_[s.slot];
+    return v;
+  }
+
+  // ---- timing -------------------------------------------------------------------------
+  void set_timing(bool on) {
+    timing_ = on;
+    timing_used_ = 0;
+    timed_ms_ = 0.0;
+    timed_launches_ = 0;
+  }
+  void collect_timing() {
+    if (!timing_used_) return;
+    HIPCHK(hipStreamSynchronize(stream_));
+    for (int i = 0; i < timing_used_; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, timing_ev_[i].first, timing_ev_[i].second));
+      timed_ms_ += ms;
+    }
+    timed_launches_ += timing_used_;
+    timing_used_ = 0;
+  }
+  double timed_ms() const { return timed_ms_; }
+  int64_t timed_launches() const { return timed_launches_; }
+
+  int64_t total_tiles() const { return total_tiles_; }
+  int total_bodies() const { return total_bodies_; }
+
+  void set_persistent(bool p) {
+    if (p != persistent_) {
+      persistent_ = p;
+      clear_graphs();
+    }
+  }
+
+ private:
+  static constexpr int kRing = 4;
+
+  void ensure_err_capacity() {
+    const int need = std::max<int>(8, (int)slot_used_.size());
+    if (need <= err_cap_) return;
+    int cap = std::max(need, err_cap_ * 2);
+    int32_t *d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(int32_t) * cap));
+    HIPCHK(launch_fill_i32(d, cap, 0, stream_));
+    if (d_err_) {
+      HIPCHK(hipMemcpyAsync(d, d_err_, sizeof(int32_t) * err_cap_, hipMemcpyDeviceToDevice, stream_));
+      HIPCHK(hipStreamSynchronize(stream_));
+      (void)hipFree(d_err_);
+    }
+    d_err_ = d;
+    int32_t *h = nullptr;
+    HIPCHK(hipHostMalloc(&h, sizeof(int32_t) * cap));
+    std::memset(h, 0, sizeof(int32_t) * cap);
+    (void)hipHostFree(h_err_);
+    h_err_ = h;
+    err_cap_ = cap;
+    for (Solve *s : members_) s->desc.err = d_err_ + s->slot;
+    clear_graphs();
+  }
+
+  void ensure_ring(int r) {
+    const size_t need = sizeof(SolveDesc) * std::max<size_t>(1, slot_used_.size());
+    if (need <= ring_bytes_[r]) return;
+    (void)hipHostFree(h_ring_[r]);
+    h_ring_[r] = nullptr;
+    const size_t bytes = std::max(need, ring_bytes_[r] * 2);
+    HIPCHK(hipHostMalloc(&h_ring_[r], bytes));
+    ring_bytes_[r] = bytes;
+  }
+
+  void rebuild_tables() {
+    // descriptor capacity follows the slot count
+    const int nslots = (int)slot_used_.size();
+    if (nslots > desc_cap_) {
+      HIPCHK(hipStreamSynchronize(stream_));
+      (void)hipFree(d_descs_);
+      desc_cap_ = std::max(nslots, desc_cap_ * 2);
+      HIPCHK(hipMalloc(&d_descs_, sizeof(SolveDesc) * desc_cap_));
+      clear_graphs();
+    }
+    // global tile and body numbering; solves in member order
+    int64_t T = 0;
+    int64_t B = 0;
+    for (Solve *s : members_) {
+      s->desc.tile_base = T;
+      s->desc.body_base = (int32_t)B;
+      T += s->tiles();
+      B += s->nb;
+    }
+    if (B >= ((int64_t)1 << 31)) fail(DILBM_EINVAL, "too many bodies in one pool");
+    HIPCHK(hipEventSynchronize(table_ev_));
+    if (T > tile_cap_) {
+      HIPCHK(hipStreamSynchronize(stream_));
+      (void)hipFree(d_tile_solve_);
+      (void)hipHostFree(h_tile_solve_);
+      tile_cap_ = std::max<int64_t>(T, tile_cap_ * 2);
+      HIPCHK(hipMalloc(&d_tile_solve_, sizeof(int32_t) * tile_cap_));
+      HIPCHK(hipHostMalloc(&h_tile_solve_, sizeof(int32_t) * tile_cap_));
+      clear_graphs();
+    }
+    if (B > body_cap_ || !d_body_solve_) {
+      HIPCHK(hipStreamSynchronize(stream_));
+      (void)hipFree(d_body_solve_);
+      (void)hipHostFree(h_body_solve_);
+      body_cap_ = std::max<int64_t>(std::max<int64_t>(B, 1), body_cap_ * 2);
+      HIPCHK(hipMalloc(&d_body_solve_, sizeof(int32_t) * body_cap_));
+      HIPCHK(hipHostMalloc(&h_body_solve_, sizeof(int32_t) * body_cap_));
+      clear_graphs();
+    }
+    for (Solve *s : members_) {
+      std::fill(h_tile_solve_ + s->desc.tile_base, h_tile_solve_ + s->desc.tile_base + s->tiles(),
+                s->slot);
+      std::fill(h_body_solve_ + s->desc.body_base, h_body_solve_ + s->desc.body_base + s->nb,
+                s->slot);
+    }
+    BatchHeader &hh = *((BatchHeader *)((SolveDesc *)h_one_ + 2) + 1);
+    hh.total_tiles = T;
+    hh.total_bodies = (int32_t)B;
+    hh.nsolves = (int32_t)members_.size();
+    if (T) HIPCHK(hipMemcpyAsync(d_tile_solve_, h_tile_solve_, sizeof(int32_t) * T,
+                                 hipMemcpyHostToDevice, stream_));
+    if (B) HIPCHK(hipMemcpyAsync(d_body_solve_, h_body_solve_, sizeof(int32_t) * B,
+                                 hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipMemcpyAsync(d_hdr_, &hh, sizeof(BatchHeader), hipMemcpyHostToDevice, stream_));
+    HIPCHK(hipEventRecord(table_ev_, stream_));
+    const bool grid_change = collide_grid_for(T) != collide_grid_ || bodies_grid_for(B) != bodies_grid_;
+    total_tiles_ = T;
+    total_bodies_ = (int)B;
+    if (grid_change) {
+      collide_grid_ = collide_grid_for(T);
+      bodies_grid_ = bodies_grid_for(B);
+      clear_graphs();
+    }
+    dirty_ = false;
+  }
+
+  int collide_grid_for(int64_t T) const {
+    // one tile per block, or a persistent grid of a few blocks per CU that sweeps the work
+    int64_t g = T;
+    if (persistent_) g = std::min<int64_t>(T, (int64_t)num_cu_ * 8);
+    g = std::min<int64_t>(g, (int64_t)1 << 30);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    return (int)g;
+  }
+  int bodies_grid_for(int64_t B) const {
+    int64_t g = (B + 3) / 4;  // one wave per body, four waves per block
+    g = std::min<int64_t>(g, (int64_t)num_cu_ * 16);
+    return (int)std::max<int64_t>(1, g);
+  }
+
+  void launch_steps(int K, bool timed) {
+    for (int k = 0; k < K; ++k) {
+      if (timed) {
+        if (timing_used_ == (int)timing_ev_.size()) {
+          hipEvent_t a, b;
+          HIPCHK(hipEventCreate(&a));
+          HIPCHK(hipEventCreate(&b));
+          timing_ev_.push_back({a, b});
+        }
+        HIPCHK(hipEventRecord(timing_ev_[timing_used_].first, stream_));
+      }
+      HIPCHK(launch_collide(shape_, storage_, collide_grid_, stream_, d_descs_, d_tile_solve_,
+                            d_hdr_, k));
+      if (timed) {
+        HIPCHK(hipEventRecord(timing_ev_[timing_used_].second, stream_));
+        ++timing_used_;
+      }
+      if (total_bodies_ > 0)
+        HIPCHK(launch_bodies(false, bodies_grid_, stream_, d_descs_, d_body_solve_, d_hdr_, k));
+    }
+    if (timed && timing_used_ >= 1024) collect_timing();
+  }
+
+  hipGraphExec_t graph_for(int K) {
+    const int key = K * 2 + (total_bodies_ > 0 ? 1 : 0);
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) return it->second;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeRelaxed));
+    try {
+      launch_steps(K, false);
+    } catch (...) {
+      (void)hipStreamEndCapture(stream_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(stream_, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    graphs_[key] = ex;
+    return ex;
+  }
+
+  void clear_graphs() {
+    if (graphs_.empty()) return;
+    (void)hipStreamSynchronize(stream_);
+    for (auto &kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+    graphs_.clear();
+  }
+
+  int device_;
+  hipStream_t stream_ = nullptr;
+  hipStream_t aux_ = nullptr;
+  bool own_stream_ = false;
+  int num_cu_ = 256;
+  int shape_ = 0;
+  int storage_ = 0;
+  int graph_steps_ = 32;
+  bool persistent_ = false;
+  std::vector<Solve *> members_;
+  std::vector<bool> slot_used_;
+  bool dirty_ = true;
+  // device tables
+  SolveDesc *d_descs_ = nullptr;
+  int desc_cap_ = 0;
+  int32_t *d_tile_solve_ = nullptr;
+  int32_t *h_tile_solve_ = nullptr;
+  int64_t tile_cap_ = 0;
+  int32_t *d_body_solve_ = nullptr;
+  int32_t *h_body_solve_ = nullptr;
+  int64_t body_cap_ = 0;
+  BatchHeader *d_hdr_ = nullptr;
+  int32_t *d_err_ = nullptr;
+  int32_t *h_err_ = nullptr;
+  int err_cap_ = 0;
+  int64_t total_tiles_ = 0;
+  int total_bodies_ = 0;
+  int collide_grid_ = 8;
+  int bodies_grid_ = 1;
+  // staging
+  void *h_ring_[kRing] = {};
+  size_t ring_bytes_[kRing] = {};
+  hipEvent_t ring_ev_[kRing] = {};
+  int ring_pos_ = 0;
+  hipEvent_t table_ev_ = nullptr;
+  SolveDesc *d_one_desc_ = nullptr;
+  BatchHeader *d_one_hdr_ = nullptr;
+  int32_t *d_one_bodies_ = nullptr;
+  int one_bodies_cap_ = 0;
+  void *h_one_ = nullptr;
+  hipEvent_t one_ev_[2] = {};
+  // graphs
+  std::map<int, hipGraphExec_t> graphs_;
+  // timing
+  bool timing_ = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_ev_;
+  int timing_used_ = 0;
+  double timed_ms_ = 0.0;
+  int64_t timed_launches_ = 0;
+};
+
+// ---------------------------------------------------------------------------------------
+// solve setup shared by the solver and the pool
+
+void upload_bodies(Solve &s, hipStream_t st, const double *pos, const double *vel,
+                   const double *omega, const double *radius, const double *density,
+                   const uint8_t *fixed) {
+  const int nb = s.nb;
+  const int p = s.parity();
+  // host arrays in the device SoA order
+  std::vector<double> state(5 * (size_t)std::max(nb, 1), 0.0), cst(5 * (size_t)std::max(nb, 1), 0.0);
+  const double nx = s.prm.nx, ny = s.prm.ny;
+  for (int b = 0; b < nb; ++b) {
+    double x = std::fmod(pos[2 * b], nx);
+    if (x < 0) x += nx;
+    if (x >= nx) x -= nx;
+    double y = std::fmod(pos[2 * b + 1], ny);
+    if (y < 0) y += ny;
+    if (y >= ny) y -= ny;
+    state[b] = x;
+    state[nb + b] = y;
+    state[2 * nb + b] = vel ? vel[2 * b] : 0.0;
+    state[3 * nb + b] = vel ? vel[2 * b + 1] : 0.0;
+    state[4 * nb + b] = omega ? omega[b] : 0.0;
+    const double R = radius[b], m = density[b] * M_PI * R * R;
+    cst[b] = R;
+    cst[nb + b] = density[b];
+    cst[2 * nb + b] = m;
+    cst[3 * nb + b] = 0.5 * m * R * R;
+    cst[4 * nb + b] = (fixed && fixed[b]) ? 1.0 : 0.0;
+  }
+  if (nb > 0) {
+    HIPCHK(hipMemcpyAsync(s.desc.bstate[p], state.data(), sizeof(double) * 5 * nb,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync((void *)s.desc.bconst, cst.data(), sizeof(double) * 5 * nb,
+                          hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(launch_fill_f64(s.desc.acc[0], 2 * 3 * (int64_t)(nb + 1), 0.0, st));
+  HIPCHK(hipStreamSynchronize(st));  // the host vectors die here
+}
+
+void init_populations(Solve &s, hipStream_t st) {
+  HIPCHK(launch_zero_bytes(s.pops.ptr, (int64_t)s.pops.bytes, st));
+}
+
+// copy a body-buffer range to the host (synchronous on st)
+void d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void get_particles_of(Solve &s, hipStream_t st, double *pos, double *vel, double *omega) {
+  const int nb = s.nb;
+  if (nb == 0) return;
+  std::vector<double> h(5 * (size_t)nb);
+  d2h(h.data(), s.desc.bstate[s.parity()], sizeof(double) * 5 * nb, st);
+  for (int b = 0; b < nb; ++b) {
+    if (pos) {
+      pos[2 * b] = h[b];
+      pos[2 * b + 1] = h[nb + b];
+    }
+    if (vel) {
+      vel[2 * b] = h[2 * nb + b];
+      vel[2 * b + 1] = h[3 * nb + b];
+    }
+    if (omega) omega[b] = h[4 * nb + b];
+  }
+}
+
+void get_forces_of(Solve &s, hipStream_t st, double *force, double *torque, double *wall) {
+  const int nb = s.nb;
+  std::vector<double> h(3 * (size_t)(nb + 1), 0.0);
+  if (s.forces_valid && s.steps_done > 0)
+    d2h(h.data(), s.desc.acc[(s.steps_done - 1) & 1], sizeof(double) * 3 * (nb + 1), st);
+  for (int b = 0; b < nb; ++b) {
+    if (force) {
+      force[2 * b] = h[3 * b];
+      force[2 * b + 1] = h[3 * b + 1];
+    }
+    if (torque) torque[b] = h[3 * b + 2];
+  }
+  if (wall) {
+    wall[0] = h[3 * nb];
+    wall[1] = h[3 * nb + 1];
+  }
+}
+
+void get_fields_of(Engine &eng, Solve &s, hipStream_t st, double **scratch, uint64_t *scratch_n,
+                   Region rg, double *rho, double *ux, double *uy) {
+  if (rg.w < 1 || rg.h < 1 || rg.x < 0 || rg.y < 0 || rg.x + rg.w > s.prm.nx ||
+      rg.y + rg.h > s.prm.ny)
+    fail(DILBM_EINVAL, "region outside the lattice");
+  const uint64_t n = (uint64_t)rg.w * rg.h;
+  if (*scratch_n < n) {
+    HIPCHK(hipStreamSynchronize(st));
+    (void)hipFree(*scratch);
+    *scratch = nullptr;
+    *scratch_n = 0;
+    HIPCHK(hipMalloc(scratch, sizeof(double) * 3 * n));
+    *scratch_n = n;
+  }
+  SolveDesc *dd = eng.one_desc(s, st, 1);
+  double *b = *scratch;
+  const int64_t ntiles = (int64_t)((rg.x + rg.w - 1) / s.desc.tx - rg.x / s.desc.tx + 1) *
+                         ((rg.y + rg.h - 1) / s.desc.ty - rg.y / s.desc.ty + 1);
+  HIPCHK(launch_fields(s.shape, s.prm.storage, ntiles, st, dd, s.parity(), rg, b, b + n,
+                       b + 2 * n));
+  if (rho) HIPCHK(hipMemcpyAsync(rho, b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (ux) HIPCHK(hipMemcpyAsync(ux, b + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (uy) HIPCHK(hipMemcpyAsync(uy, b + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+}  // namespace dilbm
+
+// =======================================================================================
+// C ABI
+
+using namespace dilbm;
+
+struct dilbm_solver {
+  std::unique_ptr<Engine> eng;
+  Solve s;
+  std::string last_error;
+  double *scratch = nullptr;
+  uint64_t scratch_n = 0;
+};
+
+struct dilbm_pool {
+  std::unique_ptr<Engine> eng;
+  std::unique_ptr<Arena> arena;
+  void *own_arena = nullptr;
+  std::map<int64_t, std::unique_ptr<Solve>> solves;
+  std::vector<std::pair<hipEvent_t, Mem>> deferred;  // memory freed once the event is done
+  int64_t next_ticket = 1;
+  int pending_shape = -1;
+  std::string last_error;
+  double *scratch = nullptr;
+  uint64_t scratch_n = 0;
+};
+
+namespace {
+
+template <class F>
+dilbm_status guard(std::string *err, F &&f) {
+  try {
+    f();
+    return DILBM_OK;
+  } catch (const Fail &e) {
+    if (err) *err = e.msg;
+    g_thread_error = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    if (err) *err = "host allocation failed";
+    g_thread_error = "host allocation failed";
+    return DILBM_ENOMEM;
+  } catch (...) {
+    if (err) *err = "unexpected exception";
+    g_thread_error = "unexpected exception";
+    return DILBM_EDEVICE;
+  }
+}
+
+void check_usable(dilbm_solver *s) {
+  if (s->s.poison != DILBM_OK) fail(DILBM_ESTATE, "handle poisoned: " + s->s.err);
+}
+
+void poll_errors(Engine &eng, Solve &s) {
+  const int32_t e = eng.read_error_of(s, eng.stream());
+  if (e & kErrInternal) {
+    s.poison = DILBM_EDEVICE;
+    s.err = "internal error: a kernel met an out-of-range body index";
+    fail(DILBM_EDEVICE, s.err);
+  }
+  if (e & kErrCapacity) {
+    s.poison = DILBM_ECAPACITY;
+    s.err = "a tile body list overflowed; raise list_capacity";
+    fail(DILBM_ECAPACITY, s.err);
+  }
+  if (e & kErrUnstable) {
+    s.poison = DILBM_EUNSTABLE;
+    s.err = "unstable: rho <= 0, |u| > 0.5 or a non-finite value";
+    fail(DILBM_EUNSTABLE, s.err);
+  }
+}
+
+void process_deferred(dilbm_pool *p) {
+  auto &v = p->deferred;
+  for (size_t i = 0; i < v.size();) {
+    if (hipEventQuery(v[i].first) == hipSuccess) {
+      (void)hipEventDestroy(v[i].first);
+      mem_free(v[i].second);
+      v[i] = v.back();
+      v.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void dilbm_params_init(dilbm_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->abi_version = DILBM_ABI_VERSION;
+  p->tau = 0.8;
+  p->rho0 = 1.0;
+  p->interface_width = 2.0;
+  p->phi_cutoff = 4.0;
+  p->wall_half_thickness = 4.0;
+  p->force_mode = DILBM_FORCE_MOMENTUM_EXCHANGE;
+  p->coll_eps_p = 1.0e4;
+  p->coll_eps_p_overlap = 1.0e4;
+  p->coll_eps_w = 0.5e4;
+  p->coll_eps_w_overlap = 0.5e4;
+  p->coll_xi = 1.0;
+  p->storage = DILBM_STORE_FP32;
+  p->fp16_scale_log2 = 10;
+  p->list_capacity = 0;
+  p->tile = -1;
+  p->device = 0;
+  p->stream = nullptr;
+}
+
+int32_t dilbm_num_tile_shapes(void) { return kNumTileShapes; }
+
+dilbm_status dilbm_tile_shape(int32_t id, int32_t *tx, int32_t *ty) {
+  if (id < 0 || id >= kNumTileShapes) return DILBM_EINVAL;
+  if (tx) *tx = kTileTX[id];
+  if (ty) *ty = kTileTY[id];
+  return DILBM_OK;
+}
+
+dilbm_status dilbm_footprint(const dilbm_params *p, int32_t n_bodies, uint64_t *bytes) {
+  return guard(nullptr, [&] {
+    validate(p);
+    if (n_bodies < 0 || !bytes) fail(DILBM_EINVAL, "bad footprint query");
+    *bytes = pop_bytes(*p) + body_layout(*p, n_bodies).total;
+  });
+}
+
+dilbm_status dilbm_create(const dilbm_params *p, dilbm_solver **out) {
+  if (!out) return DILBM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<dilbm_solver> h(new (std::nothrow) dilbm_solver);
+  if (!h) return DILBM_ENOMEM;
+  dilbm_status st = guard(nullptr, [&] {
+    validate(p);
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (p->device < 0 || p->device >= ndev) fail(DILBM_EINVAL, "no such device");
+    h->eng.reset(new Engine(p->device, p->stream));
+    Solve &s = h->s;
+    s.prm = *p;
+    s.nb = 0;
+    s.shape = p->tile >= 0 ? p->tile : 0;
+    h->eng->set_storage(p->storage);
+    h->eng->set_shape(s.shape);
+    s.L = body_layout(*p, 0);
+    s.pops = mem_alloc(nullptr, pop_bytes(*p));
+    s.body = mem_alloc(nullptr, s.L.total);
+    fill_desc(s);
+    h->eng->add(&s);
+    init_populations(s, h->eng->stream());
+    HIPCHK(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, h->eng->stream()));
+    HIPCHK(hipStreamSynchronize(h->eng->stream()));
+  });
+  if (st != DILBM_OK) {
+    if (h->eng) {
+      mem_free(h->s.pops);
+      mem_free(h->s.body);
+    }
+    return st;
+  }
+  *out = h.release();
+  return DILBM_OK;
+}
+
+dilbm_status dilbm_set_particles(dilbm_solver *h, int32_t n, const double *pos, const double *vel,
+                                 const double *omega, const double *radius, const double *density,
+                                 const uint8_t *fixed) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    check_usable(h);
+    validate_bodies(n, pos, vel, omega, radius, density);
+    HIPCHK(hipSetDevice(h->eng->device()));
+    Solve &s = h->s;
+    hipStream_t st = h->eng->stream();
+    BodyLayout L = body_layout(s.prm, n);
+    HIPCHK(hipStreamSynchronize(st));
+    Mem nm = mem_alloc(nullptr, L.total);  // strong guarantee: allocate before freeing
+    mem_free(s.body);
+    s.body = nm;
+    s.L = L;
+    s.nb = n;
+    const int32_t *err = s.desc.err;
+    fill_desc(s);
+    s.desc.err = const_cast<int32_t *>(err);
+    HIPCHK(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, st));
+    upload_bodies(s, st, pos, vel, omega, radius, density, fixed);
+    h->eng->bin_current(s, st);
+    s.forces_valid = false;
+    h->eng->mark_dirty();
+    HIPCHK(hipStreamSynchronize(st));
+    poll_errors(*h->eng, s);
+  });
+}
+
+dilbm_status dilbm_set_populations(dilbm_solver *h, const double *f_dev) {
+  if (!h || !f_dev) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    check_usable(h);
+    HIPCHK(hipSetDevice(h->eng->device()));
+    Solve &s = h->s;
+    hipStream_t st = h->eng->stream();
+    const int64_t count = (int64_t)kQ * s.prm.nx * s.prm.ny;
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, sizeof(double) * count));
+    hipError_t e = hipMemcpyAsync(tmp, f_dev, sizeof(double) * count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      SolveDesc *dd = h->eng->one_desc(s, st, 0);
+      e = launch_set_pops(s.prm.storage, count, st, dd, s.parity(), tmp);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    HIPCHK(e);
+  });
+}
+
+dilbm_status dilbm_get_populations(dilbm_solver *h, double *f_dev) {
+  if (!h || !f_dev) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    Solve &s = h->s;
+    hipStream_t st = h->eng->stream();
+    const int64_t count = (int64_t)kQ * s.prm.nx * s.prm.ny;
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, sizeof(double) * count));
+    SolveDesc *dd = h->eng->one_desc(s, st, 0);
+    hipError_t e = launch_get_pops(s.prm.storage, count, st, dd, s.parity(), tmp);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(f_dev, tmp, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    HIPCHK(e);
+  });
+}
+
+dilbm_status dilbm_step(dilbm_solver *h, int64_t nsteps) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    check_usable(h);
+    if (nsteps < 0) fail(DILBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return;
+    HIPCHK(hipSetDevice(h->eng->device()));
+    Engine &eng = *h->eng;
+    const int K = eng.graph_steps();
+    int64_t left = nsteps;
+    while (left > 0) {
+      const int k = (int)std::min<int64_t>(left, K);
+      eng.run_chunk(k, k == K);
+      left -= k;
+    }
+    eng.collect_timing();
+    HIPCHK(hipStreamSynchronize(eng.stream()));
+    poll_errors(eng, h->s);
+  });
+}
+
+dilbm_status dilbm_get_fields(dilbm_solver *h, double *rho, double *ux, double *uy) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    get_fields_of(*h->eng, h->s, h->eng->stream(), &h->scratch, &h->scratch_n,
+                  Region{0, 0, h->s.prm.nx, h->s.prm.ny}, rho, ux, uy);
+  });
+}
+
+dilbm_status dilbm_get_fields_region(dilbm_solver *h, int32_t x0, int32_t y0, int32_t w,
+                                     int32_t hgt, double *rho, double *ux, double *uy) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    get_fields_of(*h->eng, h->s, h->eng->stream(), &h->scratch, &h->scratch_n,
+                  Region{x0, y0, w, hgt}, rho, ux, uy);
+  });
+}
+
+dilbm_status dilbm_get_particle_forces(dilbm_solver *h, double *force, double *torque) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    get_forces_of(h->s, h->eng->stream(), force, torque, nullptr);
+  });
+}
+
+dilbm_status dilbm_get_particles(dilbm_solver *h, double *pos, double *vel, double *omega) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    get_particles_of(h->s, h->eng->stream(), pos, vel, omega);
+  });
+}
+
+dilbm_status dilbm_get_wall_force(dilbm_solver *h, double *force) {
+  if (!h || !force) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    HIPCHK(hipSetDevice(h->eng->device()));
+    get_forces_of(h->s, h->eng->stream(), nullptr, nullptr, force);
+  });
+}
+
+dilbm_status dilbm_get_step_count(dilbm_solver *h, int64_t *steps) {
+  if (!h || !steps) return DILBM_EINVAL;
+  *steps = h->s.steps_done;
+  return DILBM_OK;
+}
+
+dilbm_status dilbm_get_body_count(dilbm_solver *h, int32_t *n) {
+  if (!h || !n) return DILBM_EINVAL;
+  *n = h->s.nb;
+  return DILBM_OK;
+}
+
+dilbm_status dilbm_set_kernel_timing(dilbm_solver *h, int32_t enable) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] { h->eng->set_timing(enable != 0); });
+}
+
+dilbm_status dilbm_get_kernel_timing(dilbm_solver *h, double *collide_ms, int64_t *launches) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    h->eng->collect_timing();
+    if (collide_ms) *collide_ms = h->eng->timed_ms();
+    if (launches) *launches = h->eng->timed_launches();
+  });
+}
+
+void dilbm_destroy(dilbm_solver *h) {
+  if (!h) return;
+  try {
+    if (h->eng) {
+      (void)hipSetDevice(h->eng->device());
+      (void)hipStreamSynchronize(h->eng->stream());
+      h->eng->remove(&h->s);
+    }
+    mem_free(h->s.pops);
+    mem_free(h->s.body);
+    (void)hipFree(h->scratch);
+    h->eng.reset();
+  } catch (...) {
+  }
+  delete h;
+}
+
+const char *dilbm_last_error(const dilbm_solver *h) {
+  if (!h) return g_thread_error.c_str();
+  return h->last_error.c_str();
+}
+
+// ---- pool ---------------------------------------------------------------------------
+
+dilbm_status dilbm_pool_create(int32_t device, void *stream, void *arena, uint64_t arena_bytes,
+                               dilbm_pool **out) {
+  if (!out) return DILBM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<dilbm_pool> p(new (std::nothrow) dilbm_pool);
+  if (!p) return DILBM_ENOMEM;
+  dilbm_status st = guard(nullptr, [&] {
+    if (arena_bytes < (1u << 20)) fail(DILBM_EINVAL, "arena_bytes must be at least 1 MiB");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(DILBM_EINVAL, "no such device");
+    p->eng.reset(new Engine(device, stream));
+    p->eng->set_persistent(true);
+    char *base = (char *)arena;
+    if (!base) {
+      HIPCHK(hipMalloc(&p->own_arena, arena_bytes));
+      base = (char *)p->own_arena;
+    }
+    p->arena.reset(new Arena(base, arena_bytes));
+  });
+  if (st != DILBM_OK) {
+    if (p->own_arena) (void)hipFree(p->own_arena);
+    return st;
+  }
+  *out = p.release();
+  return DILBM_OK;
+}
+
+dilbm_status dilbm_pool_submit(dilbm_pool *pool, const dilbm_params *prm, int32_t n,
+                               const double *pos, const double *vel, const double *omega,
+                               const double *radius, const double *density,
+                               const uint8_t *fixed, int64_t nsteps, int64_t *ticket) {
+  if (!pool || !ticket) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    validate(prm);
+    validate_bodies(n, pos, vel, omega, radius, density);
+    if (nsteps < 0) fail(DILBM_EINVAL, "nsteps must be >= 0");
+    Engine &eng = *pool->eng;
+    HIPCHK(hipSetDevice(eng.device()));
+    if (!eng.members().empty() && prm->storage != eng.storage())
+      fail(DILBM_EINVAL, "all members of a pool share one storage type");
+    process_deferred(pool);
+    const BodyLayout L = body_layout(*prm, n);
+    const uint64_t need = pop_bytes(*prm) + L.total;
+    if (need > pool->arena->size()) fail(DILBM_ENOMEM, "solve larger than the whole arena");
+    std::unique_ptr<Solve> s(new Solve);
+    s->prm = *prm;
+    s->nb = n;
+    s->L = L;
+    s->shape = eng.shape();
+    if (pool->solves.empty() && eng.members().empty()) {
+      eng.set_storage(prm->storage);
+      if (pool->pending_shape >= 0) eng.set_shape(pool->pending_shape);
+      s->shape = eng.shape();
+    }
+    s->pops = mem_alloc(pool->arena.get(), pop_bytes(*prm));
+    try {
+      s->body = mem_alloc(pool->arena.get(), L.total);
+    } catch (...) {
+      mem_free(s->pops);
+      throw;
+    }
+    s->target = nsteps;
+    fill_desc(*s);
+    hipStream_t st = eng.stream();
+    eng.add(s.get());
+    try {
+      init_populations(*s, st);
+      HIPCHK(launch_zero_bytes(s->body.ptr, (int64_t)s->body.bytes, st));
+      upload_bodies(*s, st, pos, vel, omega, radius, density, fixed);
+      eng.bin_current(*s, st);
+      HIPCHK(hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(s->done_ev, st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      eng.remove(s.get());
+      mem_free(s->pops);
+      mem_free(s->body);
+      if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+      throw;
+    }
+    s->ticket = pool->next_ticket++;
+    *ticket = s->ticket;
+    if (nsteps == 0) {
+      s->finished = true;
+      eng.leave(s.get());
+    }
+    pool->solves[s->ticket] = std::move(s);
+  });
+}
+
+dilbm_status dilbm_pool_run(dilbm_pool *pool, int32_t steps) {
+  if (!pool || steps < 0) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Engine &eng = *pool->eng;
+    HIPCHK(hipSetDevice(eng.device()));
+    process_deferred(pool);
+    int left = steps;
+    const int K = eng.graph_steps();
+    while (left > 0 && !eng.members().empty()) {
+      const int k = std::min(left, K);
+      eng.run_chunk(k, k == K);
+      left -= k;
+      // members whose last step is enqueued leave the member set; their completion is
+      // marked by an event after this chunk
+      std::vector<Solve *> done;
+      for (Solve *s : eng.members())
+        if (s->remaining() <= 0) done.push_back(s);
+      for (Solve *s : done) {
+        HIPCHK(hipEventRecord(s->done_ev, eng.stream()));
+        s->finished = true;
+        eng.leave(s);
+      }
+    }
+  });
+}
+
+dilbm_status dilbm_pool_sync(dilbm_pool *pool) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    HIPCHK(hipSetDevice(pool->eng->device()));
+    HIPCHK(hipStreamSynchronize(pool->eng->stream()));
+    process_deferred(pool);
+  });
+}
+
+static Solve *find_ticket(dilbm_pool *pool, int64_t t) {
+  auto it = pool->solves.find(t);
+  if (it == pool->solves.end()) fail(DILBM_EINVAL, "unknown ticket");
+  return it->second.get();
+}
+
+dilbm_status dilbm_pool_query(dilbm_pool *pool, int64_t ticket, int64_t *steps_enqueued,
+                              int32_t *done) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Solve *s = find_ticket(pool, ticket);
+    if (steps_enqueued) *steps_enqueued = s->steps_done;
+    if (done) *done = (s->finished && hipEventQuery(s->done_ev) == hipSuccess) ? 1 : 0;
+  });
+}
+
+// wait (on the auxiliary stream) for the ticket's enqueued work, then check its flags
+static void ready_for_results(dilbm_pool *pool, Solve *s) {
+  Engine &eng = *pool->eng;
+  HIPCHK(hipSetDevice(eng.device()));
+  HIPCHK(hipEventSynchronize(s->done_ev));
+  if (s->poison == DILBM_OK) {
+    const int32_t e = eng.read_error_of(*s, eng.aux());
+    if (e & kErrInternal) {
+      s->poison = DILBM_EDEVICE;
+      s->err = "internal error: a kernel met an out-of-range body index";
+    } else if (e & kErrCapacity) {
+      s->poison = DILBM_ECAPACITY;
+      s->err = "a tile body list overflowed";
+    } else if (e & kErrUnstable) {
+      s->poison = DILBM_EUNSTABLE;
+      s->err = "unstable";
+    }
+  }
+}
+
+dilbm_status dilbm_pool_get_fields(dilbm_pool *pool, int64_t ticket, double *rho, double *ux,
+                                   double *uy) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Solve *s = find_ticket(pool, ticket);
+    if (!s->finished) fail(DILBM_ESTATE, "ticket still running; results need all its steps");
+    ready_for_results(pool, s);
+    get_fields_of(*pool->eng, *s, pool->eng->aux(), &pool->scratch, &pool->scratch_n,
+                  Region{0, 0, s->prm.nx, s->prm.ny}, rho, ux, uy);
+    if (s->poison != DILBM_OK) fail(s->poison, s->err);
+  });
+}
+
+dilbm_status dilbm_pool_get_particles(dilbm_pool *pool, int64_t ticket, double *pos, double *vel,
+                                      double *omega) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Solve *s = find_ticket(pool, ticket);
+    if (!s->finished) fail(DILBM_ESTATE, "ticket still running; results need all its steps");
+    ready_for_results(pool, s);
+    get_particles_of(*s, pool->eng->aux(), pos, vel, omega);
+    if (s->poison != DILBM_OK) fail(s->poison, s->err);
+  });
+}
+
+dilbm_status dilbm_pool_get_particle_forces(dilbm_pool *pool, int64_t ticket, double *force,
+                                            double *torque) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Solve *s = find_ticket(pool, ticket);
+    if (!s->finished) fail(DILBM_ESTATE, "ticket still running; results need all its steps");
+    ready_for_results(pool, s);
+    get_forces_of(*s, pool->eng->aux(), force, torque, nullptr);
+    if (s->poison != DILBM_OK) fail(s->poison, s->err);
+  });
+}
+
+dilbm_status dilbm_pool_release(dilbm_pool *pool, int64_t ticket) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Engine &eng = *pool->eng;
+    HIPCHK(hipSetDevice(eng.device()));
+    auto it = pool->solves.find(ticket);
+    if (it == pool->solves.end()) fail(DILBM_EINVAL, "unknown ticket");
+    Solve *s = it->second.get();
+    eng.remove(s);
+    // the memory goes back once everything enqueued so far (which may still touch it)
+    // has completed
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, eng.stream()));
+    hipEvent_t ev2;
+    HIPCHK(hipEventCreateWithFlags(&ev2, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev2, eng.stream()));
+    pool->deferred.push_back({ev, s->pops});
+    pool->deferred.push_back({ev2, s->body});
+    s->pops = Mem{};
+    s->body = Mem{};
+    if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+    pool->solves.erase(it);
+    process_deferred(pool);
+  });
+}
+
+dilbm_status dilbm_pool_set_launch(dilbm_pool *pool, int32_t graph_steps, int32_t tile) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    if (graph_steps < 1 || graph_steps > 256) fail(DILBM_EINVAL, "graph_steps in [1, 256]");
+    if (tile < -1 || tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
+    HIPCHK(hipSetDevice(pool->eng->device()));
+    pool->eng->set_graph_steps(graph_steps);
+    if (tile >= 0) {
+      pool->pending_shape = tile;
+      pool->eng->set_shape(tile);
+    }
+  });
+}
+
+dilbm_status dilbm_pool_autotune(dilbm_pool *pool, int32_t steps_per_trial,
+                                 int32_t *best_graph_steps, int32_t *best_tile) {
+  if (!pool || steps_per_trial < 1) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    Engine &eng = *pool->eng;
+    HIPCHK(hipSetDevice(eng.device()));
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    const int ks[] = {8, 32, 128};
+    double best = 1e300;
+    int bk = eng.graph_steps(), bt = eng.shape();
+    for (int tile = 0; tile < kNumTileShapes; ++tile) {
+      for (int K : ks) {
+        if (eng.members().empty()) break;
+        eng.set_shape(tile);
+        eng.set_graph_steps(K);
+        eng.run_chunk(K, true);  // warm: captures the graph
+        // node updates the timed steps will do; a trial with none left cannot be judged
+        double nodes = 0;
+        for (Solve *s : eng.members())
+          nodes += (double)s->prm.nx * s->prm.ny *
+                   (double)std::min<int64_t>(steps_per_trial, s->remaining());
+        if (nodes == 0) continue;
+        HIPCHK(hipEventRecord(a, eng.stream()));
+        int left = steps_per_trial;
+        while (left > 0 && !eng.members().empty()) {
+          const int k = std::min(left, K);
+          eng.run_chunk(k, k == K);
+          left -= k;
+        }
+        HIPCHK(hipEventRecord(b, eng.stream()));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        const double per = ms / nodes;
+        if (per < best) {
+          best = per;
+          bk = K;
+          bt = tile;
+        }
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    eng.set_shape(bt);
+    eng.set_graph_steps(bk);
+    pool->pending_shape = bt;
+    // members that ran out of steps during the trials leave the member set
+    std::vector<Solve *> done;
+    for (Solve *s : eng.members())
+      if (s->remaining() <= 0) done.push_back(s);
+    for (Solve *s : done) {
+      HIPCHK(hipEventRecord(s->done_ev, eng.stream()));
+      s->finished = true;
+      eng.leave(s);
+    }
+    if (best_graph_steps) *best_graph_steps = bk;
+    if (best_tile) *best_tile = bt;
+  });
+}
+
+dilbm_status dilbm_pool_stats(dilbm_pool *pool, uint64_t *free_bytes, int32_t *members) {
+  if (!pool) return DILBM_EINVAL;
+  return guard(&pool->last_error, [&] {
+    process_deferred(pool);
+    if (free_bytes) *free_bytes = pool->arena->free_bytes();
+    if (members) *members = (int32_t)pool->eng->members().size();
+  });
+}
+
+const char *dilbm_pool_last_error(const dilbm_pool *pool) {
+  if (!pool) return g_thread_error.c_str();
+  return pool->last_error.c_str();
+}
+
+void dilbm_pool_destroy(dilbm_pool *pool) {
+  if (!pool) return;
+  try {
+    if (pool->eng) {
+      (void)hipSetDevice(pool->eng->device());
+      (void)hipStreamSynchronize(pool->eng->stream());
+      (void)hipStreamSynchronize(pool->eng->aux());
+      for (auto &kv : pool->solves) {
+        pool->eng->remove(kv.second.get());
+        mem_free(kv.second->pops);
+        mem_free(kv.second->body);
+        if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
+      }
+      pool->solves.clear();
+      for (auto &d : pool->deferred) {
+        (void)hipEventSynchronize(d.first);
+        (void)hipEventDestroy(d.first);
+        mem_free(d.second);
+      }
+      pool->deferred.clear();
+      (void)hipFree(pool->scratch);
+      pool->eng.reset();
+    }
+    pool->arena.reset();
+    if (pool->own_arena) (void)hipFree(pool->own_arena);
+  } catch (...) {
+  }
+  delete pool;
+}
+
+}  // extern "C"

@@ -1,0 +1,26 @@
+// kernels.h -- launch wrappers of the gfx950 kernels (internal to libdilbm).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dilbm_internal.h"
+
+namespace dilbm {
+
+hipError_t launch_collide(int shape, int storage, int grid, hipStream_t stream,
+                          const SolveDesc *descs, const int32_t *tile_solve,
+                          const BatchHeader *hdr, int k);
+hipError_t launch_fields(int shape, int storage, int64_t ntiles, hipStream_t stream,
+                         const SolveDesc *desc, int p, Region region, double *rho, double *ux,
+                         double *uy);
+hipError_t launch_bodies(bool bin_only, int grid, hipStream_t stream, const SolveDesc *descs,
+                         const int32_t *body_solve, const BatchHeader *hdr, int k);
+hipError_t launch_set_pops(int storage, int64_t count, hipStream_t stream, const SolveDesc *desc,
+                           int p, const double *fin);
+hipError_t launch_get_pops(int storage, int64_t count, hipStream_t stream, const SolveDesc *desc,
+                           int p, double *fout);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t stream);
+hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t stream);
+
+}  // namespace dilbm

@@ -1,0 +1,750 @@
+// kernels.hip -- gfx950 kernels of the DI-LBM time step.
+//
+// k_collide   one fused pass over every node of every member solve: pull the 9 shifted
+//             populations (streaming, Eq. (13) left-hand side), take the moments
+//             (Eqs. (5), (16)), rebuild the diffuse solid field of the bodies listed for
+//             the node's tile (Eq. (14)), correct the velocity (Eq. (17)), collide with the
+//             Eq. (15) force term (Eq. (13)) and write the 9 populations back at the node.
+//             Per body, the force and torque contributions of the tile's nodes are summed
+//             in FP64 across the wave and the block, then added with one FP64 atomic per
+//             component (Eqs. (18)-(19)).
+// k_bodies    one wave per body, FP64: repulsion (Eqs. (28)-(29)), Newton-Euler update
+//             (Eqs. (22)-(24)) and binning of the moved body into the tile lists of the
+//             next step.
+// k_fields    rho and corrected u of the current state (no collision).
+//
+// The stencil is bandwidth bound (about 3 FLOP per byte of population traffic), so the
+// kernel is built for HBM streaming: structure-of-arrays planes, one node per lane, 64
+// consecutive nodes of a row per wave, and the work split so each XCD sweeps a
+// contiguous band of tiles (neighbouring tiles share L2 lines at their edges).
+#include <hip/hip_runtime.h>
+
+#include "dilbm_internal.h"
+#include "kernels.h"
+
+namespace dilbm {
+
+namespace {
+
+// D2Q9 velocities of Eq. (3).  The populations are kept as g_i = 36 (f_i - w_i rho0), so
+// the weights of Eq. (4) enter as the exact integers K_i = 36 w_i = 16, 4, 1: with 1/9 and
+// 1/36 rounded to FP32 the equilibrium's first moment would be rho u (1 + 7.5e-9), a
+// momentum source of that relative size in every collision that compounds over
+// thousands of steps.  Every constant on the mass and momentum path is exact in binary;
+// what remains is unbiased round-to-nearest.
+constexpr int CX[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr float KQ[kQ] = {16.0f, 4.0f, 4.0f, 4.0f, 4.0f, 1.0f, 1.0f, 1.0f, 1.0f};
+
+struct StoreF32 {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T *p, int64_t i, float) { return p[i]; }
+  static __device__ __forceinline__ void st(T *p, int64_t i, float v, float) { p[i] = v; }
+};
+
+struct StoreF16 {
+  using T = _Float16;
+  static __device__ __forceinline__ float ld(const T *p, int64_t i, float inv) {
+    return (float)p[i] * inv;
+  }
+  static __device__ __forceinline__ void st(T *p, int64_t i, float v, float scale) {
+    p[i] = (_Float16)(v * scale);  // round to nearest even
+  }
+};
+
+struct BodyLds {
+  double x, y;
+  float u, v, w, r;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// (1 + tanh(2 l / eps)) / 2 written as the logistic 1 / (1 + e^(-4 l / eps)); phi_k holds
+// 4 / eps * log2(e) so one hardware exp2 and one reciprocal do it.
+__device__ __forceinline__ float phi_of(float l, float phi_k) {
+  return __builtin_amdgcn_rcpf(1.0f + exp2f(-l * phi_k));
+}
+
+__device__ __forceinline__ double min_image(double d, double n) {
+  if (d >= 0.5 * n) return d - n;
+  if (d < -0.5 * n) return d + n;
+  return d;
+}
+
+// Tile range along one axis: the tiles holding nodes k with |k + 0.5 - X| <= H (wrapped
+// onto [0, n)); up to two disjoint ranges [a0, a1] and [b0, b1].
+struct AxisTiles {
+  int a0, a1, b0, b1;
+};
+
+__device__ __forceinline__ AxisTiles axis_tiles(double X, double H, int n, int t, int ntiles) {
+  const double lo = ceil(X - H - 0.5);
+  const double hi = floor(X + H - 0.5);
+  if (hi - lo + 1.0 >= (double)n) return {0, ntiles - 1, 0, -1};
+  int lw = (int)(lo - (double)n * floor(lo / (double)n));
+  int hw = (int)(hi - (double)n * floor(hi / (double)n));
+  if (lw >= n) lw -= n;
+  if (hw >= n) hw -= n;
+  if (lw <= hw) return {lw / t, hw / t, 0, -1};
+  const int a0 = lw / t, b1 = hw / t;
+  if (b1 >= a0) return {0, ntiles - 1, 0, -1};
+  return {a0, ntiles - 1, 0, b1};
+}
+
+// XCD-contiguous split of [0, T): workgroup b runs on XCD b % 8; the blocks of one XCD
+// sweep one contiguous eighth of the tiles.
+struct WorkSplit {
+  int64_t begin, end;
+  int64_t stride;
+};
+
+__device__ __forceinline__ WorkSplit xcd_split(int64_t T) {
+  const int G = gridDim.x;  // a multiple of 8
+  const int xcd = blockIdx.x & 7;
+  const int64_t q = T >> 3, r = T & 7;
+  WorkSplit w;
+  w.begin = xcd * q + (xcd < r ? xcd : r) + (blockIdx.x >> 3);
+  w.end = xcd * q + (xcd < r ? xcd : r) + q + (xcd < r ? 1 : 0);
+  w.stride = G >> 3;
+  return w;
+}
+
+enum TileMode { kModeStep = 0, kModeFields = 1 };
+
+// Copy one listed body into LDS.  An index outside [0, nb) (never written by the binning)
+// is flagged and staged as a body with no support, so it touches no memory and no node.
+__device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs, int nbs, int b,
+                                           BodyLds *sb, int32_t *sidx) {
+  if (b < 0 || b >= nbs) {
+    atomicOr(d.err, (int32_t)kErrInternal);
+    *sidx = 0;
+    sb->x = 0.0;
+    sb->y = 0.0;
+    sb->u = sb->v = sb->w = 0.f;
+    sb->r = -INFINITY;
+    return;
+  }
+  *sidx = b;
+  sb->x = bs[b];
+  sb->y = bs[nbs + b];
+  sb->u = (float)bs[2 * nbs + b];
+  sb->v = (float)bs[3 * nbs + b];
+  sb->w = (float)bs[4 * nbs + b];
+  sb->r = (float)d.bconst[b];
+}
+
+// One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
+template <class ST, int TX, int TY, int MODE>
+__device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
+                                             BodyLds *sb, int32_t *sidx,
+                                             double (*red)[kBlockThreads / 64][3],
+                                             double *__restrict__ out_rho,
+                                             double *__restrict__ out_ux,
+                                             double *__restrict__ out_uy,
+                                             const Region region) {
+  constexpr int NW = kBlockThreads / 64;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int nx = d.nx, ny = d.ny;
+  const int tyi = lt / d.tiles_x;
+  const int txi = lt - tyi * d.tiles_x;
+  const int x0 = txi * TX, y0 = tyi * TY;
+  const int x = x0 + (tid % TX);
+  const int y = y0 + (tid / TX);
+  const bool valid = (x < nx) && (y < ny);
+  const int xc = valid ? x : x0;  // clamped coordinates keep loads in bounds
+  const int yc = valid ? y : y0;
+
+  // an overflowed list (count > capacity) is flagged by the binning; read only what fits
+  const int nb = min(__builtin_amdgcn_readfirstlane(d.tile_count[p][lt]), d.list_cap);
+  if (MODE == kModeStep) {
+    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
+    if (lt == 0) {
+      double *a = d.acc[p ^ 1];
+      for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+    }
+  }
+
+  // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) --------------------------------
+  const typename ST::T *__restrict__ src = (const typename ST::T *)d.pop[p];
+  const int64_t plane = (int64_t)nx * ny;
+  const int xm = (xc == 0) ? nx - 1 : xc - 1;
+  const int xp = (xc + 1 == nx) ? 0 : xc + 1;
+  const int ym = (yc == 0) ? ny - 1 : yc - 1;
+  const int yp = (yc + 1 == ny) ? 0 : yc + 1;
+  const int64_t r0 = (int64_t)yc * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+  const float inv = d.store_inv;
+  float f[kQ];
+  f[0] = ST::ld(src, 0 * plane + r0 + xc, inv);
+  f[1] = ST::ld(src, 1 * plane + r0 + xm, inv);
+  f[2] = ST::ld(src, 2 * plane + rm + xc, inv);
+  f[3] = ST::ld(src, 3 * plane + r0 + xp, inv);
+  f[4] = ST::ld(src, 4 * plane + rp + xc, inv);
+  f[5] = ST::ld(src, 5 * plane + rm + xm, inv);
+  f[6] = ST::ld(src, 6 * plane + rm + xp, inv);
+  f[7] = ST::ld(src, 7 * plane + rp + xp, inv);
+  f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
+
+  // ---- moments, Eqs. (5) and (16); u* carries half the fluid body force ----------------
+  // (in g units: D = 36 delta rho, J = 36 j, R = 36 rho)
+  const float D = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const float Jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const float Jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const float R = d.rho36 + D;
+  const float rho = R / 36.0f;   // correctly rounded: no constant bias
+  const float drho = D / 36.0f;
+  const float Rinv = 1.0f / R;
+  const float usx = (Jx + 18.0f * d.Gx) * Rinv;  // u* = (j + G/2) / rho
+  const float usy = (Jy + 18.0f * d.Gy) * Rinv;
+
+  // ---- diffuse solid field, Eq. (14), and its sums over the covering bodies ------------
+  float Phi = 0.f, Ax = 0.f, Ay = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+  const float lcut = d.lcut;
+  const float phik = d.phi_k;
+  const float h = d.wall_h;
+  const float cut = -lcut;
+  // walls: static slabs across the seams; does this tile reach into one's support?
+  const bool wy = (d.wall_mask & 1u) &&
+                  ((float)y0 + 0.5f <= h + cut ||
+                   (float)ny - ((float)min(y0 + TY, ny) - 0.5f) <= h + cut);
+  const bool wx = (d.wall_mask & 2u) &&
+                  ((float)x0 + 0.5f <= h + cut ||
+                   (float)nx - ((float)min(x0 + TX, nx) - 0.5f) <= h + cut);
+  const bool any_solid = (nb > 0) || wy || wx;
+  float lwy = -1e30f, lwx = -1e30f;
+  if (wy) {
+    float dy = (float)yc + 0.5f;
+    if (dy >= 0.5f * (float)ny) dy -= (float)ny;
+    lwy = h - fabsf(dy);
+  }
+  if (wx) {
+    float dx = (float)xc + 0.5f;
+    if (dx >= 0.5f * (float)nx) dx -= (float)nx;
+    lwx = h - fabsf(dx);
+  }
+
+  if (any_solid) {
+    const int nsolid = nb + (wy ? 1 : 0) + (wx ? 1 : 0);
+    const int32_t *list = d.tile_list[p] + (int64_t)lt * d.list_cap;
+    const double *bs = d.bstate[p];
+    const int nbs = d.nbodies;
+    const double xnode = (double)xc + 0.5, ynode = (double)yc + 0.5;
+    const double dnx = (double)nx, dny = (double)ny;
+    float scale = 1.0f;
+
+    // pass 1 (only where several supports meet): S = sum phi_b, w_b = phi_b min(1, 1/S)
+    if (nsolid > 1) {
+      float S = 0.f;
+      if (wy && lwy >= lcut) S += phi_of(lwy, phik);
+      if (wx && lwx >= lcut) S += phi_of(lwx, phik);
+      for (int c0 = 0; c0 < nb; c0 += kBodyChunk) {
+        const int cn = min(kBodyChunk, nb - c0);
+        __syncthreads();
+        if (tid < cn) stage_body(d, bs, nbs, list[c0 + tid], sb + tid, sidx + tid);
+        __syncthreads();
+        for (int j = 0; j < cn; ++j) {
+          const float rx = (float)min_image(xnode - sb[j].x, dnx);
+          const float ry = (float)min_image(ynode - sb[j].y, dny);
+          const float l = sb[j].r - sqrtf(rx * rx + ry * ry);
+          if (l >= lcut) S += phi_of(l, phik);
+        }
+      }
+      scale = S > 1.0f ? 1.0f / S : 1.0f;
+    }
+
+    // pass 2: weights, sums for Eqs. (15) and (17), and per-body force/torque
+    const float kap = d.kappa;
+    for (int c0 = 0; c0 < nb; c0 += kBodyChunk) {
+      const int cn = min(kBodyChunk, nb - c0);
+      if (nsolid <= 1 || nb > kBodyChunk) {  // staged already when one chunk was used above
+        __syncthreads();
+        if (tid < cn) stage_body(d, bs, nbs, list[c0 + tid], sb + tid, sidx + tid);
+        __syncthreads();
+      }
+      for (int j = 0; j < cn; ++j) {
+        const float rx = (float)min_image(xnode - sb[j].x, dnx);
+        const float ry = (float)min_image(ynode - sb[j].y, dny);
+        const float l = sb[j].r - sqrtf(rx * rx + ry * ry);
+        float fx = 0.f, fy = 0.f, tq = 0.f;
+        if (valid && l >= lcut) {
+          const float w = scale * phi_of(l, phik);
+          // rigid-body solid velocity U + omega x r
+          const float ux_s = sb[j].u - sb[j].w * ry;
+          const float uy_s = sb[j].v + sb[j].w * rx;
+          Phi += w;
+          Ax += w * ux_s;
+          Ay += w * uy_s;
+          Mxx += w * ux_s * ux_s;
+          Mxy += w * ux_s * uy_s;
+          Myy += w * uy_s * uy_s;
+          // force on the body: -w rho (u_s - u*) (times the Eq. (18) scale)
+          fx = -kap * w * rho * (ux_s - usx);
+          fy = -kap * w * rho * (uy_s - usy);
+          tq = rx * fy - ry * fx;
+        }
+        if (MODE == kModeStep) {
+          const bool any = __ballot(fx != 0.f || fy != 0.f) != 0;
+          double sx = 0.0, sy = 0.0, st = 0.0;
+          if (any) {
+            sx = wave_sum((double)fx);
+            sy = wave_sum((double)fy);
+            st = wave_sum((double)tq);
+          }
+          if (lane == 0) {
+            red[j][wave][0] = sx;
+            red[j][wave][1] = sy;
+            red[j][wave][2] = st;
+          }
+        }
+      }
+      if (MODE == kModeStep) {
+        __syncthreads();
+        double *acc = d.acc[p];
+        for (int e = tid; e < 3 * cn; e += kBlockThreads) {
+          const int j = e / 3, c = e - 3 * j;
+          double v = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) v += red[j][w][c];
+          if (v != 0.0) unsafeAtomicAdd(&acc[3 * sidx[j] + c], v);
+        }
+      }
+    }
+
+    // wall slabs: solid velocity 0; their force goes to the last accumulator slot
+    if (wy || wx) {
+      float fx = 0.f, fy = 0.f;
+      if (valid && wy && lwy >= lcut) {
+        const float w = scale * phi_of(lwy, phik);
+        Phi += w;
+        fx += kap * w * rho * usx;
+        fy += kap * w * rho * usy;
+      }
+      if (valid && wx && lwx >= lcut) {
+        const float w = scale * phi_of(lwx, phik);
+        Phi += w;
+        fx += kap * w * rho * usx;
+        fy += kap * w * rho * usy;
+      }
+      if (MODE == kModeStep) {
+        const bool any = __ballot(fx != 0.f || fy != 0.f) != 0;
+        double sx = 0.0, sy = 0.0;
+        if (any) {
+          sx = wave_sum((double)fx);
+          sy = wave_sum((double)fy);
+        }
+        __syncthreads();
+        if (lane == 0) {
+          red[0][wave][0] = sx;
+          red[0][wave][1] = sy;
+        }
+        __syncthreads();
+        if (tid < 2) {
+          double v = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) v += red[0][w][tid];
+          if (v != 0.0) unsafeAtomicAdd(&d.acc[p][3 * nbs + tid], v);
+        }
+      }
+    }
+  }
+
+  // ---- corrected velocity, Eq. (17): u = u* + (sum_b w_b u_s,b - Phi u*) / 2 ----------
+  const float ux = usx + 0.5f * (Ax - Phi * usx);
+  const float uy = usy + 0.5f * (Ay - Phi * usy);
+
+  if (MODE == kModeFields) {
+    // out_* cover the region [rx0, rx0 + rw) x [ry0, ry0 + rh), row stride rw
+    const int ox = x - region.x, oy = y - region.y;
+    if (valid && ox >= 0 && ox < region.w && oy >= 0 && oy < region.h) {
+      const int64_t o = (int64_t)oy * region.w + ox;
+      out_rho[o] = (double)rho;
+      out_ux[o] = (double)ux;
+      out_uy[o] = (double)uy;
+    }
+    return;
+  }
+
+  const float usq = ux * ux + uy * uy;
+  if (__ballot(valid && !(rho > 0.0f && usq <= 0.25f)) != 0 && lane == 0)
+    atomicOr(d.err, (int32_t)kErrUnstable);
+
+  // ---- collision, Eq. (13), in g units ----------------------------------------------
+  // 36 x (phi F_i summed over bodies, Eq. (15)) = khalf K_i [3 c.P + 4.5 c.Q.c - 1.5 tr Q]
+  // with P = rho (A - Phi u*), Q = rho (M - Phi u* u*); Guo forcing adds
+  // khalf K_i [3 (c - u).G + 9 (c.u)(c.G)]; the equilibrium is K_i [drho + rho P_i(u)].
+  const float Px = rho * (Ax - Phi * usx);
+  const float Py = rho * (Ay - Phi * usy);
+  const float Qxx = rho * (Mxx - Phi * usx * usx);
+  const float Qxy = rho * (Mxy - Phi * usx * usy);
+  const float Qyy = rho * (Myy - Phi * usy * usy);
+  const float trQ = Qxx + Qyy;
+  const float uG = ux * d.Gx + uy * d.Gy;
+  const float om = d.omega;
+  const float kh = d.khalf;
+  typename ST::T *__restrict__ dst = (typename ST::T *)d.pop[p ^ 1];
+  const float sc = d.store_scale;
+  const int64_t o = r0 + xc;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float cx = (float)CX[i], cy = (float)CY[i];
+    const float cu = cx * ux + cy * uy;
+    const float feq = KQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+    const float cG = cx * d.Gx + cy * d.Gy;
+    float src_i = 3.0f * (cG - uG) + 9.0f * cu * cG;
+    if (any_solid)
+      src_i += 3.0f * (cx * Px + cy * Py) +
+               4.5f * (cx * cx * Qxx + 2.0f * cx * cy * Qxy + cy * cy * Qyy) - 1.5f * trQ;
+    const float out = f[i] + om * (feq - f[i]) + kh * KQ[i] * src_i;
+    if (valid) ST::st(dst, i * plane + o, out, sc);
+  }
+}
+
+template <class ST, int TX, int TY>
+__global__ __launch_bounds__(kBlockThreads) void k_collide(const SolveDesc *__restrict__ descs,
+                                                           const int32_t *__restrict__ tile_solve,
+                                                           const BatchHeader *__restrict__ hdr,
+                                                           int k) {
+  __shared__ BodyLds sb[kBodyChunk];
+  __shared__ int32_t sidx[kBodyChunk];
+  __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
+  const WorkSplit ws = xcd_split(hdr->total_tiles);
+  for (int64_t t = ws.begin; t < ws.end; t += ws.stride) {
+    const int s = __builtin_amdgcn_readfirstlane(tile_solve[t]);
+    const SolveDesc &d = descs[s];
+    if (k >= d.active_steps) continue;
+    const int p = (d.parity0 + k) & 1;
+    const int lt = (int)(t - d.tile_base);
+    process_tile<ST, TX, TY, kModeStep>(d, lt, p, sb, sidx, red, nullptr, nullptr, nullptr,
+                                        Region{0, 0, 0, 0});
+    __syncthreads();  // LDS reuse by the next tile
+  }
+}
+
+template <class ST, int TX, int TY>
+__global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__restrict__ desc,
+                                                          int p, Region region,
+                                                          double *__restrict__ rho,
+                                                          double *__restrict__ ux,
+                                                          double *__restrict__ uy) {
+  __shared__ BodyLds sb[kBodyChunk];
+  __shared__ int32_t sidx[kBodyChunk];
+  __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
+  const SolveDesc &d = *desc;
+  // tiles that intersect the region
+  const int tx0 = region.x / TX, tx1 = (region.x + region.w - 1) / TX;
+  const int ty0 = region.y / TY, ty1 = (region.y + region.h - 1) / TY;
+  const int ntx = tx1 - tx0 + 1;
+  const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
+  for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
+    const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
+    process_tile<ST, TX, TY, kModeFields>(d, lt, p, sb, sidx, red, rho, ux, uy, region);
+    __syncthreads();
+  }
+}
+
+// One wave per body.  BIN_ONLY: bin the bodies of the current state into the lists of
+// the current parity (after set_particles or a tile-shape change); otherwise do the body
+// step of parity p and bin the moved bodies into the lists of parity p ^ 1.
+template <bool BIN_ONLY>
+__global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__restrict__ descs,
+                                                          const int32_t *__restrict__ body_solve,
+                                                          const BatchHeader *__restrict__ hdr,
+                                                          int k) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = kBlockThreads / 64;
+  const int total = hdr->total_bodies;
+  for (int g = blockIdx.x * wpb + (threadIdx.x >> 6); g < total; g += gridDim.x * wpb) {
+    const int s = __builtin_amdgcn_readfirstlane(body_solve[g]);
+    const SolveDesc &d = descs[s];
+    if (!BIN_ONLY && k >= d.active_steps) continue;
+    const int p = BIN_ONLY ? (d.parity0 & 1) : ((d.parity0 + k) & 1);
+    const int b = g - d.body_base;
+    const int nb = d.nbodies;
+    if (b < 0 || b >= nb) {  // the tables disagree with the descriptor: never index with b
+      if ((threadIdx.x & 63) == 0) atomicOr(d.err, (int32_t)kErrInternal);
+      continue;
+    }
+    const double *st = d.bstate[p];
+    const double dnx = (double)d.nx, dny = (double)d.ny;
+    double X = st[b], Y = st[nb + b];
+    double U = st[2 * nb + b], V = st[3 * nb + b], W = st[4 * nb + b];
+    const double R = d.bconst[b], rho_s = d.bconst[nb + b];
+    const double m = d.bconst[2 * nb + b], I = d.bconst[3 * nb + b];
+    const bool fixed = d.bconst[4 * nb + b] != 0.0;
+    int q = p;
+    if (!BIN_ONLY) {
+      // Eq. (28): repulsion from every other body of the solve (minimum image)
+      double fx = 0.0, fy = 0.0;
+      const double xi = d.xi;
+      for (int j = lane; j < nb; j += 64) {
+        if (j == b) continue;
+        const double dx = min_image(X - st[j], dnx);
+        const double dy = min_image(Y - st[nb + j], dny);
+        const double dist = sqrt(dx * dx + dy * dy);
+        const double rr = R + d.bconst[j];
+        double kk = 0.0;
+        if (dist > rr + xi) {
+          kk = 0.0;
+        } else if (dist <= rr) {
+          kk = (rr - dist) / d.eps_p1;
+        } else {
+          kk = (rr + xi - dist) * (rr + xi - dist) / d.eps_p;
+        }
+        fx += kk * dx;
+        fy += kk * dy;
+      }
+      fx = wave_sum(fx);  // every lane now holds the totals
+      fy = wave_sum(fy);
+      // Eq. (29): the image across the nearer surface of each wall slab
+      const double hw = d.wall_h_d;
+      for (int wall = 0; wall < 2; ++wall) {
+        if (!(d.wall_mask & (1u << wall))) continue;
+        const double c = wall == 0 ? Y : X;
+        const double n = wall == 0 ? dny : dnx;
+        const double dd = (c - hw <= (n - hw) - c) ? 2.0 * (c - hw) : -2.0 * ((n - hw) - c);
+        const double dist = fabs(dd);
+        double kk = 0.0;
+        if (dist > 2.0 * R + xi) {
+          kk = 0.0;
+        } else if (dist <= 2.0 * R) {
+          kk = (2.0 * R - dist) / d.eps_w1;
+        } else {
+          kk = (2.0 * R + xi - dist) * (2.0 * R + xi - dist) / d.eps_w;
+        }
+        if (wall == 0)
+          fy += kk * dd;
+        else
+          fx += kk * dd;
+      }
+      const double *acc = d.acc[p];
+      // Eq. (22): hydrodynamic force plus (rho_f / rho_s - 1) m g, rho_f = rho0
+      const double gfac = (d.rho0_d / rho_s - 1.0) * m;
+      fx += acc[3 * b] + gfac * d.gx;
+      fy += acc[3 * b + 1] + gfac * d.gy;
+      const double T = acc[3 * b + 2];
+      if (fixed) {
+        X += U;  // prescribed motion
+        Y += V;
+      } else {
+        // Eqs. (22)-(24), dt = 1: Euler velocity and spin, trapezoidal position
+        const double Un = U + fx / m, Vn = V + fy / m, Wn = W + T / I;
+        X += 0.5 * (U + Un);
+        Y += 0.5 * (V + Vn);
+        U = Un;
+        V = Vn;
+        W = Wn;
+      }
+      X = X - dnx * floor(X / dnx);
+      Y = Y - dny * floor(Y / dny);
+      if (X >= dnx) X -= dnx;
+      if (Y >= dny) Y -= dny;
+      q = p ^ 1;
+      if (lane == 0) {
+        double *sn = d.bstate[q];
+        sn[b] = X;
+        sn[nb + b] = Y;
+        sn[2 * nb + b] = U;
+        sn[3 * nb + b] = V;
+        sn[4 * nb + b] = W;
+      }
+    }
+    // a blown-up body is flagged instead of binned (its tile indices would be garbage)
+    if (!isfinite(X) || !isfinite(Y) || !isfinite(R)) {
+      if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
+      continue;
+    }
+    // bin into the tile lists of parity q: every tile holding a node within R + support
+    const double H = R + d.support + 1e-3;
+    const AxisTiles ax = axis_tiles(X, H, d.nx, d.tx, d.tiles_x);
+    const AxisTiles ay = axis_tiles(Y, H, d.ny, d.ty, d.tiles_y);
+    const int na = (ax.a1 - ax.a0 + 1) + max(0, ax.b1 - ax.b0 + 1);
+    const int nbb = (ay.a1 - ay.a0 + 1) + max(0, ay.b1 - ay.b0 + 1);
+    const int na1 = ax.a1 - ax.a0 + 1, nb1 = ay.a1 - ay.a0 + 1;
+    int32_t *cnt = d.tile_count[q];
+    int32_t *lst = d.tile_list[q];
+    for (int e = lane; e < na * nbb; e += 64) {
+      const int ia = e % na, ib = e / na;
+      const int tx = ia < na1 ? ax.a0 + ia : ax.b0 + (ia - na1);
+      const int ty = ib < nb1 ? ay.a0 + ib : ay.b0 + (ib - nb1);
+      const int tile = ty * d.tiles_x + tx;
+      const int slot = atomicAdd(&cnt[tile], 1);
+      if (slot < d.list_cap)
+        lst[(int64_t)tile * d.list_cap + slot] = b;
+      else
+        atomicOr(d.err, (int32_t)kErrCapacity);
+    }
+  }
+}
+
+// Populations in: natural layout deviations f[9][ny][nx] (FP64) -> pull layout
+// pop[i][x - c_i] = f_i(x).
+template <class ST>
+__global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p, const double *__restrict__ fin) {
+  const SolveDesc &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny;
+  typename ST::T *dst = (typename ST::T *)d.pop[p];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / plane);
+    const int64_t n = e - i * plane;
+    const int y = (int)(n / d.nx), x = (int)(n - (int64_t)y * d.nx);
+    int xs = x - CX[i], ys = y - CY[i];
+    if (xs < 0) xs += d.nx;
+    if (xs >= d.nx) xs -= d.nx;
+    if (ys < 0) ys += d.ny;
+    if (ys >= d.ny) ys -= d.ny;
+    ST::st(dst, i * plane + (int64_t)ys * d.nx + xs, (float)(36.0 * fin[e]), d.store_scale);
+  }
+}
+
+template <class ST>
+__global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__restrict__ fout) {
+  const SolveDesc &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny;
+  const typename ST::T *src = (const typename ST::T *)d.pop[p];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / plane);
+    const int64_t n = e - i * plane;
+    const int y = (int)(n / d.nx), x = (int)(n - (int64_t)y * d.nx);
+    int xs = x - CX[i], ys = y - CY[i];
+    if (xs < 0) xs += d.nx;
+    if (xs >= d.nx) xs -= d.nx;
+    if (ys < 0) ys += d.ny;
+    if (ys >= d.ny) ys -= d.ny;
+    fout[e] = (double)ST::ld(src, i * plane + (int64_t)ys * d.nx + xs, d.store_inv) / 36.0;
+  }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void k_fill_bytes(uint32_t *p, int64_t nwords) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nwords;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// launch wrappers
+
+#define DILBM_SHAPES(X) X(0, 64, 4) X(1, 128, 2) X(2, 256, 1) X(3, 32, 8) X(4, 16, 16)
+
+hipError_t launch_collide(int shape, int storage, int grid, hipStream_t stream,
+                          const SolveDesc *descs, const int32_t *tile_solve,
+                          const BatchHeader *hdr, int k) {
+#define DILBM_CASE(id, tx, ty)                                                              \
+  case id:                                                                                  \
+    if (storage == 1)                                                                       \
+      hipLaunchKernelGGL((k_collide<StoreF16, tx, ty>), dim3(grid), dim3(kBlockThreads), 0, \
+                         stream, descs, tile_solve, hdr, k);                                \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_collide<StoreF32, tx, ty>), dim3(grid), dim3(kBlockThreads), 0, \
+                         stream, descs, tile_solve, hdr, k);                                \
+    break;
+  switch (shape) {
+    DILBM_SHAPES(DILBM_CASE)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef DILBM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(int shape, int storage, int64_t ntiles, hipStream_t stream,
+                         const SolveDesc *desc, int p, Region region, double *rho, double *ux,
+                         double *uy) {
+  const int grid = grid_for(ntiles, 1);
+#define DILBM_CASE(id, tx, ty)                                                               \
+  case id:                                                                                   \
+    if (storage == 1)                                                                        \
+      hipLaunchKernelGGL((k_fields<StoreF16, tx, ty>), dim3(grid), dim3(kBlockThreads), 0,   \
+                         stream, desc, p, region, rho, ux, uy);                              \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_fields<StoreF32, tx, ty>), dim3(grid), dim3(kBlockThreads), 0,   \
+                         stream, desc, p, region, rho, ux, uy);                              \
+    break;
+  switch (shape) {
+    DILBM_SHAPES(DILBM_CASE)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef DILBM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_bodies(bool bin_only, int grid, hipStream_t stream, const SolveDesc *descs,
+                         const int32_t *body_solve, const BatchHeader *hdr, int k) {
+  if (bin_only)
+    hipLaunchKernelGGL((k_bodies<true>), dim3(grid), dim3(kBlockThreads), 0, stream, descs,
+                       body_solve, hdr, k);
+  else
+    hipLaunchKernelGGL((k_bodies<false>), dim3(grid), dim3(kBlockThreads), 0, stream, descs,
+                       body_solve, hdr, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_pops(int storage, int64_t count, hipStream_t stream, const SolveDesc *desc,
+                           int p, const double *fin) {
+  const int grid = grid_for(count, 256);
+  if (storage == 1)
+    hipLaunchKernelGGL((k_set_pops<StoreF16>), dim3(grid), dim3(256), 0, stream, desc, p, fin);
+  else
+    hipLaunchKernelGGL((k_set_pops<StoreF32>), dim3(grid), dim3(256), 0, stream, desc, p, fin);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_pops(int storage, int64_t count, hipStream_t stream, const SolveDesc *desc,
+                           int p, double *fout) {
+  const int grid = grid_for(count, 256);
+  if (storage == 1)
+    hipLaunchKernelGGL((k_get_pops<StoreF16>), dim3(grid), dim3(256), 0, stream, desc, p, fout);
+  else
+    hipLaunchKernelGGL((k_get_pops<StoreF32>), dim3(grid), dim3(256), 0, stream, desc, p, fout);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256)), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t stream) {
+  const int64_t words = bytes / 4;
+  if (words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_bytes, dim3(grid_for(words, 256)), dim3(256), 0, stream,
+                     (uint32_t *)p, words);
+  return hipGetLastError();
+}
+
+}  // namespace dilbm

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs.
+
+Tolerances (fixed before measuring, from the FP32 arithmetic): the GPU stores shifted
+populations f - w rho0 in FP32 (unit round-off u32 = 2^-24) and does every node update in
+FP32 over about 30 dependent operations on values no larger than the populations'
+deviations, so one step is accurate to a few hundred u32 of the largest deviation:
+``STEP_TOL = 256 * 2^-24 = 1.5e-5`` relative to max |f - w rho0|.  Over many steps the
+velocity error is bounded by the stated 1e-5 relative L2 after 1000 steps, and body
+positions by 1e-4 lattice units.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2106_08950_amd import inputs
+from helpers import gpu_solver, log_case, momentum, oracle_solver, rel_l2, velocity_rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+U32 = 2.0**-24
+STEP_TOL = 256 * U32
+
+
+def _random_case(seed, nx, ny, nb, walls=0, overlap=True, tau=None, G=(2e-5, -1e-5),
+                 g=(0.0, 1e-5), amp=1e-3):
+    rng = np.random.default_rng(seed)
+    b = inputs.random_bodies(rng, nx, ny, nb, rmin=3.0, rmax=9.0, allow_overlap=overlap,
+                             fixed_frac=0.3)
+    wl = inputs.Workload(name=f"rand{seed}", nx=nx, ny=ny,
+                         tau=float(rng.uniform(0.55, 1.4)) if tau is None else tau, nsteps=1,
+                         eps=float(rng.uniform(1.0, 2.5)), G=G, g=g, wall_mask=walls,
+                         wall_h=3.0, **b)
+    f0 = inputs.random_deviations(nx, ny, amp=amp, seed=seed)
+    return wl, f0
+
+
+CASES = [
+    # seed, nx, ny, bodies, walls
+    (1, 16, 16, 3, 0),
+    (2, 16, 16, 3, 3),
+    (3, 77, 45, 6, 0),     # ragged in x and y for every tile shape
+    (4, 130, 66, 9, 1),
+    (5, 200, 37, 12, 2),
+    (6, 33, 300, 5, 3),
+]
+
+
+@pytest.mark.parametrize("seed,nx,ny,nb,walls", CASES)
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+def test_one_step_matches_oracle(seed, nx, ny, nb, walls, tile):
+    wl, f0 = _random_case(seed, nx, ny, nb, walls)
+    log_case(f"one step seed={seed} {nx}x{ny} nb={wl.nbodies} walls={walls} tile={tile}")
+    o = oracle_solver(wl)
+    o.set_populations(f0)
+    o.step(1)
+    g = gpu_solver(wl, tile=tile)
+    g.set_populations(f0)
+    # the FP32 copy of the input, read back, is what the GPU starts from
+    assert np.allclose(g.get_populations(), f0, rtol=0, atol=U32 * np.abs(f0).max())
+    g.step(1)
+    fo = o.get_populations()
+    fg = g.get_populations()
+    scale = np.abs(fo).max()
+    err = np.abs(fg - fo).max() / scale
+    assert err <= STEP_TOL, err
+    Fo, To = o.get_particle_forces()
+    Fg, Tg = g.get_particle_forces()
+    fs = max(np.abs(Fo).max(), 1e-30)
+    assert np.abs(Fg - Fo).max() <= 1e-4 * fs, (Fg, Fo)
+    ts = max(np.abs(To).max(), 1e-30)
+    assert np.abs(Tg - To).max() <= 1e-4 * ts
+    if walls:
+        Wo, Wg = o.get_wall_force(), g.get_wall_force()
+        assert np.abs(Wg - Wo).max() <= 1e-4 * np.abs(Wo).max()
+    xo, uo, wo = o.get_particles()
+    xg, ug, wg = g.get_particles()
+    assert np.abs(xg - xo).max() < 1e-9
+    assert np.abs(ug - uo).max() <= 1e-4 * max(np.abs(uo).max(), 1e-30) + 1e-15
+    ro, uxo, uyo = o.get_fields()
+    rg, uxg, uyg = g.get_fields()
+    assert np.abs(rg - ro).max() < 1e-6
+    assert velocity_rel_l2(uxg, uyg, uxo, uyo) < 1e-5
+
+
+@pytest.mark.parametrize("seed,nx,ny,nb,walls", [(11, 64, 48, 5, 0), (12, 90, 70, 6, 3)])
+def test_many_steps_match_oracle(seed, nx, ny, nb, walls):
+    wl, f0 = _random_case(seed, nx, ny, nb, walls, overlap=False, amp=2e-4)
+    log_case(f"300 steps seed={seed} {nx}x{ny} nb={wl.nbodies} walls={walls}")
+    o = oracle_solver(wl)
+    o.set_populations(f0)
+    g = gpu_solver(wl)
+    g.set_populations(f0)
+    o.step(300)
+    g.step(300)
+    ro, uxo, uyo = o.get_fields()
+    rg, uxg, uyg = g.get_fields()
+    assert velocity_rel_l2(uxg, uyg, uxo, uyo) < 1e-5
+    xo, uo, wo = o.get_particles()
+    xg, ug, wg = g.get_particles()
+    d = np.abs(xg - xo)
+    d = np.minimum(d, [nx, ny] - d)
+    assert d.max() < 1e-4
+
+
+def test_rest_stays_at_rest_bitwise():
+    # shifted storage: f - w rho0 == 0 stays exactly 0 (no forcing, bodies at rest,
+    # neutrally buoyant free body under gravity)
+    wl = inputs.cylinder_channel()
+    wl = inputs.Workload(**{**wl.__dict__, "G": (0.0, 0.0), "g": (0.0, -1e-3)})
+    wl.pos = np.array([[100.0, 40.0], [40.0, 30.0]])
+    wl.radius = np.array([10.0, 6.0])
+    wl.density = np.array([1.0, 1.0])
+    wl.vel = np.zeros((2, 2))
+    wl.omega = np.zeros(2)
+    wl.fixed = np.array([1, 0], np.uint8)
+    log_case("rest")
+    g = gpu_solver(wl)
+    g.step(200)
+    assert np.all(g.get_populations() == 0.0)
+    x, u, om = g.get_particles()
+    assert np.array_equal(x, wl.pos) and np.all(u == 0) and np.all(om == 0)
+
+
+def test_uniform_body_force_accelerates_exactly():
+    G = (3e-6, -1e-6)
+    wl = inputs.Workload(name="acc", nx=130, ny=70, tau=0.7, nsteps=1, G=G)
+    log_case("uniform acceleration")
+    g = gpu_solver(wl)
+    g.step(25)
+    rho, ux, uy = g.get_fields()
+    assert np.allclose(ux, 25.5 * G[0], rtol=1e-5, atol=0)
+    assert np.allclose(uy, 25.5 * G[1], rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("walls", [0, 3])
+def test_action_reaction_and_mass(walls):
+    wl, f0 = _random_case(21 + walls, 64, 64, 6, walls)
+    log_case(f"action-reaction walls={walls}")
+    g = gpu_solver(wl)
+    g.set_populations(f0)
+    m0 = g.get_populations().sum()
+    for _ in range(4):
+        p0 = momentum(g.get_populations())
+        g.step(1)
+        p1 = momentum(g.get_populations())
+        F, T = g.get_particle_forces()
+        Fw = g.get_wall_force()
+        expect = wl.nodes * np.array(wl.G) - F.sum(0) - Fw
+        # FP32 sums over 4096 nodes of deviations ~1e-3
+        assert np.allclose(p1 - p0, expect, rtol=0, atol=64 * U32 * 4096 * 1e-3)
+    m1 = g.get_populations().sum()
+    assert abs(m1 - m0) < 64 * U32 * 4096 * 1e-3
+
+
+def test_cylinder_channel_1000_steps_matches_stored_oracle():
+    golden = np.load(_golden("cylinder_channel.npz"))
+    wl = inputs.cylinder_channel()
+    _check_digest(golden, wl)
+    log_case("cylinder channel 200x80, 1000 steps")
+    g = gpu_solver(wl)
+    forces = np.zeros((1000, 3))
+    for n in range(1000):
+        g.step(1)
+        F, T = g.get_particle_forces()
+        forces[n] = (F[0, 0], F[0, 1], T[0])
+    rho, ux, uy = g.get_fields()
+    err = velocity_rel_l2(ux, uy, golden["ux_1000"], golden["uy_1000"])
+    assert err <= 1e-5, err
+    fo = golden["forces"][:1000]
+    assert np.abs(forces[:, 0] - fo[:, 0]).max() <= 1e-5 * np.abs(fo[:, 0]).max()
+    # mirror symmetry of the channel: lift and torque vanish up to FP32 round-off
+    assert np.abs(forces[:, 1]).max() <= 1e-5 * np.abs(fo[:, 0]).max()
+
+
+def _golden(name):
+    import os
+
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
+def _check_digest(golden, wl):
+    import json
+    import sys
+    import os
+
+    sys.path.insert(0, os.path.dirname(_golden("x")))
+    from make_golden import workload_digest
+
+    meta = json.loads(str(golden["meta"]))
+    assert meta["digest"] == workload_digest(wl), "input generator changed; regenerate goldens"
