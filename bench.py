@@ -1,12 +1,19 @@
 """Benchmark of the DI-LBM time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp16] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs fp32,fp16,batched,served]
+                    [--no-cpu]
 
-Workload (one step = the whole hot path over one solve): the dense suspension of
+Headline workload (one step = the whole hot path over one solve): the dense suspension of
 4096 x 4096 periodic nodes with 2000 free discs of radius 8 (seed 3), tau = 0.6, body
-force 1e-6, FP32 shifted-population storage -- its 1.2 GB working set exceeds the
-256 MB Infinity Cache, so the populations stream from HBM every step.  Inputs are
-resident in HBM before the timed region starts.  Prints one JSON line.
+force 1e-6, FP32 shifted-population storage -- its 1.2 GB working set exceeds the 256 MB
+Infinity Cache, so the populations stream from HBM every step.  Inputs are resident in
+HBM before the timed region starts.  Further legs, reported in the same JSON line:
+* fp16: the same workload with FP16 storage (36 B per node update);
+* batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
+  same solves run one after another as plain solves;
+* served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
+  loop, with p50/p99 completion latency.
+Prints one JSON line.
 """
 import argparse
 import json
@@ -19,6 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline, FP32 vs batched/FP16; p50/p99 latency of served solves"
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def run_oracle_sample(wl, steps):
@@ -39,53 +50,123 @@ def run_oracle_sample(wl, steps):
     return {"value": round(wl.nodes * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{wl.name}: {steps} steps after 1 warm-up step, FP64, "
-                      f"{oracle.num_threads()} OpenMP threads"}
+                      f"{oracle.num_threads()} OpenMP threads, {dt:.1f} s"}
+
+
+def single_solve(wl, storage, steps, warmup, tile, stream):
+    """Timed single-solve run; returns (mlups, seconds, collide_ms_avg, launches)."""
+    import torch
+
+    from paper_2106_08950_amd import dilbm
+
+    prm = dilbm.params_from_workload(wl, storage=storage, tile=tile, device=0,
+                                     stream=stream.cuda_stream)
+    s = dilbm.Solver(prm)
+    s.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
+    s.step(warmup)
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    collide_ms, launches = s.kernel_timing()
+    s.close()
+    return wl.nodes * steps / dt / 1e6, dt, collide_ms / max(launches, 1), launches
+
+
+def batched_leg(stream, steps_per_solve=2000):
+    """256-solve ensemble: one pool vs one plain solve after another."""
+    import torch
+
+    from paper_2106_08950_amd import dilbm, inputs
+
+    wls = inputs.ensemble(nsteps=steps_per_solve)
+    total = sum(w.nodes for w in wls) * steps_per_solve
+    fp = sum(dilbm.footprint(dilbm.params_from_workload(w), w.nbodies) for w in wls)
+    arena = torch.empty(int(fp * 1.05) + (64 << 20), dtype=torch.uint8, device="cuda")
+    pool = dilbm.Pool(arena_bytes=arena.numel(), stream=stream.cuda_stream,
+                      arena_ptr=arena.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = [pool.submit(dilbm.params_from_workload(w), w.nsteps, w.pos, w.radius,
+                           w.density, w.vel, w.omega, w.fixed) for w in wls]
+    k, tile = pool.autotune(steps_per_trial=16)
+    pool.run(steps_per_solve)
+    pool.sync()
+    dt_pool = time.perf_counter() - t0
+    for t in tickets:
+        assert pool.query(t) == (steps_per_solve, True)
+    pool.close()
+    del arena
+    log(f"batched pool: {dt_pool:.2f} s, graph_steps={k}, tile={tile}")
+    # the same solves, one plain solve after another
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in wls:
+        s = dilbm.Solver(dilbm.params_from_workload(w, stream=stream.cuda_stream))
+        s.set_particles(w.pos, w.radius, w.density, w.vel, w.omega, w.fixed)
+        s.step(steps_per_solve)
+        s.close()
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    log(f"sequential plain solves: {dt_seq:.2f} s")
+    return {"workload": f"ensemble of {len(wls)} solves x {steps_per_solve} steps",
+            "node_updates": total,
+            "pool_mlups": round(total / dt_pool / 1e6, 1),
+            "sequential_mlups": round(total / dt_seq / 1e6, 1),
+            "speedup": round(dt_seq / dt_pool, 2),
+            "graph_steps": k, "tile": tile,
+            "timing": "wall clock, admission + autotune + all steps (pool); create + "
+                      "steps + destroy of each solve (sequential)"}
+
+
+def served_leg(count=500):
+    from paper_2106_08950_amd import inputs, serve
+
+    reqs = inputs.request_stream(count=count)
+    st = serve.serve(reqs, arena_bytes=200 << 30, chunk=64, graph_steps=32, tile=0,
+                     realtime=True)
+    log(f"served: {len(st.results)} done, makespan {st.makespan:.1f} s")
+    return {"workload": f"request stream: {count} Poisson arrivals at 50/s",
+            "completed": len(st.results), "rejected": st.rejected,
+            "aggregate_mlups": round(st.mlups, 1),
+            "p50_latency_s": round(st.percentile(50), 3),
+            "p99_latency_s": round(st.percentile(99), 3),
+            "makespan_s": round(st.makespan, 2),
+            "arrival_span_s": round(reqs[-1][0], 2)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--legs", default="fp32,fp16,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--served-count", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the slab decomposition is described in DESIGN.md); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(","))
 
     import torch
 
     from paper_2106_08950_amd import dilbm, inputs
 
     torch.cuda.init()
-    wl = inputs.dense_suspension()
-    storage = dilbm.STORE_FP16 if args.storage == "fp16" else dilbm.STORE_FP32
     stream = torch.cuda.Stream()
-    prm = dilbm.params_from_workload(wl, storage=storage, tile=args.tile, device=0,
-                                     stream=stream.cuda_stream)
-    s = dilbm.Solver(prm)
-    s.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
-    s.step(args.warmup)
+    wl = inputs.dense_suspension()
 
-    s.set_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    collide_ms, launches = s.kernel_timing()
-    s.set_kernel_timing(False)
-
-    nodes = wl.nodes
-    mlups = nodes * args.steps / dt / 1e6
-    bytes_per_node = 72 if storage == dilbm.STORE_FP32 else 36
-    avg_ms = collide_ms / max(launches, 1)
-    achieved = bytes_per_node * nodes / (avg_ms * 1e-3) / 1e9
+    log(f"fp32 {wl.name}: {args.steps} steps")
+    mlups, dt, avg_ms, launches = single_solve(wl, dilbm.STORE_FP32, args.steps, args.warmup,
+                                               args.tile, stream)
+    achieved = 72 * wl.nodes / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -100,16 +181,32 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "bodies": wl.nbodies,
-                   "tau": wl.tau, "storage": args.storage, "tile": prm.tile},
+                   "tau": wl.tau, "storage": "fp32", "tile": args.tile},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "k_collide", "bytes_per_node": bytes_per_node,
+                     "traffic": None, "kernel": "k_collide", "bytes_per_node": 72,
                      "avg_launch_ms": round(avg_ms, 5), "launches": launches},
     }
+    if "fp16" in legs:
+        log("fp16")
+        m16, dt16, avg16, n16 = single_solve(wl, dilbm.STORE_FP16, args.steps, args.warmup,
+                                             args.tile, stream)
+        a16 = 36 * wl.nodes / (avg16 * 1e-3) / 1e9
+        out["fp16"] = {"value": round(m16, 1), "unit": "MLUPS",
+                       "ms_per_step": round(dt16 * 1e3 / args.steps, 4),
+                       "roofline": {"bound": "hbm", "achieved": round(a16, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(a16 / HBM_PEAK_GBS, 4), "bytes_per_node": 36,
+                                    "avg_launch_ms": round(avg16, 5)}}
+    if "batched" in legs:
+        log("batched")
+        out["batched"] = batched_leg(stream)
+    if "served" in legs:
+        log("served")
+        out["served"] = served_leg(args.served_count)
     if not args.no_cpu:
+        log("cpu baseline")
         out["cpu_baseline"] = run_oracle_sample(wl, args.cpu_steps)
-    s.close()
     print(json.dumps(out), flush=True)
 
 

@@ -29,6 +29,17 @@ constexpr int kBlockThreads = 256;       // every tile shape has 256 nodes
 constexpr int kBodyChunk = 64;           // bodies staged in LDS at a time
 constexpr int kMaxListCap = 1024;
 
+// Register budget of the collide kernel: it is compiled for at least this many waves per
+// SIMD (512 / N VGPRs per lane).  The step streams populations, so waves in flight are
+// bytes in flight.
+#ifndef DILBM_COLLIDE_WAVES
+#define DILBM_COLLIDE_WAVES 6
+#endif
+// Persistent collide grid: this many times the blocks that are resident on one CU at once.
+#ifndef DILBM_GRID_MULT
+#define DILBM_GRID_MULT 1
+#endif
+
 enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
 
 struct SolveDesc {
@@ -53,13 +64,15 @@ struct SolveDesc {
   float phi_k;                 // 4 / eps * log2(e): phi = 1 / (1 + 2^(-l * phi_k))
   float lcut;                  // -cutoff * eps
   float wall_h;
+  int32_t wall_y_lo, wall_y_hi;  // rows outside [lo, hi) are within a y-wall's support
+  int32_t wall_x_lo, wall_x_hi;
   float kappa;                 // force scale of Eqs. (18)-(19)
   float store_scale, store_inv;
   int32_t storage;
   // FP64 body constants
   double rho0_d;
   double gx, gy;
-  double eps_p, eps_p1, eps_w, eps_w1, xi;
+  double inv_eps_p, inv_eps_p1, inv_eps_w, inv_eps_w1, xi;  // Eqs. (28)-(29)
   double wall_h_d;
   double support;              // cutoff * eps: phi support beyond the radius
   // device buffers

@@ -260,6 +260,16 @@ void fill_desc(Solve &s) {
   d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
   d.lcut = (float)(-p.phi_cutoff * p.interface_width);
   d.wall_h = (float)p.wall_half_thickness;
+  {
+    // node j (centre j + 1/2) is within reach of the seam at 0 when j + 1/2 <= h + cut,
+    // and of the seam at n when n - (j + 1/2) <= h + cut; one node of slack each side
+    const double reach = p.wall_half_thickness + p.phi_cutoff * p.interface_width;
+    const int lo = (int)std::floor(reach - 0.5) + 2;
+    d.wall_y_lo = std::min(lo, p.ny);
+    d.wall_y_hi = std::max(p.ny - lo, 0);
+    d.wall_x_lo = std::min(lo, p.nx);
+    d.wall_x_hi = std::max(p.nx - lo, 0);
+  }
   d.kappa = p.force_mode == DILBM_FORCE_PAPER_LITERAL ? (float)(1.0 - 0.5 / p.tau) : 1.0f;
   d.storage = p.storage;
   const double sc = p.storage == DILBM_STORE_FP16 ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
@@ -268,10 +278,10 @@ void fill_desc(Solve &s) {
   d.rho0_d = p.rho0;
   d.gx = p.gravity[0];
   d.gy = p.gravity[1];
-  d.eps_p = p.coll_eps_p;
-  d.eps_p1 = p.coll_eps_p_overlap;
-  d.eps_w = p.coll_eps_w;
-  d.eps_w1 = p.coll_eps_w_overlap;
+  d.inv_eps_p = 1.0 / p.coll_eps_p;
+  d.inv_eps_p1 = 1.0 / p.coll_eps_p_overlap;
+  d.inv_eps_w = 1.0 / p.coll_eps_w;
+  d.inv_eps_w1 = 1.0 / p.coll_eps_w_overlap;
   d.xi = p.coll_xi;
   d.wall_h_d = p.wall_half_thickness;
   d.support = p.phi_cutoff * p.interface_width;
@@ -637,6 +647,19 @@ class Engine {
                                  hipMemcpyHostToDevice, stream_));
     HIPCHK(hipMemcpyAsync(d_hdr_, &hh, sizeof(BatchHeader), hipMemcpyHostToDevice, stream_));
     HIPCHK(hipEventRecord(table_ev_, stream_));
+    // population addressing: one buffer resource while a population buffer (9 planes)
+    // stays under 2 GB, 32-bit plane offsets while a plane stays under 2 GB, else 64-bit
+    int addr = 0;
+    for (Solve *s : members_) {
+      const uint64_t pb = (uint64_t)s->prm.nx * s->prm.ny *
+                          (s->prm.storage == DILBM_STORE_FP16 ? 2 : 4);
+      const int a = kQ * pb < (1ull << 31) ? 0 : (pb < (1ull << 31) ? 1 : 2);
+      addr = std::max(addr, a);
+    }
+    if (addr != addr_) {
+      addr_ = addr;
+      clear_graphs();
+    }
     const bool grid_change = collide_grid_for(T) != collide_grid_ || bodies_grid_for(B) != bodies_grid_;
     total_tiles_ = T;
     total_bodies_ = (int)B;
@@ -648,10 +671,13 @@ class Engine {
     dirty_ = false;
   }
 
-  int collide_grid_for(int64_t T) const {
-    // one tile per block, or a persistent grid of a few blocks per CU that sweeps the work
-    int64_t g = T;
-    if (persistent_) g = std::min<int64_t>(T, (int64_t)num_cu_ * 8);
+  int collide_grid_for(int64_t T) {
+    // a persistent grid sweeps the tiles, sized to the blocks that are resident at once
+    // (per-block set-up is paid once per block, not once per tile; blocks beyond the
+    // resident ones would run as a second, thinner wave)
+    int &bpc = blocks_per_cu_[shape_][storage_][addr_];
+    if (bpc == 0) bpc = std::max(1, collide_blocks_per_cu(shape_, storage_, addr_));
+    int64_t g = std::min<int64_t>(T, (int64_t)num_cu_ * bpc * DILBM_GRID_MULT);
     g = std::min<int64_t>(g, (int64_t)1 << 30);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
@@ -673,8 +699,8 @@ class Engine {
         }
         HIPCHK(hipEventRecord(timing_ev_[timing_used_].first, stream_));
       }
-      HIPCHK(launch_collide(shape_, storage_, collide_grid_, stream_, d_descs_, d_tile_solve_,
-                            d_hdr_, k));
+      HIPCHK(launch_collide(shape_, storage_, addr_, collide_grid_, stream_, d_descs_,
+                            d_tile_solve_, d_hdr_, k));
       if (timed) {
         HIPCHK(hipEventRecord(timing_ev_[timing_used_].second, stream_));
         ++timing_used_;
@@ -723,6 +749,8 @@ class Engine {
   int storage_ = 0;
   int graph_steps_ = 32;
   bool persistent_ = false;
+  int addr_ = 0;
+  int blocks_per_cu_[kNumTileShapes][2][3] = {};
   std::vector<Solve *> members_;
   std::vector<bool> slot_used_;
   bool dirty_ = true;

@@ -36,21 +36,70 @@ constexpr int CX[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int CY[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr float KQ[kQ] = {16.0f, 4.0f, 4.0f, 4.0f, 4.0f, 1.0f, 1.0f, 1.0f, 1.0f};
 
+// Global-address-space access.  Pointers read from a descriptor are generic, and generic
+// accesses compile to flat instructions with a 64-bit address per lane; casting the
+// (uniform) plane base to the global address space and adding a 32-bit byte offset lets
+// each access be one global_load/global_store with a scalar base.
+#define DILBM_GLOBAL __attribute__((address_space(1)))
+
+// Buffer resource word 3 for raw 32-bit buffer access on gfx9-family parts.
+constexpr int kBufferFlags = 0x00020000;
+
 struct StoreF32 {
   using T = float;
+  static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void stb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                             uint32_t soff, float v, float) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  }
   static __device__ __forceinline__ float ld(const T *p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ void st(T *p, int64_t i, float v, float) { p[i] = v; }
+  static __device__ __forceinline__ float ldo(const T *plane, uint32_t byte_off, float) {
+    return *(const DILBM_GLOBAL T *)((const DILBM_GLOBAL char *)plane + byte_off);
+  }
+  static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float) {
+    *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = v;
+  }
 };
 
 struct StoreF16 {
   using T = _Float16;
+  static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, float inv) {
+    const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return (float)__builtin_bit_cast(_Float16, h) * inv;
+  }
+  static __device__ __forceinline__ void stb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                             uint32_t soff, float v, float scale) {
+    const _Float16 h = (_Float16)(v * scale);  // round to nearest even
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, voff, soff, 0);
+  }
   static __device__ __forceinline__ float ld(const T *p, int64_t i, float inv) {
     return (float)p[i] * inv;
   }
   static __device__ __forceinline__ void st(T *p, int64_t i, float v, float scale) {
     p[i] = (_Float16)(v * scale);  // round to nearest even
   }
+  static __device__ __forceinline__ float ldo(const T *plane, uint32_t byte_off, float inv) {
+    return (float)*(const DILBM_GLOBAL T *)((const DILBM_GLOBAL char *)plane + byte_off) * inv;
+  }
+  static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float scale) {
+    *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = (_Float16)(v * scale);
+  }
 };
+
+constexpr float kInv36 = 1.0f / 36.0f;
+
+// x / 36 to within the round-off of the correctly rounded quotient: one product with the
+// rounded reciprocal and one exact-residual correction.  Unlike x * fl(1/36) alone it
+// carries no constant relative bias.
+__device__ __forceinline__ float div36(float x) {
+  const float q = x * kInv36;
+  return fmaf(fmaf(-36.0f, q, x), kInv36, q);
+}
 
 struct BodyLds {
   double x, y;
@@ -115,6 +164,57 @@ __device__ __forceinline__ WorkSplit xcd_split(int64_t T) {
 
 enum TileMode { kModeStep = 0, kModeFields = 1 };
 
+// How population planes are addressed: one buffer resource per population buffer with
+// scalar plane offsets (buffer under 4 GB), a scalar plane base with 32-bit byte offsets
+// (plane under 2 GB), or 64-bit addresses.
+enum AddrMode { kAddrBuf = 0, kAddrG32 = 1, kAddrWide = 2 };
+
+// Per-node inputs of the collision, all in g units (36 x physical) except where noted.
+struct NodeState {
+  float drho, rho;        // physical
+  float ux, uy;           // corrected velocity, Eq. (17)
+  float momx, momy;       // rho u, physical, without constant bias
+  float Px, Py;           // rho (A - Phi u*), physical
+  float Qxx, Qxy, Qyy;    // rho (M - Phi u* u*), physical
+};
+
+// Eq. (13) for one node, over the four pairs of opposite directions (c_j = -c_i) so that
+// each pair shares its even part: the post-collision g_i is
+//   g_i + omega (geq_i - g_i) + khalf K_i S_i,
+//   geq_i = K_i [drho + 3 c.(rho u) + rho (4.5 (c.u)^2 - 1.5 u^2)],
+//   S_i   = 3 (c - u).G + 9 (c.u)(c.G)                          (body-force forcing)
+//         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q   when the tile has solid (Eq. (15) summed).
+template <bool SOLID>
+__device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], const NodeState &n,
+                                             float Gx, float Gy, float om, float kh) {
+  const float usq = n.ux * n.ux + n.uy * n.uy;
+  const float even0 = fmaf(-1.5f * n.rho, usq, n.drho);
+  const float r45 = 4.5f * n.rho;
+  float se0 = -3.0f * (n.ux * Gx + n.uy * Gy);
+  if (SOLID) se0 = fmaf(-1.5f, n.Qxx + n.Qyy, se0);
+  out[0] = fmaf(kh * 16.0f, se0, fmaf(om, 16.0f * even0 - f[0], f[0]));
+  auto pair = [&](int i, int j, float K, float cu, float cm, float cG, float cP, float cQc) {
+    const float E = fmaf(r45, cu * cu, even0);
+    const float O = 3.0f * cm;
+    float Se = fmaf(9.0f * cG, cu, se0);
+    float So = 3.0f * cG;
+    if (SOLID) {
+      Se = fmaf(4.5f, cQc, Se);
+      So = fmaf(3.0f, cP, So);
+    }
+    const float khK = kh * K;
+    out[i] = fmaf(khK, Se + So, fmaf(om, K * (E + O) - f[i], f[i]));
+    out[j] = fmaf(khK, Se - So, fmaf(om, K * (E - O) - f[j], f[j]));
+  };
+  // (1,0)/(-1,0), (0,1)/(0,-1), (1,1)/(-1,-1), (-1,1)/(1,-1)
+  pair(1, 3, 4.0f, n.ux, n.momx, Gx, n.Px, n.Qxx);
+  pair(2, 4, 4.0f, n.uy, n.momy, Gy, n.Py, n.Qyy);
+  pair(5, 7, 1.0f, n.ux + n.uy, n.momx + n.momy, Gx + Gy, n.Px + n.Py,
+       n.Qxx + 2.0f * n.Qxy + n.Qyy);
+  pair(6, 8, 1.0f, n.uy - n.ux, n.momy - n.momx, Gy - Gx, n.Py - n.Px,
+       n.Qxx - 2.0f * n.Qxy + n.Qyy);
+}
+
 // Copy one listed body into LDS.  An index outside [0, nb) (never written by the binning)
 // is flagged and staged as a body with no support, so it touches no memory and no node.
 __device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs, int nbs, int b,
@@ -138,7 +238,7 @@ __device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs,
 }
 
 // One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
-template <class ST, int TX, int TY, int MODE>
+template <class ST, int TX, int TY, int MODE, int AM>
 __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
                                              BodyLds *sb, int32_t *sidx,
                                              double (*red)[kBlockThreads / 64][3],
@@ -155,10 +255,11 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const int txi = lt - tyi * d.tiles_x;
   const int x0 = txi * TX, y0 = tyi * TY;
   const int x = x0 + (tid % TX);
-  const int y = y0 + (tid / TX);
+  // a wave covers part of one row when the tile is at least 64 wide: its row is uniform
+  const int y = TX >= 64 ? __builtin_amdgcn_readfirstlane(y0 + tid / TX) : y0 + tid / TX;
   const bool valid = (x < nx) && (y < ny);
-  const int xc = valid ? x : x0;  // clamped coordinates keep loads in bounds
-  const int yc = valid ? y : y0;
+  const int xc = min(x, nx - 1);  // clamped coordinates keep loads in bounds
+  const int yc = min(y, ny - 1);
 
   // an overflowed list (count > capacity) is flagged by the binning; read only what fits
   const int nb = min(__builtin_amdgcn_readfirstlane(d.tile_count[p][lt]), d.list_cap);
@@ -171,24 +272,79 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   }
 
   // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) --------------------------------
-  const typename ST::T *__restrict__ src = (const typename ST::T *)d.pop[p];
+  using T = typename ST::T;
+  const T *__restrict__ src = (const T *)d.pop[p];
+  T *__restrict__ dst = (T *)d.pop[p ^ 1];
   const int64_t plane = (int64_t)nx * ny;
   const int xm = (xc == 0) ? nx - 1 : xc - 1;
   const int xp = (xc + 1 == nx) ? 0 : xc + 1;
   const int ym = (yc == 0) ? ny - 1 : yc - 1;
   const int yp = (yc + 1 == ny) ? 0 : yc + 1;
-  const int64_t r0 = (int64_t)yc * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
   const float inv = d.store_inv;
   float f[kQ];
-  f[0] = ST::ld(src, 0 * plane + r0 + xc, inv);
-  f[1] = ST::ld(src, 1 * plane + r0 + xm, inv);
-  f[2] = ST::ld(src, 2 * plane + rm + xc, inv);
-  f[3] = ST::ld(src, 3 * plane + r0 + xp, inv);
-  f[4] = ST::ld(src, 4 * plane + rp + xc, inv);
-  f[5] = ST::ld(src, 5 * plane + rm + xm, inv);
-  f[6] = ST::ld(src, 6 * plane + rm + xp, inv);
-  f[7] = ST::ld(src, 7 * plane + rp + xp, inv);
-  f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
+  // byte offsets inside a plane: 32-bit unless the plane reaches 2 GB
+  uint32_t o_r0 = 0, o_rm = 0, o_rp = 0, o_x0 = 0, o_xm = 0, o_xp = 0;
+  constexpr uint32_t es = sizeof(T);
+  if (AM != kAddrWide) {
+    o_r0 = (uint32_t)(yc * nx) * es;
+    o_rm = (uint32_t)(ym * nx) * es;
+    o_rp = (uint32_t)(yp * nx) * es;
+    o_x0 = (uint32_t)xc * es;
+    o_xm = (uint32_t)xm * es;
+    o_xp = (uint32_t)xp * es;
+  }
+  const uint32_t pb = (uint32_t)plane * es;  // plane bytes (buffer mode only)
+  if (AM == kAddrBuf && TX >= 64) {
+    // rows are wave-uniform: plane and row offsets go in the scalar offset, and every
+    // load needs one of three per-lane column offsets
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)(kQ * pb), kBufferFlags);
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(o_r0);
+    const uint32_t sm = __builtin_amdgcn_readfirstlane(o_rm);
+    const uint32_t sp = __builtin_amdgcn_readfirstlane(o_rp);
+    f[0] = ST::ldb(rs, o_x0, 0 * pb + s0, inv);
+    f[1] = ST::ldb(rs, o_xm, 1 * pb + s0, inv);
+    f[2] = ST::ldb(rs, o_x0, 2 * pb + sm, inv);
+    f[3] = ST::ldb(rs, o_xp, 3 * pb + s0, inv);
+    f[4] = ST::ldb(rs, o_x0, 4 * pb + sp, inv);
+    f[5] = ST::ldb(rs, o_xm, 5 * pb + sm, inv);
+    f[6] = ST::ldb(rs, o_xp, 6 * pb + sm, inv);
+    f[7] = ST::ldb(rs, o_xp, 7 * pb + sp, inv);
+    f[8] = ST::ldb(rs, o_xm, 8 * pb + sp, inv);
+  } else if (AM == kAddrBuf) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)(kQ * pb), kBufferFlags);
+    f[0] = ST::ldb(rs, o_r0 + o_x0, 0 * pb, inv);
+    f[1] = ST::ldb(rs, o_r0 + o_xm, 1 * pb, inv);
+    f[2] = ST::ldb(rs, o_rm + o_x0, 2 * pb, inv);
+    f[3] = ST::ldb(rs, o_r0 + o_xp, 3 * pb, inv);
+    f[4] = ST::ldb(rs, o_rp + o_x0, 4 * pb, inv);
+    f[5] = ST::ldb(rs, o_rm + o_xm, 5 * pb, inv);
+    f[6] = ST::ldb(rs, o_rm + o_xp, 6 * pb, inv);
+    f[7] = ST::ldb(rs, o_rp + o_xp, 7 * pb, inv);
+    f[8] = ST::ldb(rs, o_rp + o_xm, 8 * pb, inv);
+  } else if (AM == kAddrG32) {
+    f[0] = ST::ldo(src + 0 * plane, o_r0 + o_x0, inv);
+    f[1] = ST::ldo(src + 1 * plane, o_r0 + o_xm, inv);
+    f[2] = ST::ldo(src + 2 * plane, o_rm + o_x0, inv);
+    f[3] = ST::ldo(src + 3 * plane, o_r0 + o_xp, inv);
+    f[4] = ST::ldo(src + 4 * plane, o_rp + o_x0, inv);
+    f[5] = ST::ldo(src + 5 * plane, o_rm + o_xm, inv);
+    f[6] = ST::ldo(src + 6 * plane, o_rm + o_xp, inv);
+    f[7] = ST::ldo(src + 7 * plane, o_rp + o_xp, inv);
+    f[8] = ST::ldo(src + 8 * plane, o_rp + o_xm, inv);
+  } else {
+    const int64_t r0 = (int64_t)yc * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+    f[0] = ST::ld(src, 0 * plane + r0 + xc, inv);
+    f[1] = ST::ld(src, 1 * plane + r0 + xm, inv);
+    f[2] = ST::ld(src, 2 * plane + rm + xc, inv);
+    f[3] = ST::ld(src, 3 * plane + r0 + xp, inv);
+    f[4] = ST::ld(src, 4 * plane + rp + xc, inv);
+    f[5] = ST::ld(src, 5 * plane + rm + xm, inv);
+    f[6] = ST::ld(src, 6 * plane + rm + xp, inv);
+    f[7] = ST::ld(src, 7 * plane + rp + xp, inv);
+    f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
+  }
 
   // ---- moments, Eqs. (5) and (16); u* carries half the fluid body force ----------------
   // (in g units: D = 36 delta rho, J = 36 j, R = 36 rho)
@@ -196,11 +352,17 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float Jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const float Jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const float R = d.rho36 + D;
-  const float rho = R / 36.0f;   // correctly rounded: no constant bias
-  const float drho = D / 36.0f;
-  const float Rinv = 1.0f / R;
-  const float usx = (Jx + 18.0f * d.Gx) * Rinv;  // u* = (j + G/2) / rho
-  const float usy = (Jy + 18.0f * d.Gy) * Rinv;
+  // rho enters only second-order and body terms, drho only the mass term: a constant
+  // relative error of 7.5e-9 from fl(1/36) there is harmless
+  const float rho = R * kInv36;
+  const float drho = D * kInv36;
+  // 1/R: hardware reciprocal plus one Newton step (about half an ulp)
+  float Rinv = __builtin_amdgcn_rcpf(R);
+  Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
+  const float Jgx = Jx + 18.0f * d.Gx;  // 36 rho u* = 36 (j + G/2)
+  const float Jgy = Jy + 18.0f * d.Gy;
+  const float usx = Jgx * Rinv;         // u*
+  const float usy = Jgy * Rinv;
 
   // ---- diffuse solid field, Eq. (14), and its sums over the covering bodies ------------
   float Phi = 0.f, Ax = 0.f, Ay = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
@@ -209,26 +371,23 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float h = d.wall_h;
   const float cut = -lcut;
   // walls: static slabs across the seams; does this tile reach into one's support?
-  const bool wy = (d.wall_mask & 1u) &&
-                  ((float)y0 + 0.5f <= h + cut ||
-                   (float)ny - ((float)min(y0 + TY, ny) - 0.5f) <= h + cut);
-  const bool wx = (d.wall_mask & 2u) &&
-                  ((float)x0 + 0.5f <= h + cut ||
-                   (float)nx - ((float)min(x0 + TX, nx) - 0.5f) <= h + cut);
+  // (rows [0, wall_lo) and [wall_hi, n) hold the nodes within h + cutoff of a seam)
+  const bool wy = (d.wall_mask & 1u) && (y0 < d.wall_y_lo || y0 + TY > d.wall_y_hi);
+  const bool wx = (d.wall_mask & 2u) && (x0 < d.wall_x_lo || x0 + TX > d.wall_x_hi);
   const bool any_solid = (nb > 0) || wy || wx;
-  float lwy = -1e30f, lwx = -1e30f;
-  if (wy) {
-    float dy = (float)yc + 0.5f;
-    if (dy >= 0.5f * (float)ny) dy -= (float)ny;
-    lwy = h - fabsf(dy);
-  }
-  if (wx) {
-    float dx = (float)xc + 0.5f;
-    if (dx >= 0.5f * (float)nx) dx -= (float)nx;
-    lwx = h - fabsf(dx);
-  }
 
   if (any_solid) {
+    float lwy = -1e30f, lwx = -1e30f;
+    if (wy) {
+      float dy = (float)yc + 0.5f;
+      if (dy >= 0.5f * (float)ny) dy -= (float)ny;
+      lwy = h - fabsf(dy);
+    }
+    if (wx) {
+      float dx = (float)xc + 0.5f;
+      if (dx >= 0.5f * (float)nx) dx -= (float)nx;
+      lwx = h - fabsf(dx);
+    }
     const int nsolid = nb + (wy ? 1 : 0) + (wx ? 1 : 0);
     const int32_t *list = d.tile_list[p] + (int64_t)lt * d.list_cap;
     const double *bs = d.bstate[p];
@@ -354,8 +513,17 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   }
 
   // ---- corrected velocity, Eq. (17): u = u* + (sum_b w_b u_s,b - Phi u*) / 2 ----------
-  const float ux = usx + 0.5f * (Ax - Phi * usx);
-  const float uy = usy + 0.5f * (Ay - Phi * usy);
+  // P = rho (A - Phi u*) is the momentum the node takes from the bodies; 36 rho u =
+  // 36 rho u* + 18 P.  The equilibrium's momentum-carrying term is built from
+  // rho u = (36 rho u) / 36 directly: through u = (36 rho u) / R it would inherit the
+  // constant rounding error of 1/R (R is 36 to within 1e-5, a handful of float values),
+  // a momentum bias in every collision that compounds over the run.
+  const float Px = rho * (Ax - Phi * usx);
+  const float Py = rho * (Ay - Phi * usy);
+  const float Mx = fmaf(18.0f, Px, Jgx);
+  const float My = fmaf(18.0f, Py, Jgy);
+  const float ux = Mx * Rinv;
+  const float uy = My * Rinv;
 
   if (MODE == kModeFields) {
     // out_* cover the region [rx0, rx0 + rw) x [ry0, ry0 + rh), row stride rw
@@ -374,38 +542,51 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     atomicOr(d.err, (int32_t)kErrUnstable);
 
   // ---- collision, Eq. (13), in g units ----------------------------------------------
-  // 36 x (phi F_i summed over bodies, Eq. (15)) = khalf K_i [3 c.P + 4.5 c.Q.c - 1.5 tr Q]
-  // with P = rho (A - Phi u*), Q = rho (M - Phi u* u*); Guo forcing adds
-  // khalf K_i [3 (c - u).G + 9 (c.u)(c.G)]; the equilibrium is K_i [drho + rho P_i(u)].
-  const float Px = rho * (Ax - Phi * usx);
-  const float Py = rho * (Ay - Phi * usy);
-  const float Qxx = rho * (Mxx - Phi * usx * usx);
-  const float Qxy = rho * (Mxy - Phi * usx * usy);
-  const float Qyy = rho * (Myy - Phi * usy * usy);
-  const float trQ = Qxx + Qyy;
-  const float uG = ux * d.Gx + uy * d.Gy;
-  const float om = d.omega;
-  const float kh = d.khalf;
-  typename ST::T *__restrict__ dst = (typename ST::T *)d.pop[p ^ 1];
+  NodeState n;
+  n.drho = drho;
+  n.rho = rho;
+  n.ux = ux;
+  n.uy = uy;
+  n.momx = div36(Mx);
+  n.momy = div36(My);
+  n.Px = Px;
+  n.Py = Py;
+  n.Qxx = rho * (Mxx - Phi * usx * usx);
+  n.Qxy = rho * (Mxy - Phi * usx * usy);
+  n.Qyy = rho * (Myy - Phi * usy * usy);
+  float out[kQ];
+  if (any_solid)
+    collide_node<true>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
+  else
+    collide_node<false>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
   const float sc = d.store_scale;
-  const int64_t o = r0 + xc;
+  if (valid) {
+    if (AM == kAddrBuf && TX >= 64) {
+      const __amdgpu_buffer_rsrc_t rd =
+          __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
+      const uint32_t s0 = __builtin_amdgcn_readfirstlane(o_r0);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const float cx = (float)CX[i], cy = (float)CY[i];
-    const float cu = cx * ux + cy * uy;
-    const float feq = KQ[i] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-    const float cG = cx * d.Gx + cy * d.Gy;
-    float src_i = 3.0f * (cG - uG) + 9.0f * cu * cG;
-    if (any_solid)
-      src_i += 3.0f * (cx * Px + cy * Py) +
-               4.5f * (cx * cx * Qxx + 2.0f * cx * cy * Qxy + cy * cy * Qyy) - 1.5f * trQ;
-    const float out = f[i] + om * (feq - f[i]) + kh * KQ[i] * src_i;
-    if (valid) ST::st(dst, i * plane + o, out, sc);
+      for (int i = 0; i < kQ; ++i) ST::stb(rd, o_x0, i * pb + s0, out[i], sc);
+    } else if (AM == kAddrBuf) {
+      const __amdgpu_buffer_rsrc_t rd =
+          __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
+      const uint32_t o = o_r0 + o_x0;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) ST::stb(rd, o, i * pb, out[i], sc);
+    } else if (AM == kAddrG32) {
+      const uint32_t o = o_r0 + o_x0;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) ST::sto(dst + i * plane, o, out[i], sc);
+    } else {
+      const int64_t o = (int64_t)yc * nx + xc;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) ST::st(dst, i * plane + o, out[i], sc);
+    }
   }
 }
 
-template <class ST, int TX, int TY>
-__global__ __launch_bounds__(kBlockThreads) void k_collide(const SolveDesc *__restrict__ descs,
+template <class ST, int TX, int TY, int AM>
+__global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(const SolveDesc *__restrict__ descs,
                                                            const int32_t *__restrict__ tile_solve,
                                                            const BatchHeader *__restrict__ hdr,
                                                            int k) {
@@ -419,8 +600,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_collide(const SolveDesc *__re
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep>(d, lt, p, sb, sidx, red, nullptr, nullptr, nullptr,
-                                        Region{0, 0, 0, 0});
+    process_tile<ST, TX, TY, kModeStep, AM>(d, lt, p, sb, sidx, red, nullptr, nullptr,
+                                            nullptr, Region{0, 0, 0, 0});
     __syncthreads();  // LDS reuse by the next tile
   }
 }
@@ -442,7 +623,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields>(d, lt, p, sb, sidx, red, rho, ux, uy, region);
+    process_tile<ST, TX, TY, kModeFields, kAddrWide>(d, lt, p, sb, sidx, red, rho, ux, uy,
+                                                     region);
     __syncthreads();
   }
 }
@@ -478,23 +660,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     const bool fixed = d.bconst[4 * nb + b] != 0.0;
     int q = p;
     if (!BIN_ONLY) {
-      // Eq. (28): repulsion from every other body of the solve (minimum image)
+      // Eq. (28): repulsion from every other body of the solve (minimum image); pairs
+      // farther apart than r_i + r_j + xi are rejected on the squared distance
       double fx = 0.0, fy = 0.0;
       const double xi = d.xi;
       for (int j = lane; j < nb; j += 64) {
-        if (j == b) continue;
         const double dx = min_image(X - st[j], dnx);
         const double dy = min_image(Y - st[nb + j], dny);
-        const double dist = sqrt(dx * dx + dy * dy);
+        const double d2 = dx * dx + dy * dy;
         const double rr = R + d.bconst[j];
-        double kk = 0.0;
-        if (dist > rr + xi) {
-          kk = 0.0;
-        } else if (dist <= rr) {
-          kk = (rr - dist) / d.eps_p1;
-        } else {
-          kk = (rr + xi - dist) * (rr + xi - dist) / d.eps_p;
-        }
+        if (j == b || d2 > (rr + xi) * (rr + xi)) continue;
+        const double dist = sqrt(d2);
+        const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
+                                     : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
         fx += kk * dx;
         fy += kk * dy;
       }
@@ -512,9 +690,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
         if (dist > 2.0 * R + xi) {
           kk = 0.0;
         } else if (dist <= 2.0 * R) {
-          kk = (2.0 * R - dist) / d.eps_w1;
+          kk = (2.0 * R - dist) * d.inv_eps_w1;
         } else {
-          kk = (2.0 * R + xi - dist) * (2.0 * R + xi - dist) / d.eps_w;
+          kk = (2.0 * R + xi - dist) * (2.0 * R + xi - dist) * d.inv_eps_w;
         }
         if (wall == 0)
           fy += kk * dd;
@@ -653,25 +831,46 @@ int grid_for(int64_t n, int block) {
 
 #define DILBM_SHAPES(X) X(0, 64, 4) X(1, 128, 2) X(2, 256, 1) X(3, 32, 8) X(4, 16, 16)
 
-hipError_t launch_collide(int shape, int storage, int grid, hipStream_t stream,
-                          const SolveDesc *descs, const int32_t *tile_solve,
-                          const BatchHeader *hdr, int k) {
-#define DILBM_CASE(id, tx, ty)                                                              \
-  case id:                                                                                  \
-    if (storage == 1)                                                                       \
-      hipLaunchKernelGGL((k_collide<StoreF16, tx, ty>), dim3(grid), dim3(kBlockThreads), 0, \
-                         stream, descs, tile_solve, hdr, k);                                \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_collide<StoreF32, tx, ty>), dim3(grid), dim3(kBlockThreads), 0, \
-                         stream, descs, tile_solve, hdr, k);                                \
-    break;
+using CollideKernel = void (*)(const SolveDesc *, const int32_t *, const BatchHeader *, int);
+
+// The k_collide instance for a tile shape, storage format and addressing mode.
+static CollideKernel collide_kernel(int shape, int storage, int addr) {
+#define DILBM_PICK(ST, tx, ty)                                  \
+  if (addr == kAddrBuf) return &k_collide<ST, tx, ty, kAddrBuf>; \
+  if (addr == kAddrG32) return &k_collide<ST, tx, ty, kAddrG32>; \
+  return &k_collide<ST, tx, ty, kAddrWide>;
+#define DILBM_CASE(id, tx, ty)   \
+  case id:                       \
+    if (storage == 1) {          \
+      DILBM_PICK(StoreF16, tx, ty) \
+    } else {                     \
+      DILBM_PICK(StoreF32, tx, ty) \
+    }
   switch (shape) {
     DILBM_SHAPES(DILBM_CASE)
     default:
-      return hipErrorInvalidValue;
+      return nullptr;
   }
 #undef DILBM_CASE
+#undef DILBM_PICK
+}
+
+hipError_t launch_collide(int shape, int storage, int addr, int grid, hipStream_t stream,
+                          const SolveDesc *descs, const int32_t *tile_solve,
+                          const BatchHeader *hdr, int k) {
+  const CollideKernel f = collide_kernel(shape, storage, addr);
+  if (!f) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(f, dim3(grid), dim3(kBlockThreads), 0, stream, descs, tile_solve, hdr, k);
   return hipGetLastError();
+}
+
+int collide_blocks_per_cu(int shape, int storage, int addr) {
+  const CollideKernel f = collide_kernel(shape, storage, addr);
+  int n = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f),
+                                                         kBlockThreads, 0) != hipSuccess)
+    return 0;
+  return n;
 }
 
 hipError_t launch_fields(int shape, int storage, int64_t ntiles, hipStream_t stream,

@@ -75,6 +75,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libdilbm.so not found at {LIB_PATH}; build it with "
                            "`python -m paper_2106_08950_amd.build` (no fallback exists)")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch first makes
+    # the library bind to that one runtime, so torch streams and device pointers are valid
+    # handles here; loaded the other way round a process would hold two runtimes and
+    # torch would find no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     V, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     P = C.POINTER(dilbm_params)

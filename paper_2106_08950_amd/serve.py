@@ -65,7 +65,8 @@ def serve(requests, arena_bytes: int, chunk: int = 64, graph_steps: int = 32, ti
     """Run a stream of (arrival_time_s, inputs.Workload) requests to completion.
 
     With ``realtime`` a request is only visible once its arrival time has passed on the
-    wall clock; otherwise all are available at once (arrival times still define latency).
+    wall clock, and latency runs from that time.  Otherwise the stream is an offline
+    batch: every request arrives at time zero and is admitted in list order.
     """
     import torch
 
@@ -77,7 +78,8 @@ def serve(requests, arena_bytes: int, chunk: int = 64, graph_steps: int = 32, ti
                       arena_ptr=arena.data_ptr())
     pool.set_launch(graph_steps, tile)
     stats = ServeStats()
-    pending = sorted(((t, i, wl) for i, (t, wl) in enumerate(requests)), key=lambda r: r[0])
+    pending = sorted(((t if realtime else 0.0, i, wl) for i, (t, wl) in enumerate(requests)),
+                     key=lambda r: (r[0], r[1]))
     running = {}   # ticket -> (index, arrival, admitted, workload)
     t0 = clock()
     nxt = 0

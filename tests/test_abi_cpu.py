@@ -87,3 +87,12 @@ def test_tile_shapes_cover_256_nodes():
     shapes = dilbm.tile_shapes()
     assert len(shapes) >= 3
     assert all(tx * ty == 256 for tx, ty in shapes)
+
+
+def test_one_hip_runtime_per_process():
+    """The library binds to the HIP runtime PyTorch already holds: a process that also
+    uses torch streams and tensors must not map a second copy of the runtime."""
+    dilbm.load()
+    with open("/proc/self/maps") as f:
+        paths = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    assert len(paths) == 1, paths
