@@ -3,8 +3,12 @@
 // Memory layout of one solve in HBM:
 //   pop[2]        two population buffers, structure of arrays [9][ny][nx] of shifted,
 //                 scaled populations g_i = 36 (f_i - w_i rho0) in FP32 (or FP16 times
-//                 2^k); the factor 36 makes the D2Q9 weights exact integers.  The pull
-//                 scheme keeps post-collision values: node x at time t_n finds f_i in
+//                 2^k); the factor 36 makes the D2Q9 weights exact integers.  What is
+//                 stored at step t is g_i - 3 K_i c_i.V_t (K_i = 36 w_i): the populations
+//                 seen from a reference frame moving with a small pseudo-random uniform
+//                 velocity V_t drawn afresh every step (see ref_velocity), which keeps
+//                 FP32/FP16 rounding from accumulating a bias.  The pull scheme keeps
+//                 post-collision values: node x at time t_n finds f_i in
 //                 pop[p][i][x - c_i].
 //   tile_count[2] per tile, number of bodies whose phi support may touch the tile
 //   tile_list[2]  per tile, `list_cap` body indices
@@ -37,7 +41,7 @@ constexpr int kMaxListCap = 1024;
 #endif
 // Persistent collide grid: this many times the blocks that are resident on one CU at once.
 #ifndef DILBM_GRID_MULT
-#define DILBM_GRID_MULT 1
+#define DILBM_GRID_MULT 8
 #endif
 
 enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
@@ -53,6 +57,7 @@ struct SolveDesc {
   int32_t list_cap;
   uint32_t wall_mask;
   // chunk control (rewritten by the host before every chunk)
+  int64_t step0;               // steps the solve has taken at the chunk start
   int32_t active_steps;        // step k of the chunk runs iff k < active_steps
   int32_t parity0;             // parity of the solve's state at the chunk start
   // FP32 node constants

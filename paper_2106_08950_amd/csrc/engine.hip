@@ -417,6 +417,7 @@ class Engine {
     HIPCHK(hipEventSynchronize(one_ev_[which]));
     SolveDesc *h = (SolveDesc *)h_one_ + which;
     *h = s.desc;
+    h->step0 = s.steps_done;
     h->parity0 = s.parity();
     h->active_steps = 1;
     // one-solve launches number tiles and bodies from 0, not from the solve's place in
@@ -484,6 +485,7 @@ class Engine {
     }
     for (Solve *s : members_) {
       const int64_t a = std::min<int64_t>(K, s->remaining());
+      s->desc.step0 = s->steps_done;
       s->desc.active_steps = (int32_t)a;
       s->desc.parity0 = s->parity();
       h[s->slot] = s->desc;
@@ -677,7 +679,8 @@ class Engine {
     // resident ones would run as a second, thinner wave)
     int &bpc = blocks_per_cu_[shape_][storage_][addr_];
     if (bpc == 0) bpc = std::max(1, collide_blocks_per_cu(shape_, storage_, addr_));
-    int64_t g = std::min<int64_t>(T, (int64_t)num_cu_ * bpc * DILBM_GRID_MULT);
+    int64_t g = DILBM_GRID_MULT > 0 ? std::min<int64_t>(T, (int64_t)num_cu_ * bpc * DILBM_GRID_MULT)
+                                    : T;
     g = std::min<int64_t>(g, (int64_t)1 << 30);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
@@ -833,8 +836,10 @@ void upload_bodies(Solve &s, hipStream_t st, const double *pos, const double *ve
   HIPCHK(hipStreamSynchronize(st));  // the host vectors die here
 }
 
-void init_populations(Solve &s, hipStream_t st) {
-  HIPCHK(launch_zero_bytes(s.pops.ptr, (int64_t)s.pops.bytes, st));
+// the fluid at rest (rho = rho0, u = 0) at the solve's current step
+void init_populations(Engine &eng, Solve &s, hipStream_t st) {
+  SolveDesc *dd = eng.one_desc(s, st, 0);
+  HIPCHK(launch_rest_pops(s.prm.storage, (int64_t)kQ * s.prm.nx * s.prm.ny, st, dd));
 }
 
 // copy a body-buffer range to the host (synchronous on st)
@@ -1059,7 +1064,7 @@ dilbm_status dilbm_create(const dilbm_params *p, dilbm_solver **out) {
     s.body = mem_alloc(nullptr, s.L.total);
     fill_desc(s);
     h->eng->add(&s);
-    init_populations(s, h->eng->stream());
+    init_populations(*h->eng, s, h->eng->stream());
     HIPCHK(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, h->eng->stream()));
     HIPCHK(hipStreamSynchronize(h->eng->stream()));
   });
@@ -1325,7 +1330,7 @@ dilbm_status dilbm_pool_submit(dilbm_pool *pool, const dilbm_params *prm, int32_
     hipStream_t st = eng.stream();
     eng.add(s.get());
     try {
-      init_populations(*s, st);
+      init_populations(eng, *s, st);
       HIPCHK(launch_zero_bytes(s->body.ptr, (int64_t)s->body.bytes, st));
       upload_bodies(*s, st, pos, vel, omega, radius, density, fixed);
       eng.bin_current(*s, st);

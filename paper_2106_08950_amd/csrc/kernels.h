@@ -23,6 +23,9 @@ hipError_t launch_set_pops(int storage, int64_t count, hipStream_t stream, const
                            int p, const double *fin);
 hipError_t launch_get_pops(int storage, int64_t count, hipStream_t stream, const SolveDesc *desc,
                            int p, double *fout);
+// every population of both buffers at the rest state of step desc->step0 (count = 9 nx ny)
+hipError_t launch_rest_pops(int storage, int64_t count, hipStream_t stream,
+                            const SolveDesc *desc);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_zero_bytes(void *p, int64_t bytes, hipStream_t stream);

@@ -47,6 +47,9 @@ constexpr int kBufferFlags = 0x00020000;
 
 struct StoreF32 {
   using T = float;
+  static constexpr bool kFrame = true;  // stored in the moving frame of ref_velocity
+  static constexpr int kRefLog2 = -17;  // |V_t| < 2^-17
+  static constexpr bool kStochastic = false;
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                               uint32_t soff, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
@@ -63,10 +66,29 @@ struct StoreF32 {
   static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float) {
     *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = v;
   }
+  static __device__ __forceinline__ float round_out(float v, float, uint32_t) { return v; }
 };
 
+// FP16 storage keeps 11 significant bits of g_i 2^k.  Rounded to nearest, a population
+// whose per-step change is under half an FP16 ulp never changes at all: a slowly
+// accelerating flow stalls.  The collide write-back therefore rounds stochastically:
+// random bits below the 10 kept mantissa bits are added to the FP32 pattern, which is
+// then truncated; the stored value rounds up with probability equal to its distance
+// from the lower neighbour in ulps, so it is right on average at every magnitude
+// (values that are already representable, zero included, are stored exactly).  Host
+// conversions in and out round to nearest.  FP16 needs no moving frame: its storage
+// rounding dwarfs the FP32 arithmetic drift the frame removes.
 struct StoreF16 {
   using T = _Float16;
+  static constexpr bool kFrame = false;
+  static constexpr int kRefLog2 = 0;
+  static constexpr bool kStochastic = true;
+  // v * scale rounded stochastically to a value FP16 holds exactly (normal range); r8
+  // is 8 random bits
+  static __device__ __forceinline__ float round_out(float v, float scale, uint32_t r8) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, v * scale);
+    return __builtin_bit_cast(float, (b + ((r8 << 5) | 0x10u)) & 0xFFFFE000u);
+  }
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                               uint32_t soff, float inv) {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
@@ -99,6 +121,66 @@ constexpr float kInv36 = 1.0f / 36.0f;
 __device__ __forceinline__ float div36(float x) {
   const float q = x * kInv36;
   return fmaf(fmaf(-36.0f, q, x), kInv36, q);
+}
+
+// Reference frame of the stored populations.  Step t has a uniform velocity V_t, and
+// what is stored is g_i - 3 K_i c_i.V_t.  The step computes the same update in that
+// frame: the equilibrium's linear term takes the momentum relative to V_t, the
+// second-order, forcing and solid terms the true velocity.  Only the rounding changes.
+// In a smooth, steadily driven flow a node gains nearly the same increment every step,
+// and rounding a fixed increment onto the FP32 (or FP16) grid of a slowly changing value
+// makes the same error every step: a drift that grows with the step count (about 6e-5
+// of the momentum after 1000 steps of uniform acceleration at tau = 0.6).  With V_t
+// pseudo-random those roundings see a different offset every step and average out.
+// V_t has 20 significant bits on the binary grid 2^(L-19), |V_t| < 2^L, so every frame
+// constant 3 K_i c_i.V_t, its changes and short sums of them are exact in FP32: a fluid
+// at rest stays exactly at rest.  V_t is the SplitMix64 finaliser (Steele, Lea and
+// Flood, OOPSLA 2014) of t, the solve's own step count: the same sequence whether a
+// solve runs alone or batched.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <int L>
+__device__ __forceinline__ float2 ref_velocity(int64_t t) {
+  const uint64_t z = splitmix64((uint64_t)t);
+  const int kx = (int)(z & 0xFFFFFu) - (1 << 19);
+  const int ky = (int)((z >> 20) & 0xFFFFFu) - (1 << 19);
+  constexpr float q = (float)(1.0 / (double)(1ull << (19 - L)));  // 2^(L-19)
+  return make_float2((float)kx * q, (float)ky * q);
+}
+
+template <class ST>
+__device__ __forceinline__ float2 frame_velocity(int64_t t) {
+  if constexpr (ST::kFrame)
+    return ref_velocity<ST::kRefLog2>(t);
+  else
+    return make_float2(0.0f, 0.0f);
+}
+
+// Counter-based 32-bit hash (Wellons' "lowbias32" integer finaliser) and one xorshift32
+// step (Marsaglia, 2003): random bits for stochastic rounding, keyed by node and step.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+// 3 K_i c_i.V: the frame offset of direction i
+__device__ __forceinline__ double frame_offset(int i, float2 V) {
+  return 3.0 * (double)KQ[i] * ((double)CX[i] * V.x + (double)CY[i] * V.y);
 }
 
 struct BodyLds {
@@ -173,7 +255,7 @@ enum AddrMode { kAddrBuf = 0, kAddrG32 = 1, kAddrWide = 2 };
 struct NodeState {
   float drho, rho;        // physical
   float ux, uy;           // corrected velocity, Eq. (17)
-  float momx, momy;       // rho u, physical, without constant bias
+  float momx, momy;       // rho u - V: momentum relative to the storage frame, physical
   float Px, Py;           // rho (A - Phi u*), physical
   float Qxx, Qxy, Qyy;    // rho (M - Phi u* u*), physical
 };
@@ -181,7 +263,7 @@ struct NodeState {
 // Eq. (13) for one node, over the four pairs of opposite directions (c_j = -c_i) so that
 // each pair shares its even part: the post-collision g_i is
 //   g_i + omega (geq_i - g_i) + khalf K_i S_i,
-//   geq_i = K_i [drho + 3 c.(rho u) + rho (4.5 (c.u)^2 - 1.5 u^2)],
+//   geq_i = K_i [drho + 3 c.(rho u - V) + rho (4.5 (c.u)^2 - 1.5 u^2)]   (frame V),
 //   S_i   = 3 (c - u).G + 9 (c.u)(c.G)                          (body-force forcing)
 //         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q   when the tile has solid (Eq. (15) summed).
 template <bool SOLID>
@@ -192,7 +274,9 @@ __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], c
   const float r45 = 4.5f * n.rho;
   float se0 = -3.0f * (n.ux * Gx + n.uy * Gy);
   if (SOLID) se0 = fmaf(-1.5f, n.Qxx + n.Qyy, se0);
-  out[0] = fmaf(kh * 16.0f, se0, fmaf(om, 16.0f * even0 - f[0], f[0]));
+  // each output is f + (small update): the update's own roundings are tiny, and the one
+  // rounding at the scale of f sees an addend that changes from step to step
+  out[0] = f[0] + fmaf(om, 16.0f * even0 - f[0], (kh * 16.0f) * se0);
   auto pair = [&](int i, int j, float K, float cu, float cm, float cG, float cP, float cQc) {
     const float E = fmaf(r45, cu * cu, even0);
     const float O = 3.0f * cm;
@@ -203,8 +287,8 @@ __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], c
       So = fmaf(3.0f, cP, So);
     }
     const float khK = kh * K;
-    out[i] = fmaf(khK, Se + So, fmaf(om, K * (E + O) - f[i], f[i]));
-    out[j] = fmaf(khK, Se - So, fmaf(om, K * (E - O) - f[j], f[j]));
+    out[i] = f[i] + fmaf(om, K * (E + O) - f[i], khK * (Se + So));
+    out[j] = f[j] + fmaf(om, K * (E - O) - f[j], khK * (Se - So));
   };
   // (1,0)/(-1,0), (0,1)/(0,-1), (1,1)/(-1,-1), (-1,1)/(1,-1)
   pair(1, 3, 4.0f, n.ux, n.momx, Gx, n.Px, n.Qxx);
@@ -240,7 +324,7 @@ __device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs,
 // One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
 template <class ST, int TX, int TY, int MODE, int AM>
 __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
-                                             BodyLds *sb, int32_t *sidx,
+                                             const int64_t t, BodyLds *sb, int32_t *sidx,
                                              double (*red)[kBlockThreads / 64][3],
                                              double *__restrict__ out_rho,
                                              double *__restrict__ out_ux,
@@ -346,8 +430,28 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
   }
 
+  // ---- storage frame: populations of step t are stored relative to V_t; a step moves
+  // them to the frame of step t + 1 (exact constants, one rounding per population)
+  const float2 Vt = frame_velocity<ST>(t);
+  float2 Vf = Vt;
+  if (MODE == kModeStep && ST::kFrame) {
+    Vf = frame_velocity<ST>(t + 1);
+    const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y;
+    const float a = 12.0f * dvx, b = 12.0f * dvy;                  // axis directions
+    const float c5 = 3.0f * (dvx + dvy), c6 = 3.0f * (dvy - dvx);  // diagonals
+    f[1] -= a;
+    f[3] += a;
+    f[2] -= b;
+    f[4] += b;
+    f[5] -= c5;
+    f[7] += c5;
+    f[6] -= c6;
+    f[8] += c6;
+  }
+  const float V36x = 36.0f * Vf.x, V36y = 36.0f * Vf.y;  // frame momentum, g units (exact)
+
   // ---- moments, Eqs. (5) and (16); u* carries half the fluid body force ----------------
-  // (in g units: D = 36 delta rho, J = 36 j, R = 36 rho)
+  // (in g units: D = 36 delta rho, J = 36 j - 36 V, R = 36 rho; the frame carries no mass)
   const float D = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float Jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const float Jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
@@ -359,8 +463,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   // 1/R: hardware reciprocal plus one Newton step (about half an ulp)
   float Rinv = __builtin_amdgcn_rcpf(R);
   Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
-  const float Jgx = Jx + 18.0f * d.Gx;  // 36 rho u* = 36 (j + G/2)
-  const float Jgy = Jy + 18.0f * d.Gy;
+  // 36 rho u* = 36 (j + G/2), back in the fixed frame
+  const float Jgx = Jx + (V36x + 18.0f * d.Gx);
+  const float Jgy = Jy + (V36y + 18.0f * d.Gy);
   const float usx = Jgx * Rinv;         // u*
   const float usy = Jgy * Rinv;
 
@@ -515,9 +620,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   // ---- corrected velocity, Eq. (17): u = u* + (sum_b w_b u_s,b - Phi u*) / 2 ----------
   // P = rho (A - Phi u*) is the momentum the node takes from the bodies; 36 rho u =
   // 36 rho u* + 18 P.  The equilibrium's momentum-carrying term is built from
-  // rho u = (36 rho u) / 36 directly: through u = (36 rho u) / R it would inherit the
-  // constant rounding error of 1/R (R is 36 to within 1e-5, a handful of float values),
-  // a momentum bias in every collision that compounds over the run.
+  // rho u - V = (36 rho u - 36 V) / 36 directly: through u = (36 rho u) / R it would
+  // inherit the constant rounding error of 1/R (R is 36 to within 1e-5, a handful of
+  // float values), a momentum bias in every collision that compounds over the run.
   const float Px = rho * (Ax - Phi * usx);
   const float Py = rho * (Ay - Phi * usy);
   const float Mx = fmaf(18.0f, Px, Jgx);
@@ -547,8 +652,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   n.rho = rho;
   n.ux = ux;
   n.uy = uy;
-  n.momx = div36(Mx);
-  n.momy = div36(My);
+  n.momx = div36(Mx - V36x);
+  n.momy = div36(My - V36y);
   n.Px = Px;
   n.Py = Py;
   n.Qxx = rho * (Mxx - Phi * usx * usx);
@@ -559,7 +664,20 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     collide_node<true>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
   else
     collide_node<false>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
-  const float sc = d.store_scale;
+  float sc = d.store_scale;
+  if constexpr (ST::kStochastic) {
+    // 8 random bits per population from one hash of (node, step) and two xorshifts
+    const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
+    const uint32_t h0 = lowbias32(((uint32_t)yc * (uint32_t)nx + (uint32_t)xc) ^ tk);
+    const uint32_t h1 = xorshift32(h0);
+    const uint32_t h2 = xorshift32(h1);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const uint32_t h = i < 4 ? h0 : (i < 8 ? h1 : h2);
+      out[i] = ST::round_out(out[i], sc, (h >> (8 * (i & 3))) & 0xFFu);
+    }
+    sc = 1.0f;  // already scaled
+  }
   if (valid) {
     if (AM == kAddrBuf && TX >= 64) {
       const __amdgpu_buffer_rsrc_t rd =
@@ -600,8 +718,8 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep, AM>(d, lt, p, sb, sidx, red, nullptr, nullptr,
-                                            nullptr, Region{0, 0, 0, 0});
+    process_tile<ST, TX, TY, kModeStep, AM>(d, lt, p, d.step0 + k, sb, sidx, red, nullptr,
+                                            nullptr, nullptr, Region{0, 0, 0, 0});
     __syncthreads();  // LDS reuse by the next tile
   }
 }
@@ -623,8 +741,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields, kAddrWide>(d, lt, p, sb, sidx, red, rho, ux, uy,
-                                                     region);
+    process_tile<ST, TX, TY, kModeFields, kAddrWide>(d, lt, p, d.step0, sb, sidx, red, rho,
+                                                     ux, uy, region);
     __syncthreads();
   }
 }
@@ -761,10 +879,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
 
 // Populations in: natural layout deviations f[9][ny][nx] (FP64) -> pull layout
 // pop[i][x - c_i] = f_i(x).
+// Populations in and out (deviations f_i - w_i rho0, FP64, layout [9][ny][nx]) at the
+// solve's current step d.step0, stored in that step's frame.
 template <class ST>
 __global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p, const double *__restrict__ fin) {
   const SolveDesc &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny;
+  const float2 V = frame_velocity<ST>(d.step0);
   typename ST::T *dst = (typename ST::T *)d.pop[p];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -776,7 +897,8 @@ __global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p, const doub
     if (xs >= d.nx) xs -= d.nx;
     if (ys < 0) ys += d.ny;
     if (ys >= d.ny) ys -= d.ny;
-    ST::st(dst, i * plane + (int64_t)ys * d.nx + xs, (float)(36.0 * fin[e]), d.store_scale);
+    ST::st(dst, i * plane + (int64_t)ys * d.nx + xs, (float)(36.0 * fin[e] - frame_offset(i, V)),
+           d.store_scale);
   }
 }
 
@@ -784,6 +906,7 @@ template <class ST>
 __global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__restrict__ fout) {
   const SolveDesc &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny;
+  const float2 V = frame_velocity<ST>(d.step0);
   const typename ST::T *src = (const typename ST::T *)d.pop[p];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -795,7 +918,24 @@ __global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__
     if (xs >= d.nx) xs -= d.nx;
     if (ys < 0) ys += d.ny;
     if (ys >= d.ny) ys -= d.ny;
-    fout[e] = (double)ST::ld(src, i * plane + (int64_t)ys * d.nx + xs, d.store_inv) / 36.0;
+    const double g = (double)ST::ld(src, i * plane + (int64_t)ys * d.nx + xs, d.store_inv);
+    fout[e] = (g + frame_offset(i, V)) / 36.0;
+  }
+}
+
+// The fluid at rest with rho = rho0 (every deviation zero) at step d.step0, in both
+// population buffers.
+template <class ST>
+__global__ void k_rest_pops(const SolveDesc *__restrict__ desc) {
+  const SolveDesc &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny;
+  const float2 V = frame_velocity<ST>(d.step0);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / plane);
+    const float v = (float)(-frame_offset(i, V));  // exact
+    ST::st((typename ST::T *)d.pop[0], e, v, d.store_scale);
+    ST::st((typename ST::T *)d.pop[1], e, v, d.store_scale);
   }
 }
 
@@ -923,6 +1063,16 @@ hipError_t launch_get_pops(int storage, int64_t count, hipStream_t stream, const
     hipLaunchKernelGGL((k_get_pops<StoreF16>), dim3(grid), dim3(256), 0, stream, desc, p, fout);
   else
     hipLaunchKernelGGL((k_get_pops<StoreF32>), dim3(grid), dim3(256), 0, stream, desc, p, fout);
+  return hipGetLastError();
+}
+
+hipError_t launch_rest_pops(int storage, int64_t count, hipStream_t stream,
+                            const SolveDesc *desc) {
+  const int grid = grid_for(count, 256);
+  if (storage == 1)
+    hipLaunchKernelGGL((k_rest_pops<StoreF16>), dim3(grid), dim3(256), 0, stream, desc);
+  else
+    hipLaunchKernelGGL((k_rest_pops<StoreF32>), dim3(grid), dim3(256), 0, stream, desc);
   return hipGetLastError();
 }
 
