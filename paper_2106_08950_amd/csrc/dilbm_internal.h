@@ -100,6 +100,8 @@ struct BatchHeader {
   int64_t total_tiles;
   int32_t total_bodies;
   int32_t nsolves;
+  int32_t solo_slot;           // descriptor slot of the only member, or -1
+  int32_t reserved;
 };
 
 }  // namespace dilbm

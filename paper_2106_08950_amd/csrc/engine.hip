@@ -448,6 +448,8 @@ class Engine {
     hh->total_tiles = 0;
     hh->total_bodies = s.nb;
     hh->nsolves = 1;
+    hh->solo_slot = 0;
+    hh->reserved = 0;
     HIPCHK(hipMemcpyAsync(d_one_hdr_, hh, sizeof(BatchHeader), hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(table_ev_, st));
     HIPCHK(launch_bodies(true, std::max(1, (s.nb + 3) / 4), st, dd, d_one_bodies_, d_one_hdr_, 0));
@@ -643,6 +645,8 @@ class Engine {
     hh.total_tiles = T;
     hh.total_bodies = (int32_t)B;
     hh.nsolves = (int32_t)members_.size();
+    hh.solo_slot = members_.size() == 1 ? members_[0]->slot : -1;
+    hh.reserved = 0;
     if (T) HIPCHK(hipMemcpyAsync(d_tile_solve_, h_tile_solve_, sizeof(int32_t) * T,
                                  hipMemcpyHostToDevice, stream_));
     if (B) HIPCHK(hipMemcpyAsync(d_body_solve_, h_body_solve_, sizeof(int32_t) * B,

@@ -41,6 +41,9 @@ constexpr float KQ[kQ] = {16.0f, 4.0f, 4.0f, 4.0f, 4.0f, 1.0f, 1.0f, 1.0f, 1.0f}
 // (uniform) plane base to the global address space and adding a 32-bit byte offset lets
 // each access be one global_load/global_store with a scalar base.
 #define DILBM_GLOBAL __attribute__((address_space(1)))
+// Constant address space: wave-uniform reads of data no kernel writes while it is read
+// compile to scalar loads.
+#define DILBM_CONST __attribute__((address_space(4)))
 
 // Buffer resource word 3 for raw 32-bit buffer access on gfx9-family parts.
 constexpr int kBufferFlags = 0x00020000;
@@ -226,21 +229,26 @@ __device__ __forceinline__ AxisTiles axis_tiles(double X, double H, int n, int t
   return {a0, ntiles - 1, 0, b1};
 }
 
-// XCD-contiguous split of [0, T): workgroup b runs on XCD b % 8; the blocks of one XCD
-// sweep one contiguous eighth of the tiles.
+// Static split of [0, T) into contiguous chunks: workgroup b runs on XCD b % 8 and sweeps
+// chunk b / 8 of that XCD's contiguous eighth.  The grid holds several times the blocks a
+// CU keeps resident: those resident at any moment cover a compact band of tiles (tiles
+// share L2 lines at their edges, so a band re-reads little), and blocks that finish early
+// make room for the next ones, which evens out tiles made slow by bodies.
 struct WorkSplit {
   int64_t begin, end;
-  int64_t stride;
 };
 
 __device__ __forceinline__ WorkSplit xcd_split(int64_t T) {
-  const int G = gridDim.x;  // a multiple of 8
+  const int64_t nblk = gridDim.x >> 3;  // blocks per XCD group (the grid is a multiple of 8)
   const int xcd = blockIdx.x & 7;
-  const int64_t q = T >> 3, r = T & 7;
+  const int64_t per = T >> 3, r = T & 7;
+  const int64_t lo = xcd * per + (xcd < r ? xcd : r);
+  const int64_t count = per + (xcd < r ? 1 : 0);
+  const int64_t chunk = (count + nblk - 1) / nblk;
+  const int64_t l = blockIdx.x >> 3;
   WorkSplit w;
-  w.begin = xcd * q + (xcd < r ? xcd : r) + (blockIdx.x >> 3);
-  w.end = xcd * q + (xcd < r ? xcd : r) + q + (xcd < r ? 1 : 0);
-  w.stride = G >> 3;
+  w.begin = lo + min(count, l * chunk);
+  w.end = lo + min(count, (l + 1) * chunk);
   return w;
 }
 
@@ -345,17 +353,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const int xc = min(x, nx - 1);  // clamped coordinates keep loads in bounds
   const int yc = min(y, ny - 1);
 
-  // an overflowed list (count > capacity) is flagged by the binning; read only what fits
-  const int nb = min(__builtin_amdgcn_readfirstlane(d.tile_count[p][lt]), d.list_cap);
-  if (MODE == kModeStep) {
-    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
-    if (lt == 0) {
-      double *a = d.acc[p ^ 1];
-      for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
-    }
-  }
-
   // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) --------------------------------
+  // (issued before anything else of the tile waits on memory: the population stream is
+  // what the kernel is bound by)
   using T = typename ST::T;
   const T *__restrict__ src = (const T *)d.pop[p];
   T *__restrict__ dst = (T *)d.pop[p ^ 1];
@@ -428,6 +428,17 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     f[6] = ST::ld(src, 6 * plane + rm + xp, inv);
     f[7] = ST::ld(src, 7 * plane + rp + xp, inv);
     f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
+  }
+
+  // the tile's body count (wave-uniform: a scalar load, in flight with the populations);
+  // an overflowed list (count > capacity) is flagged by the binning: read only what fits
+  const int nb = min(*(const DILBM_CONST int32_t *)(d.tile_count[p] + lt), d.list_cap);
+  if (MODE == kModeStep) {
+    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
+    if (lt == 0) {
+      double *a = d.acc[p ^ 1];
+      for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+    }
   }
 
   // ---- storage frame: populations of step t are stored relative to V_t; a step moves
@@ -712,8 +723,9 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
   __shared__ int32_t sidx[kBodyChunk];
   __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
   const WorkSplit ws = xcd_split(hdr->total_tiles);
-  for (int64_t t = ws.begin; t < ws.end; t += ws.stride) {
-    const int s = __builtin_amdgcn_readfirstlane(tile_solve[t]);
+  const int solo = hdr->solo_slot;  // one member: no per-tile lookup
+  for (int64_t t = ws.begin; t < ws.end; ++t) {
+    const int s = solo >= 0 ? solo : __builtin_amdgcn_readfirstlane(tile_solve[t]);
     const SolveDesc &d = descs[s];
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
@@ -758,8 +770,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
   const int lane = threadIdx.x & 63;
   const int wpb = kBlockThreads / 64;
   const int total = hdr->total_bodies;
+  const int solo = hdr->solo_slot;
   for (int g = blockIdx.x * wpb + (threadIdx.x >> 6); g < total; g += gridDim.x * wpb) {
-    const int s = __builtin_amdgcn_readfirstlane(body_solve[g]);
+    const int s = solo >= 0 ? solo : __builtin_amdgcn_readfirstlane(body_solve[g]);
     const SolveDesc &d = descs[s];
     if (!BIN_ONLY && k >= d.active_steps) continue;
     const int p = BIN_ONLY ? (d.parity0 & 1) : ((d.parity0 + k) & 1);
@@ -780,19 +793,34 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     if (!BIN_ONLY) {
       // Eq. (28): repulsion from every other body of the solve (minimum image); pairs
       // farther apart than r_i + r_j + xi are rejected on the squared distance
+      // (the other bodies are read kU rounds of 64 at a time: all loads of a batch are in
+      // flight together, so the loop pays one memory latency per batch, not per round)
       double fx = 0.0, fy = 0.0;
       const double xi = d.xi;
-      for (int j = lane; j < nb; j += 64) {
-        const double dx = min_image(X - st[j], dnx);
-        const double dy = min_image(Y - st[nb + j], dny);
-        const double d2 = dx * dx + dy * dy;
-        const double rr = R + d.bconst[j];
-        if (j == b || d2 > (rr + xi) * (rr + xi)) continue;
-        const double dist = sqrt(d2);
-        const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
-                                     : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
-        fx += kk * dx;
-        fy += kk * dy;
+      constexpr int kU = 8;
+      for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
+        double xs[kU], ys[kU], rs[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = min(j0 + 64 * u + lane, nb - 1);  // clamped: a valid index
+          xs[u] = st[j];
+          ys[u] = st[nb + j];
+          rs[u] = d.bconst[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = j0 + 64 * u + lane;
+          const double dx = min_image(X - xs[u], dnx);
+          const double dy = min_image(Y - ys[u], dny);
+          const double d2 = dx * dx + dy * dy;
+          const double rr = R + rs[u];
+          if (j >= nb || j == b || d2 > (rr + xi) * (rr + xi)) continue;
+          const double dist = sqrt(d2);
+          const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
+                                       : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
+          fx += kk * dx;
+          fy += kk * dy;
+        }
       }
       fx = wave_sum(fx);  // every lane now holds the totals
       fy = wave_sum(fy);
@@ -877,8 +905,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
   }
 }
 
-// Populations in: natural layout deviations f[9][ny][nx] (FP64) -> pull layout
-// pop[i][x - c_i] = f_i(x).
 // Populations in and out (deviations f_i - w_i rho0, FP64, layout [9][ny][nx]) at the
 // solve's current step d.step0, stored in that step's frame.
 template <class ST>
