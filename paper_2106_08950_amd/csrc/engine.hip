@@ -322,7 +322,8 @@ class Engine {
     HIPCHK(hipMalloc(&d_one_hdr_, sizeof(BatchHeader) * 2));
     HIPCHK(hipHostMalloc(&h_one_, sizeof(SolveDesc) * 2 + sizeof(BatchHeader) * 2));
     for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&one_ev_[i], hipEventDisableTiming));
-    for (int i = 0; i < kRing; ++i) HIPCHK(hipEventCreateWithFlags(&ring_ev_[i], hipEventDisableTiming));
+    for (int i = 0; i < kRing; ++i)
+      HIPCHK(hipEventCreateWithFlags(&ring_ev_[i], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&table_ev_, hipEventDisableTiming));
     HIPCHK(hipDeviceGetAttribute(&num_cu_, hipDeviceAttributeMultiprocessorCount, device));
   }
@@ -571,7 +572,8 @@ class Engine {
     HIPCHK(hipMalloc(&d, sizeof(int32_t) * cap));
     HIPCHK(launch_fill_i32(d, cap, 0, stream_));
     if (d_err_) {
-      HIPCHK(hipMemcpyAsync(d, d_err_, sizeof(int32_t) * err_cap_, hipMemcpyDeviceToDevice, stream_));
+      HIPCHK(hipMemcpyAsync(d, d_err_, sizeof(int32_t) * err_cap_, hipMemcpyDeviceToDevice,
+                            stream_));
       HIPCHK(hipStreamSynchronize(stream_));
       (void)hipFree(d_err_);
     }
@@ -666,7 +668,8 @@ class Engine {
       addr_ = addr;
       clear_graphs();
     }
-    const bool grid_change = collide_grid_for(T) != collide_grid_ || bodies_grid_for(B) != bodies_grid_;
+    const bool grid_change =
+        collide_grid_for(T) != collide_grid_ || bodies_grid_for(B) != bodies_grid_;
     total_tiles_ = T;
     total_bodies_ = (int)B;
     if (grid_change) {
@@ -809,7 +812,8 @@ void upload_bodies(Solve &s, hipStream_t st, const double *pos, const double *ve
   const int nb = s.nb;
   const int p = s.parity();
   // host arrays in the device SoA order
-  std::vector<double> state(5 * (size_t)std::max(nb, 1), 0.0), cst(5 * (size_t)std::max(nb, 1), 0.0);
+  std::vector<double> state(5 * (size_t)std::max(nb, 1), 0.0);
+  std::vector<double> cst(5 * (size_t)std::max(nb, 1), 0.0);
   const double nx = s.prm.nx, ny = s.prm.ny;
   for (int b = 0; b < nb; ++b) {
     double x = std::fmod(pos[2 * b], nx);

@@ -715,10 +715,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 }
 
 template <class ST, int TX, int TY, int AM>
-__global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(const SolveDesc *__restrict__ descs,
-                                                           const int32_t *__restrict__ tile_solve,
-                                                           const BatchHeader *__restrict__ hdr,
-                                                           int k) {
+__global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
+    const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
+    const BatchHeader *__restrict__ hdr, int k) {
   __shared__ BodyLds sb[kBodyChunk];
   __shared__ int32_t sidx[kBodyChunk];
   __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
@@ -791,13 +790,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     const bool fixed = d.bconst[4 * nb + b] != 0.0;
     int q = p;
     if (!BIN_ONLY) {
+      // hydrodynamic force and torque of the step (read now: in flight with the pair loads)
+      const double *acc = d.acc[p];
+      const double hfx = acc[3 * b], hfy = acc[3 * b + 1], T = acc[3 * b + 2];
       // Eq. (28): repulsion from every other body of the solve (minimum image); pairs
       // farther apart than r_i + r_j + xi are rejected on the squared distance
       // (the other bodies are read kU rounds of 64 at a time: all loads of a batch are in
       // flight together, so the loop pays one memory latency per batch, not per round)
       double fx = 0.0, fy = 0.0;
       const double xi = d.xi;
-      constexpr int kU = 8;
+      constexpr int kU = 16;
       for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
         double xs[kU], ys[kU], rs[kU];
 #pragma unroll
@@ -845,12 +847,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
         else
           fx += kk * dd;
       }
-      const double *acc = d.acc[p];
       // Eq. (22): hydrodynamic force plus (rho_f / rho_s - 1) m g, rho_f = rho0
       const double gfac = (d.rho0_d / rho_s - 1.0) * m;
-      fx += acc[3 * b] + gfac * d.gx;
-      fy += acc[3 * b + 1] + gfac * d.gy;
-      const double T = acc[3 * b + 2];
+      fx += hfx + gfac * d.gx;
+      fy += hfy + gfac * d.gy;
       if (fixed) {
         X += U;  // prescribed motion
         Y += V;
@@ -908,7 +908,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
 // Populations in and out (deviations f_i - w_i rho0, FP64, layout [9][ny][nx]) at the
 // solve's current step d.step0, stored in that step's frame.
 template <class ST>
-__global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p, const double *__restrict__ fin) {
+__global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p,
+                           const double *__restrict__ fin) {
   const SolveDesc &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny;
   const float2 V = frame_velocity<ST>(d.step0);

@@ -1,0 +1,32 @@
+"""bench.py host logic: the roofline's measured-traffic figure is reported only while the
+counter summary it comes from was taken on the current kernel source."""
+import importlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _bench():
+    return importlib.import_module("bench")
+
+
+def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    bench = _bench()
+    f = tmp_path / "counters.txt"
+    f.write_text(f"hbm_bytes_per_launch: 1234567\nkernel_source_sha256_16: {bench.kernel_source_hash()}\n")
+    monkeypatch.setattr(bench, "COUNTERS", str(f))
+    assert bench.measured_traffic() == 1234567.0
+    f.write_text("hbm_bytes_per_launch: 1234567\nkernel_source_sha256_16: 0000000000000000\n")
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic() is None
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
