@@ -71,6 +71,28 @@ def copy_calibration():
     print("copied 3 x 1 GiB (read 1 GiB + write 1 GiB per copy)", flush=True)
 
 
+def copy_reference(nbytes):
+    """A plain device-to-device copy of the population volume (nbytes read, nbytes
+    written), timed with events: the second denominator of the roofline."""
+    import torch
+
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    reps = 20
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def run_oracle_sample(wl, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
@@ -231,6 +253,9 @@ def main():
                      "traffic": measured_traffic(), "kernel": "k_collide", "bytes_per_node": 72,
                      "avg_launch_ms": round(avg_ms, 5), "launches": launches},
     }
+    cgbs = copy_reference(36 * wl.nodes)
+    out["roofline"]["copy_GBs"] = round(cgbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / cgbs, 4)
     if "fp16" in legs:
         log("fp16")
         m16, dt16, avg16, n16 = single_solve(wl, dilbm.STORE_FP16, args.steps, args.warmup,
