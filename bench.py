@@ -1,6 +1,7 @@
 """Benchmark of the DI-LBM time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs fp32,fp16,batched,served]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--legs fp32,fp16,open_ends,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -9,6 +10,8 @@ force 1e-6, FP32 shifted-population storage -- its 1.2 GB working set exceeds th
 Infinity Cache, so the populations stream from HBM every step.  Inputs are resident in
 HBM before the timed region starts.  Further legs, reported in the same JSON line:
 * fp16: the same workload with FP16 storage (36 B per node update);
+* open_ends: a 4096 x 2048 inflow channel (velocity inlet, zero-gradient outlet, 300
+  fixed discs), FP32;
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -204,7 +207,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--legs", default="fp32,fp16,batched,served")
+    ap.add_argument("--legs", default="fp32,fp16,open_ends,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--served-count", type=int, default=500)
@@ -267,6 +270,18 @@ def main():
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(a16 / HBM_PEAK_GBS, 4), "bytes_per_node": 36,
                                     "avg_launch_ms": round(avg16, 5)}}
+    if "open_ends" in legs:
+        log("open ends")
+        wo = inputs.inflow_array()
+        mo, dto, avgo, no = single_solve(wo, dilbm.STORE_FP32, args.steps // 2, args.warmup,
+                                         args.tile, stream)
+        ao = 72 * wo.nodes / (avgo * 1e-3) / 1e9
+        out["open_ends"] = {"workload": wo.name, "value": round(mo, 1), "unit": "MLUPS",
+                            "ms_per_step": round(dto * 1e3 / (args.steps // 2), 4),
+                            "roofline": {"bound": "hbm", "achieved": round(ao, 1),
+                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                         "frac": round(ao / HBM_PEAK_GBS, 4),
+                                         "bytes_per_node": 72, "avg_launch_ms": round(avgo, 5)}}
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

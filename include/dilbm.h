@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define DILBM_ABI_VERSION 1u
+#define DILBM_ABI_VERSION 2u
 
 typedef enum dilbm_status {
   DILBM_OK = 0,
@@ -68,6 +68,16 @@ enum { DILBM_STORE_FP32 = 0, DILBM_STORE_FP16 = 1 };
  * F_i as printed, which is (1 - 1/(2 tau)) times the former. */
 enum { DILBM_FORCE_MOMENTUM_EXCHANGE = 0, DILBM_FORCE_PAPER_LITERAL = 1 };
 enum { DILBM_WALL_Y = 1u, DILBM_WALL_X = 2u };
+/* Open ends in x: the boundary treatment the paper applies to its physical boundaries
+ * (Section 3), non-equilibrium extrapolation (Guo, Zheng & Shi 2002).  The inlet column
+ * x = 0 and the outlet column x = nx - 1 take, after each collision, f^eq of their
+ * boundary state plus (1 - 1/tau) times the non-equilibrium part of the neighbouring
+ * column (x = 1, x = nx - 2) at the same step; the neighbour's velocity includes half the
+ * body force, as in its own collision.  Boundary columns exert no force on bodies: keep
+ * bodies' supports off the two outermost columns on each side. */
+enum { DILBM_XBC_PERIODIC = 0, DILBM_XBC_INLET_OUTLET = 1 };
+enum { DILBM_INLET_VELOCITY = 0, DILBM_INLET_PRESSURE = 1 };
+enum { DILBM_OUTLET_PRESSURE = 0, DILBM_OUTLET_ZERO_GRADIENT = 1 };
 
 typedef struct dilbm_params {
   uint32_t abi_version;        /* must be DILBM_ABI_VERSION, else DILBM_EABI */
@@ -90,6 +100,18 @@ typedef struct dilbm_params {
   int32_t fp16_scale_log2;     /* FP16 storage keeps 36 (f - w rho0) * 2^k; k in [0, 24] */
   int32_t list_capacity;       /* bodies per tile list; 0 = min(n_bodies, 128) */
   int32_t tile;                /* tile shape id (dilbm_tile_shape); -1 = default */
+  int32_t x_boundary;          /* DILBM_XBC_*; INLET_OUTLET needs nx >= 3, no DILBM_WALL_X */
+  int32_t inlet_kind;          /* DILBM_INLET_*: VELOCITY prescribes inlet_velocity and
+                                  takes rho from the neighbour; PRESSURE prescribes
+                                  inlet_density and takes u from the neighbour */
+  int32_t inlet_profile;       /* velocity inlet: 0 uniform; 1 parabolic 4 s (1 - s) across
+                                  the channel (between the y wall slabs, else the full
+                                  height), peak inlet_velocity */
+  int32_t outlet_kind;         /* DILBM_OUTLET_*: PRESSURE prescribes outlet_density and
+                                  takes u from the neighbour; ZERO_GRADIENT takes both */
+  double inlet_velocity[2];
+  double inlet_density;        /* > 0 when used */
+  double outlet_density;       /* > 0 when used */
   int32_t device;              /* HIP device ordinal */
   void *stream;                /* hipStream_t to run on, or NULL for a library stream */
 } dilbm_params;

@@ -41,6 +41,9 @@ class _Params(C.Structure):
         ("eps_p", C.c_double), ("eps_p1", C.c_double), ("eps_w", C.c_double),
         ("eps_w1", C.c_double), ("xi", C.c_double),
         ("bb_walls_y", C.c_int32),
+        ("x_boundary", C.c_int32), ("inlet_kind", C.c_int32), ("inlet_profile", C.c_int32),
+        ("outlet_kind", C.c_int32), ("u_in", C.c_double * 2),
+        ("rho_in", C.c_double), ("rho_out", C.c_double),
     ]
 
 
@@ -63,6 +66,9 @@ def _L():
                                          C.c_double, C.c_double, C.c_int32, _dp, _dp, _dp, _dp,
                                          _dp]
         lib.ora_collide_node.restype = C.c_int32
+        lib.ora_nee_node.argtypes = [C.c_double, C.c_double, _dp, C.c_double, C.c_double,
+                                     C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double,
+                                     _dp, _dp, _dp]
         lib.ora_pp_force.argtypes = [C.c_double] * 7 + [_dp]
         lib.ora_pw_force.argtypes = [C.c_double] * 6 + [_dp]
         lib.ora_body_update.argtypes = [C.c_double] * 5 + [_dp] * 5
@@ -158,6 +164,21 @@ def collide_node(tau, rho0, f_dev, phis=(), us=(), G=(0.0, 0.0), force_mode=0):
     return int(st), fp, float(rho[0]), u, ust, fb[: 2 * nb].reshape(nb, 2)
 
 
+def nee_node(tau, rho0, f_nb_dev, G=(0.0, 0.0), rho_set=None, u_set=None):
+    """Non-equilibrium extrapolation at one boundary node from its neighbour's populations:
+    rho_set / u_set prescribe the boundary state, None takes the neighbour's.
+    Returns (f*_b deviations, rho_b, u_b)."""
+    fn = _f64(f_nb_dev)
+    out = np.zeros(9)
+    rb = C.c_double()
+    ub = np.zeros(2)
+    ux, uy = (0.0, 0.0) if u_set is None else u_set
+    _L().ora_nee_node(tau, rho0, _ptr(fn), G[0], G[1], int(rho_set is None),
+                      0.0 if rho_set is None else float(rho_set), int(u_set is None), ux, uy,
+                      _ptr(out), C.byref(rb), _ptr(ub))
+    return out, rb.value, ub
+
+
 def pp_force(d, ri, rj, xi, eps_p, eps_p1):
     out = np.zeros(2)
     _L().ora_pp_force(d[0], d[1], ri, rj, xi, eps_p, eps_p1, _ptr(out))
@@ -197,6 +218,13 @@ class OracleParams:
     eps_w1: float = 0.5e4
     xi: float = 1.0
     bb_walls_y: int = 0
+    x_boundary: int = 0        # 1: inlet column x = 0, outlet column x = nx - 1
+    inlet_kind: int = 0        # 0 velocity, 1 pressure
+    inlet_profile: int = 0     # 0 uniform, 1 parabolic across the channel
+    outlet_kind: int = 0       # 0 pressure, 1 zero gradient
+    u_in: tuple = (0.0, 0.0)
+    rho_in: float = 1.0
+    rho_out: float = 1.0
 
     def _c(self):
         p = _Params()
@@ -210,6 +238,10 @@ class OracleParams:
         p.eps_p, p.eps_p1, p.eps_w, p.eps_w1, p.xi = (self.eps_p, self.eps_p1, self.eps_w,
                                                       self.eps_w1, self.xi)
         p.bb_walls_y = int(self.bb_walls_y)
+        p.x_boundary, p.inlet_kind = int(self.x_boundary), int(self.inlet_kind)
+        p.inlet_profile, p.outlet_kind = int(self.inlet_profile), int(self.outlet_kind)
+        p.u_in[0], p.u_in[1] = self.u_in
+        p.rho_in, p.rho_out = self.rho_in, self.rho_out
         return p
 
 

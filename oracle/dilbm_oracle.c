@@ -193,6 +193,46 @@ int32_t ora_collide_node(double tau, double rho0, const double *f_dev, int32_t n
   return bad ? ORA_EUNSTABLE : ORA_OK;
 }
 
+/* Non-equilibrium extrapolation (Guo, Zheng & Shi 2002), the boundary treatment the paper
+ * applies to its physical boundaries (Section 3): the boundary node takes the equilibrium
+ * of its boundary state plus the neighbour's non-equilibrium part, relaxed as in Eq. (13). */
+void ora_nee_node(double tau, double rho0, const double *f_nb_dev, double Gx, double Gy,
+                  int32_t rho_from_nb, double rho_set, int32_t u_from_nb, double ux_set,
+                  double uy_set, double *fpost_dev, double *rho_b, double *u_b) {
+  double f[Q];
+  for (int i = 0; i < Q; ++i) f[i] = f_nb_dev[i] + WT[i] * rho0;
+  double rho = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    jx += CX[i] * f[i];
+    jy += CY[i] * f[i];
+  }
+  const double ux = (jx + 0.5 * Gx) / rho, uy = (jy + 0.5 * Gy) / rho;
+  const double rb = rho_from_nb ? rho : rho_set;
+  const double uxb = u_from_nb ? ux : ux_set, uyb = u_from_nb ? uy : uy_set;
+  double feq_nb[Q], feq_b[Q];
+  ora_feq(rho, ux, uy, feq_nb);
+  ora_feq(rb, uxb, uyb, feq_b);
+  for (int i = 0; i < Q; ++i)
+    fpost_dev[i] = feq_b[i] + (1.0 - 1.0 / tau) * (f[i] - feq_nb[i]) - WT[i] * rho0;
+  if (rho_b) *rho_b = rb;
+  if (u_b) {
+    u_b[0] = uxb;
+    u_b[1] = uyb;
+  }
+}
+
+double ora_inlet_shape(const ora_params *p, int32_t j) {
+  if (!p->inlet_profile) return 1.0;
+  double y0 = 0.0, y1 = (double)p->ny;
+  if ((p->wall_mask & 1u) && !p->bb_walls_y) {  /* slab across the y seam: |y - seam| < h */
+    y0 = p->wall_h;
+    y1 = (double)p->ny - p->wall_h;
+  }
+  const double sv = ((double)j + 0.5 - y0) / (y1 - y0);
+  return (sv > 0.0 && sv < 1.0) ? 4.0 * sv * (1.0 - sv) : 0.0;
+}
+
 /* Eq. (28): repulsion on body i from body j; (dx, dy) = X_i - X_j, d = |X_i - X_j|. */
 void ora_pp_force(double dx, double dy, double ri, double rj, double xi, double eps_p,
                   double eps_p1, double *F) {
@@ -406,6 +446,15 @@ static int valid_params(const ora_params *p) {
   if (p->wall_mask & ~3u) return 0;
   if (p->wall_mask && !(p->wall_h > 0.0)) return 0;
   if (p->force_mode != 0 && p->force_mode != 1) return 0;
+  if (p->x_boundary != 0 && p->x_boundary != 1) return 0;
+  if (p->x_boundary) {
+    if (p->nx < 3 || (p->wall_mask & 2u)) return 0;
+    if ((p->inlet_kind != 0 && p->inlet_kind != 1) || (p->outlet_kind != 0 && p->outlet_kind != 1))
+      return 0;
+    if (p->inlet_profile != 0 && p->inlet_profile != 1) return 0;
+    if (p->inlet_kind == 1 && !(p->rho_in > 0.0)) return 0;
+    if (p->outlet_kind == 0 && !(p->rho_out > 0.0)) return 0;
+  }
   return 1;
 }
 
@@ -534,6 +583,33 @@ static int node_pass(ora_solver *s, double *fout, double *rho_o, double *ux_o, d
       int st = ora_collide_node(p->tau, p->rho0, fd, nb, nb ? s->e_phi + e0 : NULL,
                                 nb ? s->e_usx + e0 : NULL, nb ? s->e_usy + e0 : NULL, p->G[0],
                                 p->G[1], p->force_mode, fp, &rho, u, NULL, eF);
+      if (p->x_boundary && (i == 0 || i == nx - 1)) {
+        /* inlet / outlet column: its post-collision state comes from the neighbour */
+        const int32_t in = (i == 0);
+        const int64_t nbn = (int64_t)j * nx + (in ? 1 : nx - 2);
+        double fnb[Q];
+        for (int q = 0; q < Q; ++q) fnb[q] = s->f[q * n + nbn];
+        int32_t rho_nb, u_nb;
+        double rset, uxs = 0.0, uys = 0.0;
+        if (in) {
+          rho_nb = p->inlet_kind == 0;
+          u_nb = p->inlet_kind == 1;
+          rset = p->rho_in;
+          const double sh = ora_inlet_shape(p, j);
+          uxs = sh * p->u_in[0];
+          uys = sh * p->u_in[1];
+        } else {
+          rho_nb = p->outlet_kind == 1;
+          u_nb = 1;
+          rset = p->rho_out;
+        }
+        ora_nee_node(p->tau, p->rho0, fnb, p->G[0], p->G[1], rho_nb, rset, u_nb, uxs, uys, fp,
+                     &rho, u);
+        for (int64_t e = 0; e < 2 * (int64_t)nb; ++e) eF[e] = 0.0;  /* no body force here */
+        st = (rho > 0.0 && u[0] * u[0] + u[1] * u[1] <= 0.25) ? ORA_OK : ORA_EUNSTABLE;
+        for (int q = 0; q < Q; ++q)
+          if (!isfinite(fp[q])) st = ORA_EUNSTABLE;
+      }
       if (st != ORA_OK) bad = 1;
       if (rho_o) rho_o[node] = rho;
       if (ux_o) ux_o[node] = u[0];

@@ -36,6 +36,17 @@ typedef struct ora_params {
   int32_t force_mode;      /* 0: momentum-exchange scale; 1: Eq. (18) taken literally */
   double eps_p, eps_p1, eps_w, eps_w1, xi;   /* Eqs. (28)-(29): eps_P, eps_P', eps_W, eps_W', xi */
   int32_t bb_walls_y;      /* test-only: halfway bounce-back walls at y = 0 and y = ny */
+  /* open ends in x: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) replaces the
+   * post-collision populations of the inlet column x = 0 and the outlet column x = nx-1 */
+  int32_t x_boundary;      /* 0: periodic in x; 1: inlet and outlet columns */
+  int32_t inlet_kind;      /* 0: velocity (u_in prescribed, rho from the neighbour);
+                              1: pressure (rho_in prescribed, u from the neighbour) */
+  int32_t inlet_profile;   /* velocity inlet: 0 uniform u_in; 1 parabolic across the
+                              channel between the y walls, peak u_in */
+  int32_t outlet_kind;     /* 0: pressure (rho_out prescribed, u from the neighbour);
+                              1: zero gradient (rho and u from the neighbour) */
+  double u_in[2];
+  double rho_in, rho_out;
 } ora_params;
 
 typedef struct ora_solver ora_solver;
@@ -51,6 +62,16 @@ int32_t ora_collide_node(double tau, double rho0, const double *f_dev, int32_t n
                          const double *phi_b, const double *usx, const double *usy,
                          double Gx, double Gy, int32_t force_mode, double *fpost_dev,
                          double *rho_out, double *u_out, double *ustar_out, double *force_b);
+/* Non-equilibrium extrapolation at one boundary node: f*_b = f^eq(rho_b, u_b) +
+ * (1 - 1/tau) (f_nb - f^eq(rho_nb, u_nb)), where f_nb are the neighbour's populations
+ * (deviations) and rho_nb, u_nb its moments (u with half the body force).  rho_b is
+ * rho_set (rho_from_nb = 0) or rho_nb; u_b is u_set (u_from_nb = 0) or u_nb. */
+void   ora_nee_node(double tau, double rho0, const double *f_nb_dev, double Gx, double Gy,
+                    int32_t rho_from_nb, double rho_set, int32_t u_from_nb, double ux_set,
+                    double uy_set, double *fpost_dev, double *rho_b, double *u_b);
+/* prescribed inlet velocity (x component scale) at row j: 1 for a uniform inlet,
+ * 4 s (1 - s) across the channel for a parabolic one */
+double ora_inlet_shape(const ora_params *p, int32_t j);
 void   ora_pp_force(double dx, double dy, double ri, double rj,
                     double xi, double eps_p, double eps_p1, double *F);
 void   ora_pw_force(double dx, double dy, double r,

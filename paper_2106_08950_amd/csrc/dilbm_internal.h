@@ -72,6 +72,11 @@ struct SolveDesc {
   int32_t wall_y_lo, wall_y_hi;  // rows outside [lo, hi) are within a y-wall's support
   int32_t wall_x_lo, wall_x_hi;
   float kappa;                 // force scale of Eqs. (18)-(19)
+  // open ends in x (non-equilibrium extrapolation at the columns x = 0 and x = nx - 1)
+  int32_t xbc, inlet_kind, inlet_profile, outlet_kind;
+  float u_in_x, u_in_y;        // prescribed inlet velocity (peak of a parabolic profile)
+  float rho36_in, rho36_out;   // 36 x prescribed inlet / outlet density
+  float prof_y0, prof_inv_h;   // parabolic profile: s = (y + 1/2 - prof_y0) * prof_inv_h
   float store_scale, store_inv;
   int32_t storage;
   // FP64 body constants

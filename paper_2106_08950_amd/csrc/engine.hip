@@ -168,6 +168,24 @@ void validate(const dilbm_params *p) {
   if (p->list_capacity < 0 || p->list_capacity > kMaxListCap)
     fail(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
   if (p->tile < -1 || p->tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
+  if (p->x_boundary != DILBM_XBC_PERIODIC && p->x_boundary != DILBM_XBC_INLET_OUTLET)
+    fail(DILBM_EINVAL, "unknown x_boundary");
+  if (p->x_boundary == DILBM_XBC_INLET_OUTLET) {
+    if (p->nx < 3) fail(DILBM_EINVAL, "an inlet and an outlet need nx >= 3");
+    if (p->wall_mask & DILBM_WALL_X) fail(DILBM_EINVAL, "x_boundary excludes DILBM_WALL_X");
+    if (p->inlet_kind != DILBM_INLET_VELOCITY && p->inlet_kind != DILBM_INLET_PRESSURE)
+      fail(DILBM_EINVAL, "unknown inlet_kind");
+    if (p->outlet_kind != DILBM_OUTLET_PRESSURE && p->outlet_kind != DILBM_OUTLET_ZERO_GRADIENT)
+      fail(DILBM_EINVAL, "unknown outlet_kind");
+    if (p->inlet_profile != 0 && p->inlet_profile != 1) fail(DILBM_EINVAL, "unknown inlet_profile");
+    if (!fin(p->inlet_velocity[0]) || !fin(p->inlet_velocity[1]))
+      fail(DILBM_EINVAL, "inlet_velocity must be finite");
+    if (p->inlet_kind == DILBM_INLET_PRESSURE && !(p->inlet_density > 0.0 && fin(p->inlet_density)))
+      fail(DILBM_EINVAL, "inlet_density must be > 0");
+    if (p->outlet_kind == DILBM_OUTLET_PRESSURE &&
+        !(p->outlet_density > 0.0 && fin(p->outlet_density)))
+      fail(DILBM_EINVAL, "outlet_density must be > 0");
+  }
 }
 
 void validate_bodies(int32_t n, const double *pos, const double *vel, const double *omega,
@@ -271,6 +289,22 @@ void fill_desc(Solve &s) {
     d.wall_x_hi = std::max(p.nx - lo, 0);
   }
   d.kappa = p.force_mode == DILBM_FORCE_PAPER_LITERAL ? (float)(1.0 - 0.5 / p.tau) : 1.0f;
+  d.xbc = p.x_boundary;
+  d.inlet_kind = p.inlet_kind;
+  d.inlet_profile = p.inlet_profile;
+  d.outlet_kind = p.outlet_kind;
+  d.u_in_x = (float)p.inlet_velocity[0];
+  d.u_in_y = (float)p.inlet_velocity[1];
+  d.rho36_in = (float)(36.0 * p.inlet_density);
+  d.rho36_out = (float)(36.0 * p.outlet_density);
+  {
+    // parabolic inlet: s = (y + 1/2 - y0) / (y1 - y0) across the fluid between the y wall
+    // slabs (or the full height)
+    const double y0 = (p.wall_mask & DILBM_WALL_Y) ? p.wall_half_thickness : 0.0;
+    const double y1 = (p.wall_mask & DILBM_WALL_Y) ? p.ny - p.wall_half_thickness : (double)p.ny;
+    d.prof_y0 = (float)y0;
+    d.prof_inv_h = (float)(1.0 / (y1 - y0));
+  }
   d.storage = p.storage;
   const double sc = p.storage == DILBM_STORE_FP16 ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
   d.store_scale = (float)sc;
@@ -668,6 +702,12 @@ class Engine {
       addr_ = addr;
       clear_graphs();
     }
+    bool open = false;
+    for (Solve *s : members_) open = open || s->prm.x_boundary != DILBM_XBC_PERIODIC;
+    if (open != open_) {
+      open_ = open;
+      clear_graphs();
+    }
     const bool grid_change =
         collide_grid_for(T) != collide_grid_ || bodies_grid_for(B) != bodies_grid_;
     total_tiles_ = T;
@@ -684,8 +724,8 @@ class Engine {
     // a persistent grid sweeps the tiles, sized to the blocks that are resident at once
     // (per-block set-up is paid once per block, not once per tile; blocks beyond the
     // resident ones would run as a second, thinner wave)
-    int &bpc = blocks_per_cu_[shape_][storage_][addr_];
-    if (bpc == 0) bpc = std::max(1, collide_blocks_per_cu(shape_, storage_, addr_));
+    int &bpc = blocks_per_cu_[shape_][storage_][addr_][open_ ? 1 : 0];
+    if (bpc == 0) bpc = std::max(1, collide_blocks_per_cu(shape_, storage_, addr_, open_));
     int64_t g = DILBM_GRID_MULT > 0 ? std::min<int64_t>(T, (int64_t)num_cu_ * bpc * DILBM_GRID_MULT)
                                     : T;
     g = std::min<int64_t>(g, (int64_t)1 << 30);
@@ -709,7 +749,7 @@ class Engine {
         }
         HIPCHK(hipEventRecord(timing_ev_[timing_used_].first, stream_));
       }
-      HIPCHK(launch_collide(shape_, storage_, addr_, collide_grid_, stream_, d_descs_,
+      HIPCHK(launch_collide(shape_, storage_, addr_, open_, collide_grid_, stream_, d_descs_,
                             d_tile_solve_, d_hdr_, k));
       if (timed) {
         HIPCHK(hipEventRecord(timing_ev_[timing_used_].second, stream_));
@@ -760,7 +800,8 @@ class Engine {
   int graph_steps_ = 32;
   bool persistent_ = false;
   int addr_ = 0;
-  int blocks_per_cu_[kNumTileShapes][2][3] = {};
+  int blocks_per_cu_[kNumTileShapes][2][3][2] = {};
+  bool open_ = false;  // some member has open ends in x
   std::vector<Solve *> members_;
   std::vector<bool> slot_used_;
   bool dirty_ = true;
@@ -1029,6 +1070,12 @@ void dilbm_params_init(dilbm_params *p) {
   p->fp16_scale_log2 = 10;
   p->list_capacity = 0;
   p->tile = -1;
+  p->x_boundary = DILBM_XBC_PERIODIC;
+  p->inlet_kind = DILBM_INLET_VELOCITY;
+  p->inlet_profile = 0;
+  p->outlet_kind = DILBM_OUTLET_PRESSURE;
+  p->inlet_density = 1.0;
+  p->outlet_density = 1.0;
   p->device = 0;
   p->stream = nullptr;
 }

@@ -8,12 +8,13 @@
 namespace dilbm {
 
 // addr: 0 = one buffer resource per population buffer (buffer under 4 GB), 1 = 32-bit
-// offsets from a plane base (plane under 2 GB), 2 = 64-bit addresses
-hipError_t launch_collide(int shape, int storage, int addr, int grid, hipStream_t stream,
-                          const SolveDesc *descs, const int32_t *tile_solve,
+// offsets from a plane base (plane under 2 GB), 2 = 64-bit addresses; open: some member has
+// open ends in x (the instance with the inlet / outlet columns)
+hipError_t launch_collide(int shape, int storage, int addr, bool open, int grid,
+                          hipStream_t stream, const SolveDesc *descs, const int32_t *tile_solve,
                           const BatchHeader *hdr, int k);
 // blocks of the collide instance resident on one CU at once (0 on error)
-int collide_blocks_per_cu(int shape, int storage, int addr);
+int collide_blocks_per_cu(int shape, int storage, int addr, bool open);
 hipError_t launch_fields(int shape, int storage, int64_t ntiles, hipStream_t stream,
                          const SolveDesc *desc, int p, Region region, double *rho, double *ux,
                          double *uy);

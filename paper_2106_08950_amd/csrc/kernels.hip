@@ -329,8 +329,99 @@ __device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs,
   sb->r = (float)d.bconst[b];
 }
 
+// Change of storage frame V_t -> V_{t+1} of one node's populations: g_i -= 3 K_i c_i.dV
+// (axis directions 12 dV, diagonals 3 (dVx +- dVy); exact constants).
+struct FrameShift {
+  float a, b, c5, c6;
+  __device__ __forceinline__ void apply(float g[kQ]) const {
+    g[1] -= a;
+    g[3] += a;
+    g[2] -= b;
+    g[4] += b;
+    g[5] -= c5;
+    g[7] += c5;
+    g[6] -= c6;
+    g[8] += c6;
+  }
+};
+
+// 36 (f^eq_i - w_i rho0) in the storage frame V for density R/36 and velocity u, with
+// mom = rho u - V given separately (physical units).
+__device__ __forceinline__ void geq_frame(float R, float rho36, float ux, float uy, float momx,
+                                          float momy, float geq[kQ]) {
+  const float rho = R * kInv36;
+  const float drho = (R - rho36) * kInv36;
+  const float even0 = fmaf(-1.5f * rho, ux * ux + uy * uy, drho);
+  const float r45 = 4.5f * rho;
+  geq[0] = 16.0f * even0;
+#pragma unroll
+  for (int i = 1; i < kQ; ++i) {
+    const float cu = (float)CX[i] * ux + (float)CY[i] * uy;
+    const float cm = (float)CX[i] * momx + (float)CY[i] * momy;
+    geq[i] = KQ[i] * (fmaf(r45, cu * cu, even0) + 3.0f * cm);
+  }
+}
+
+// Non-equilibrium extrapolation (Guo, Zheng & Shi 2002), the paper's treatment of its
+// physical boundaries (Section 3), at an inlet (x = 0) or outlet (x = nx - 1) node:
+// f*_b = f^eq(rho_b, u_b) + (1 - 1/tau) (f_nb - f^eq(rho_nb, u_nb)), from the populations
+// the neighbouring column pulls at this step.  u_nb carries half the body force, as in the
+// neighbour's own collision; the storage frame cancels in the non-equilibrium part.
+template <class ST>
+__device__ void nee_node(const SolveDesc &d, const typename ST::T *src, int64_t plane, int x,
+                         int y, const FrameShift &fs, float V36x, float V36y, float out[kQ],
+                         float &rho_b, float &uxb, float &uyb) {
+  const int nx = d.nx, ny = d.ny;
+  const bool inlet = x == 0;
+  const int xn = inlet ? 1 : nx - 2;  // the neighbour; its pulls stay inside [0, nx)
+  float g[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    int ys = y - CY[i];
+    ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+    g[i] = ST::ld(src, i * plane + (int64_t)ys * nx + (xn - CX[i]), d.store_inv);
+  }
+  fs.apply(g);
+  const float D = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const float Jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+  const float Jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+  const float R = d.rho36 + D;
+  const float Jgx = Jx + (V36x + 18.0f * d.Gx), Jgy = Jy + (V36y + 18.0f * d.Gy);
+  const float ux = Jgx / R, uy = Jgy / R;
+  const float momx = div36(Jgx - V36x), momy = div36(Jgy - V36y);
+  float Rb = R;
+  float bx = ux, by = uy;
+  if (inlet) {
+    if (d.inlet_kind == 0) {  // velocity inlet
+      float sh = 1.0f;
+      if (d.inlet_profile) {
+        const float sv = ((float)y + 0.5f - d.prof_y0) * d.prof_inv_h;
+        sh = (sv > 0.0f && sv < 1.0f) ? 4.0f * sv * (1.0f - sv) : 0.0f;
+      }
+      bx = sh * d.u_in_x;
+      by = sh * d.u_in_y;
+    } else {
+      Rb = d.rho36_in;
+    }
+  } else if (d.outlet_kind == 0) {
+    Rb = d.rho36_out;
+  }
+  const bool same = Rb == R && bx == ux && by == uy;
+  const float mbx = same ? momx : div36(fmaf(Rb, bx, -V36x));
+  const float mby = same ? momy : div36(fmaf(Rb, by, -V36y));
+  float eb[kQ], en[kQ];
+  geq_frame(Rb, d.rho36, bx, by, mbx, mby, eb);
+  geq_frame(R, d.rho36, ux, uy, momx, momy, en);
+  const float keep = 1.0f - d.omega;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) out[i] = fmaf(keep, g[i] - en[i], eb[i]);
+  rho_b = Rb * kInv36;
+  uxb = bx;
+  uyb = by;
+}
+
 // One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
-template <class ST, int TX, int TY, int MODE, int AM>
+template <class ST, int TX, int TY, int MODE, int AM, bool OPEN>
 __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
                                              const int64_t t, BodyLds *sb, int32_t *sidx,
                                              double (*red)[kBlockThreads / 64][3],
@@ -350,6 +441,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   // a wave covers part of one row when the tile is at least 64 wide: its row is uniform
   const int y = TX >= 64 ? __builtin_amdgcn_readfirstlane(y0 + tid / TX) : y0 + tid / TX;
   const bool valid = (x < nx) && (y < ny);
+  // an inlet / outlet node (open ends in x): its state comes from its neighbour
+  const bool bnd = OPEN && d.xbc && valid && (x == 0 || x == nx - 1);
   const int xc = min(x, nx - 1);  // clamped coordinates keep loads in bounds
   const int yc = min(y, ny - 1);
 
@@ -445,19 +538,12 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   // them to the frame of step t + 1 (exact constants, one rounding per population)
   const float2 Vt = frame_velocity<ST>(t);
   float2 Vf = Vt;
+  FrameShift fs{0.0f, 0.0f, 0.0f, 0.0f};
   if (MODE == kModeStep && ST::kFrame) {
     Vf = frame_velocity<ST>(t + 1);
     const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y;
-    const float a = 12.0f * dvx, b = 12.0f * dvy;                  // axis directions
-    const float c5 = 3.0f * (dvx + dvy), c6 = 3.0f * (dvy - dvx);  // diagonals
-    f[1] -= a;
-    f[3] += a;
-    f[2] -= b;
-    f[4] += b;
-    f[5] -= c5;
-    f[7] += c5;
-    f[6] -= c6;
-    f[8] += c6;
+    fs = FrameShift{12.0f * dvx, 12.0f * dvy, 3.0f * (dvx + dvy), 3.0f * (dvy - dvx)};
+    fs.apply(f);
   }
   const float V36x = 36.0f * Vf.x, V36y = 36.0f * Vf.y;  // frame momentum, g units (exact)
 
@@ -546,7 +632,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         const float ry = (float)min_image(ynode - sb[j].y, dny);
         const float l = sb[j].r - sqrtf(rx * rx + ry * ry);
         float fx = 0.f, fy = 0.f, tq = 0.f;
-        if (valid && l >= lcut) {
+        if (valid && !bnd && l >= lcut) {
           const float w = scale * phi_of(l, phik);
           // rigid-body solid velocity U + omega x r
           const float ux_s = sb[j].u - sb[j].w * ry;
@@ -593,13 +679,13 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     // wall slabs: solid velocity 0; their force goes to the last accumulator slot
     if (wy || wx) {
       float fx = 0.f, fy = 0.f;
-      if (valid && wy && lwy >= lcut) {
+      if (valid && !bnd && wy && lwy >= lcut) {
         const float w = scale * phi_of(lwy, phik);
         Phi += w;
         fx += kap * w * rho * usx;
         fy += kap * w * rho * usy;
       }
-      if (valid && wx && lwx >= lcut) {
+      if (valid && !bnd && wx && lwx >= lcut) {
         const float w = scale * phi_of(lwx, phik);
         Phi += w;
         fx += kap * w * rho * usx;
@@ -640,22 +726,28 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float My = fmaf(18.0f, Py, Jgy);
   const float ux = Mx * Rinv;
   const float uy = My * Rinv;
+  // an inlet / outlet node in this wave (periodic instances compile all of it away)
+  const bool any_bnd = OPEN && d.xbc && __ballot(bnd) != 0;
 
   if (MODE == kModeFields) {
+    float rho_r = rho, uxr = ux, uyr = uy;
+    if constexpr (OPEN) {
+      if (any_bnd && bnd) {
+        float tmp[kQ];
+        nee_node<ST>(d, src, plane, x, y, fs, V36x, V36y, tmp, rho_r, uxr, uyr);
+      }
+    }
     // out_* cover the region [rx0, rx0 + rw) x [ry0, ry0 + rh), row stride rw
     const int ox = x - region.x, oy = y - region.y;
     if (valid && ox >= 0 && ox < region.w && oy >= 0 && oy < region.h) {
       const int64_t o = (int64_t)oy * region.w + ox;
-      out_rho[o] = (double)rho;
-      out_ux[o] = (double)ux;
-      out_uy[o] = (double)uy;
+      out_rho[o] = (double)rho_r;
+      out_ux[o] = (double)uxr;
+      out_uy[o] = (double)uyr;
     }
     return;
   }
 
-  const float usq = ux * ux + uy * uy;
-  if (__ballot(valid && !(rho > 0.0f && usq <= 0.25f)) != 0 && lane == 0)
-    atomicOr(d.err, (int32_t)kErrUnstable);
 
   // ---- collision, Eq. (13), in g units ----------------------------------------------
   NodeState n;
@@ -675,6 +767,15 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     collide_node<true>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
   else
     collide_node<false>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
+  // inlet / outlet nodes replace the result (after the collision: no registers held
+  // across it for the few boundary lanes)
+  float rho_r = rho, uxr = ux, uyr = uy;
+  if constexpr (OPEN) {
+    if (any_bnd && bnd) nee_node<ST>(d, src, plane, x, y, fs, V36x, V36y, out, rho_r, uxr, uyr);
+  }
+  const float usq = uxr * uxr + uyr * uyr;
+  if (__ballot(valid && !(rho_r > 0.0f && usq <= 0.25f)) != 0 && lane == 0)
+    atomicOr(d.err, (int32_t)kErrUnstable);
   float sc = d.store_scale;
   if constexpr (ST::kStochastic) {
     // 8 random bits per population from one hash of (node, step) and two xorshifts
@@ -714,7 +815,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   }
 }
 
-template <class ST, int TX, int TY, int AM>
+template <class ST, int TX, int TY, int AM, bool OPEN>
 __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
@@ -729,8 +830,8 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep, AM>(d, lt, p, d.step0 + k, sb, sidx, red, nullptr,
-                                            nullptr, nullptr, Region{0, 0, 0, 0});
+    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, sb, sidx, red,
+                                                  nullptr, nullptr, nullptr, Region{0, 0, 0, 0});
     __syncthreads();  // LDS reuse by the next tile
   }
 }
@@ -752,7 +853,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields, kAddrWide>(d, lt, p, d.step0, sb, sidx, red, rho,
+    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, sb, sidx, red, rho,
                                                      ux, uy, region);
     __syncthreads();
   }
@@ -1000,17 +1101,20 @@ int grid_for(int64_t n, int block) {
 
 using CollideKernel = void (*)(const SolveDesc *, const int32_t *, const BatchHeader *, int);
 
-// The k_collide instance for a tile shape, storage format and addressing mode.
-static CollideKernel collide_kernel(int shape, int storage, int addr) {
-#define DILBM_PICK(ST, tx, ty)                                  \
-  if (addr == kAddrBuf) return &k_collide<ST, tx, ty, kAddrBuf>; \
-  if (addr == kAddrG32) return &k_collide<ST, tx, ty, kAddrG32>; \
-  return &k_collide<ST, tx, ty, kAddrWide>;
-#define DILBM_CASE(id, tx, ty)   \
-  case id:                       \
-    if (storage == 1) {          \
+// The k_collide instance for a tile shape, storage format, addressing mode and whether
+// any member has open ends in x.
+static CollideKernel collide_kernel(int shape, int storage, int addr, bool open) {
+#define DILBM_PICK2(ST, tx, ty, A)                             \
+  return open ? &k_collide<ST, tx, ty, A, true> : &k_collide<ST, tx, ty, A, false>;
+#define DILBM_PICK(ST, tx, ty)                           \
+  if (addr == kAddrBuf) { DILBM_PICK2(ST, tx, ty, kAddrBuf) } \
+  if (addr == kAddrG32) { DILBM_PICK2(ST, tx, ty, kAddrG32) } \
+  DILBM_PICK2(ST, tx, ty, kAddrWide)
+#define DILBM_CASE(id, tx, ty)     \
+  case id:                         \
+    if (storage == 1) {            \
       DILBM_PICK(StoreF16, tx, ty) \
-    } else {                     \
+    } else {                       \
       DILBM_PICK(StoreF32, tx, ty) \
     }
   switch (shape) {
@@ -1020,19 +1124,20 @@ static CollideKernel collide_kernel(int shape, int storage, int addr) {
   }
 #undef DILBM_CASE
 #undef DILBM_PICK
+#undef DILBM_PICK2
 }
 
-hipError_t launch_collide(int shape, int storage, int addr, int grid, hipStream_t stream,
-                          const SolveDesc *descs, const int32_t *tile_solve,
+hipError_t launch_collide(int shape, int storage, int addr, bool open, int grid,
+                          hipStream_t stream, const SolveDesc *descs, const int32_t *tile_solve,
                           const BatchHeader *hdr, int k) {
-  const CollideKernel f = collide_kernel(shape, storage, addr);
+  const CollideKernel f = collide_kernel(shape, storage, addr, open);
   if (!f) return hipErrorInvalidValue;
   hipLaunchKernelGGL(f, dim3(grid), dim3(kBlockThreads), 0, stream, descs, tile_solve, hdr, k);
   return hipGetLastError();
 }
 
-int collide_blocks_per_cu(int shape, int storage, int addr) {
-  const CollideKernel f = collide_kernel(shape, storage, addr);
+int collide_blocks_per_cu(int shape, int storage, int addr, bool open) {
+  const CollideKernel f = collide_kernel(shape, storage, addr, open);
   int n = 0;
   if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(f),
                                                          kBlockThreads, 0) != hipSuccess)

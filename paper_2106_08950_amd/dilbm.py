@@ -22,7 +22,10 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTAB
 STORE_FP32, STORE_FP16 = 0, 1
 FORCE_MOMENTUM_EXCHANGE, FORCE_PAPER_LITERAL = 0, 1
 WALL_Y, WALL_X = 1, 2
-ABI_VERSION = 1
+XBC_PERIODIC, XBC_INLET_OUTLET = 0, 1
+INLET_VELOCITY, INLET_PRESSURE = 0, 1
+OUTLET_PRESSURE, OUTLET_ZERO_GRADIENT = 0, 1
+ABI_VERSION = 2
 
 EXPORTED = [
     "dilbm_params_init", "dilbm_num_tile_shapes", "dilbm_tile_shape", "dilbm_footprint",
@@ -53,6 +56,9 @@ class dilbm_params(C.Structure):
         ("coll_xi", C.c_double),
         ("storage", C.c_int32), ("fp16_scale_log2", C.c_int32),
         ("list_capacity", C.c_int32), ("tile", C.c_int32),
+        ("x_boundary", C.c_int32), ("inlet_kind", C.c_int32), ("inlet_profile", C.c_int32),
+        ("outlet_kind", C.c_int32), ("inlet_velocity", C.c_double * 2),
+        ("inlet_density", C.c_double), ("outlet_density", C.c_double),
         ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -164,6 +170,13 @@ class Params:
     fp16_scale_log2: int = 10
     list_capacity: int = 0
     tile: int = -1
+    x_boundary: int = XBC_PERIODIC
+    inlet_kind: int = INLET_VELOCITY
+    inlet_profile: int = 0
+    outlet_kind: int = OUTLET_PRESSURE
+    inlet_velocity: tuple = (0.0, 0.0)
+    inlet_density: float = 1.0
+    outlet_density: float = 1.0
     device: int = 0
     stream: int = 0
 
@@ -174,7 +187,7 @@ class Params:
             if name == "abi_version":
                 continue
             v = getattr(self, name)
-            if name in ("body_force", "gravity"):
+            if name in ("body_force", "gravity", "inlet_velocity"):
                 getattr(p, name)[0], getattr(p, name)[1] = float(v[0]), float(v[1])
             elif name == "stream":
                 p.stream = C.c_void_p(int(v)) if v else None
@@ -189,7 +202,10 @@ def params_from_workload(wl, **overrides) -> Params:
              phi_cutoff=wl.cutoff, body_force=tuple(wl.G), gravity=tuple(wl.g),
              wall_mask=wl.wall_mask, wall_half_thickness=wl.wall_h, force_mode=wl.force_mode,
              coll_eps_p=wl.eps_p, coll_eps_p_overlap=wl.eps_p1, coll_eps_w=wl.eps_w,
-             coll_eps_w_overlap=wl.eps_w1, coll_xi=wl.xi)
+             coll_eps_w_overlap=wl.eps_w1, coll_xi=wl.xi, x_boundary=wl.x_boundary,
+             inlet_kind=wl.inlet_kind, inlet_profile=wl.inlet_profile,
+             outlet_kind=wl.outlet_kind, inlet_velocity=tuple(wl.u_in),
+             inlet_density=wl.rho_in, outlet_density=wl.rho_out)
     d.update(overrides)
     return Params(**d)
 

@@ -15,6 +15,9 @@ Workloads (lattice units; node (i, j) sits at (i + 0.5, j + 0.5)):
   Section 3.2.
 * ``dense_suspension``   -- 4096x4096 periodic, 2000 discs R = 8 placed by rejection
   sampling (seed 3), density ratio 1.2, G = (1e-6, 0), tau = 0.6, 5000 steps.
+* ``inflow_array``       -- 4096x2048 channel open in x: uniform velocity inlet u = 0.05
+  at x = 0, zero-gradient outlet, periodic across, 300 fixed discs R = 8 (seed 6) kept 64
+  nodes clear of both ends, tau = 0.6.  The Section 3.1 set-up at benchmark size.
 * ``ensemble``           -- 256 independent periodic solves (seed 4): nx log-uniform in
   [128, 1024], ny log-uniform in [128, 512], 1-32 discs with R uniform in [4, 16], tau
   uniform in [0.55, 1.5], G_x uniform in [1e-7, 1e-5], 2000 steps each.
@@ -61,6 +64,13 @@ class Workload:
     eps_w: float = 0.5e4
     eps_w1: float = 0.5e4
     xi: float = 1.0
+    x_boundary: int = 0        # 1: inlet column x = 0, outlet column x = nx - 1
+    inlet_kind: int = 0        # 0 velocity, 1 pressure
+    inlet_profile: int = 0     # 0 uniform, 1 parabolic across the channel
+    outlet_kind: int = 0       # 0 pressure, 1 zero gradient
+    u_in: tuple = (0.0, 0.0)
+    rho_in: float = 1.0
+    rho_out: float = 1.0
     pos: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
     vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
     omega: np.ndarray = field(default_factory=lambda: np.zeros(0))
@@ -148,6 +158,20 @@ def dense_suspension(n=4096, count=2000, seed=3) -> Workload:
     return Workload(name=f"dense_suspension_{n}x{n}_{len(rad)}discs", nx=n, ny=n, tau=0.6,
                     nsteps=5000, eps=2.0, G=(1.0e-6, 0.0),
                     **_bodies(pos, rad, np.full(len(rad), 1.2)))
+
+
+def inflow_array(nx=4096, ny=2048, count=300, seed=6) -> Workload:
+    """A uniform stream (u = 0.05) entering at the inlet column through an array of fixed
+    discs (R = 8, kept 64 nodes clear of both ends) and leaving through a zero-gradient
+    outlet, periodic across: the Section 3.1 set-up at benchmark size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos, rad = place_discs(rng, nx - 128, ny, count, lambda r: 8.0)
+    pos = pos + np.array([64.0, 0.0])
+    return Workload(name=f"inflow_array_{nx}x{ny}_{len(rad)}discs", nx=nx, ny=ny, tau=0.6,
+                    nsteps=2000, eps=2.0, x_boundary=1, inlet_kind=0, outlet_kind=1,
+                    u_in=(0.05, 0.0),
+                    **_bodies(pos, rad, np.full(len(rad), 1.0),
+                              fixed=np.ones(len(rad), np.uint8)))
 
 
 def _log_uniform_int(rng, lo, hi):

@@ -8,7 +8,9 @@ def oracle_solver(wl, **kw):
     d = dict(nx=wl.nx, ny=wl.ny, tau=wl.tau, rho0=wl.rho0, eps=wl.eps, cutoff=wl.cutoff,
              G=tuple(wl.G), g=tuple(wl.g), wall_mask=wl.wall_mask, wall_h=wl.wall_h,
              force_mode=wl.force_mode, eps_p=wl.eps_p, eps_p1=wl.eps_p1, eps_w=wl.eps_w,
-             eps_w1=wl.eps_w1, xi=wl.xi)
+             eps_w1=wl.eps_w1, xi=wl.xi, x_boundary=wl.x_boundary, inlet_kind=wl.inlet_kind,
+             inlet_profile=wl.inlet_profile, outlet_kind=wl.outlet_kind, u_in=tuple(wl.u_in),
+             rho_in=wl.rho_in, rho_out=wl.rho_out)
     d.update(kw)
     s = oracle.OracleSolver(oracle.OracleParams(**d))
     if wl.nbodies:

@@ -96,3 +96,23 @@ def test_one_hip_runtime_per_process():
     with open("/proc/self/maps") as f:
         paths = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
     assert len(paths) == 1, paths
+
+
+@pytest.mark.parametrize("bad", [
+    dict(x_boundary=2),
+    dict(x_boundary=1, nx=2),
+    dict(x_boundary=1, wall_mask=2),
+    dict(x_boundary=1, inlet_kind=2),
+    dict(x_boundary=1, outlet_kind=3),
+    dict(x_boundary=1, inlet_profile=2),
+    dict(x_boundary=1, inlet_kind=1, inlet_density=0.0),
+    dict(x_boundary=1, outlet_kind=0, outlet_density=-1.0),
+    dict(x_boundary=1, inlet_velocity=(float("nan"), 0.0)),
+])
+def test_create_rejects_bad_open_ends_before_device(bad):
+    base = dict(nx=32, ny=16)
+    base.update(bad)
+    p = dilbm.Params(**base)
+    h = C.c_void_p()
+    st = dilbm.load().dilbm_create(C.byref(p.to_c()), C.byref(h))
+    assert st == dilbm.EINVAL and not h.value

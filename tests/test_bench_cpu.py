@@ -15,7 +15,8 @@ def _bench():
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     bench = _bench()
     f = tmp_path / "counters.txt"
-    f.write_text(f"hbm_bytes_per_launch: 1234567\nkernel_source_sha256_16: {bench.kernel_source_hash()}\n")
+    h = bench.kernel_source_hash()
+    f.write_text(f"hbm_bytes_per_launch: 1234567\nkernel_source_sha256_16: {h}\n")
     monkeypatch.setattr(bench, "COUNTERS", str(f))
     assert bench.measured_traffic() == 1234567.0
     f.write_text("hbm_bytes_per_launch: 1234567\nkernel_source_sha256_16: 0000000000000000\n")
