@@ -14,6 +14,9 @@
 //   tile_list[2]  per tile, `list_cap` body indices
 //   bstate[2]     body state SoA [5][nb]: x, y, ux, uy, omega (FP64)
 //   bconst        body constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
+//   bsnap[2]      per body, what the collide kernel reads of it (BodySnap, 32 B): written
+//                 with every body update, so that a tile reads one listed body in one
+//                 dependent load
 //   acc[2]        FP64 force accumulators [(nb + 1) * 3]: Fx, Fy, T per body, then the
 //                 wall force in the last slot
 //   err           sticky error bits
@@ -30,7 +33,6 @@ constexpr int kNumTileShapes = 5;
 constexpr int kTileTX[kNumTileShapes] = {64, 128, 256, 32, 16};
 constexpr int kTileTY[kNumTileShapes] = {4, 2, 1, 8, 16};
 constexpr int kBlockThreads = 256;       // every tile shape has 256 nodes
-constexpr int kBodyChunk = 64;           // bodies staged in LDS at a time
 constexpr int kMaxListCap = 1024;
 
 // Register budget of the collide kernel: it is compiled for at least this many waves per
@@ -45,6 +47,13 @@ constexpr int kMaxListCap = 1024;
 #endif
 
 enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
+
+// One body as the collide kernel sees it at a step: position (FP64, so that node - centre
+// differences keep FP64 accuracy before they are rounded), rigid velocity, spin and radius.
+struct BodySnap {
+  double x, y;
+  float u, v, w, r;
+};
 
 struct SolveDesc {
   // geometry and tiling
@@ -91,6 +100,7 @@ struct SolveDesc {
   int32_t *tile_list[2];
   double *bstate[2];
   const double *bconst;
+  BodySnap *bsnap[2];
   double *acc[2];
   int32_t *err;
 };

@@ -207,7 +207,7 @@ void validate_bodies(int32_t n, const double *pos, const double *vel, const doub
 
 struct BodyLayout {
   int cap = 1;
-  uint64_t counts = 0, lists = 0, bstate = 0, bconst = 0, acc = 0, total = 0;
+  uint64_t counts = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, acc = 0, total = 0;
 };
 
 BodyLayout body_layout(const dilbm_params &p, int nb) {
@@ -223,6 +223,8 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   o += align_up(2 * 5 * (uint64_t)std::max(nb, 1) * 8);
   L.bconst = o;
   o += align_up(5 * (uint64_t)std::max(nb, 1) * 8);
+  L.bsnap = o;
+  o += align_up(2 * (uint64_t)std::max(nb, 1) * sizeof(BodySnap));
   L.acc = o;
   o += align_up(2 * 3 * (uint64_t)(nb + 1) * 8);
   L.total = o;
@@ -333,6 +335,8 @@ void fill_desc(Solve &s) {
   d.bstate[0] = (double *)(bb + s.L.bstate);
   d.bstate[1] = d.bstate[0] + 5 * nbs;
   d.bconst = (const double *)(bb + s.L.bconst);
+  d.bsnap[0] = (BodySnap *)(bb + s.L.bsnap);
+  d.bsnap[1] = d.bsnap[0] + nbs;
   d.acc[0] = (double *)(bb + s.L.acc);
   d.acc[1] = d.acc[0] + 3 * (uint64_t)(s.nb + 1);
 }

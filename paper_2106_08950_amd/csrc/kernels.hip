@@ -186,10 +186,11 @@ __device__ __forceinline__ double frame_offset(int i, float2 V) {
   return 3.0 * (double)KQ[i] * ((double)CX[i] * V.x + (double)CY[i] * V.y);
 }
 
-struct BodyLds {
-  double x, y;
-  float u, v, w, r;
-};
+// A body snapshot through the constant address space (scalar loads: the index is
+// wave-uniform and no kernel writes snapshots while the collide kernel reads them).
+__device__ __forceinline__ BodySnap load_snap(const DILBM_CONST BodySnap *q) {
+  return BodySnap{q->x, q->y, q->u, q->v, q->w, q->r};
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -309,26 +310,6 @@ __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], c
 
 // Copy one listed body into LDS.  An index outside [0, nb) (never written by the binning)
 // is flagged and staged as a body with no support, so it touches no memory and no node.
-__device__ __forceinline__ void stage_body(const SolveDesc &d, const double *bs, int nbs, int b,
-                                           BodyLds *sb, int32_t *sidx) {
-  if (b < 0 || b >= nbs) {
-    atomicOr(d.err, (int32_t)kErrInternal);
-    *sidx = 0;
-    sb->x = 0.0;
-    sb->y = 0.0;
-    sb->u = sb->v = sb->w = 0.f;
-    sb->r = -INFINITY;
-    return;
-  }
-  *sidx = b;
-  sb->x = bs[b];
-  sb->y = bs[nbs + b];
-  sb->u = (float)bs[2 * nbs + b];
-  sb->v = (float)bs[3 * nbs + b];
-  sb->w = (float)bs[4 * nbs + b];
-  sb->r = (float)d.bconst[b];
-}
-
 // Change of storage frame V_t -> V_{t+1} of one node's populations: g_i -= 3 K_i c_i.dV
 // (axis directions 12 dV, diagonals 3 (dVx +- dVy); exact constants).
 struct FrameShift {
@@ -423,15 +404,12 @@ __device__ void nee_node(const SolveDesc &d, const typename ST::T *src, int64_t 
 // One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
 template <class ST, int TX, int TY, int MODE, int AM, bool OPEN>
 __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
-                                             const int64_t t, BodyLds *sb, int32_t *sidx,
-                                             double (*red)[kBlockThreads / 64][3],
+                                             const int64_t t,
                                              double *__restrict__ out_rho,
                                              double *__restrict__ out_ux,
                                              double *__restrict__ out_uy,
                                              const Region region) {
-  constexpr int NW = kBlockThreads / 64;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
   const int lane = tid & 63;
   const int nx = d.nx, ny = d.ny;
   const int tyi = lt / d.tiles_x;
@@ -523,9 +501,22 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
   }
 
-  // the tile's body count (wave-uniform: a scalar load, in flight with the populations);
-  // an overflowed list (count > capacity) is flagged by the binning: read only what fits
+  // the tile's body count, its first listed body and that body's snapshot (wave-uniform
+  // scalar loads, in flight with the populations).  The first entry is read before the
+  // count is known: it is clamped into range for the snapshot load and used only when the
+  // count lists it.  An overflowed list (count > capacity) is flagged by the binning:
+  // read only what fits.
   const int nb = min(*(const DILBM_CONST int32_t *)(d.tile_count[p] + lt), d.list_cap);
+  const int nbs = d.nbodies;
+  const DILBM_CONST int32_t *list =
+      (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
+  const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
+  int e0 = -1;
+  BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
+  if (nbs > 0) {
+    e0 = list[0];
+    s0 = load_snap(snap + min(max(e0, 0), nbs - 1));
+  }
   if (MODE == kModeStep) {
     if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
     if (lt == 0) {
@@ -571,7 +562,6 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float lcut = d.lcut;
   const float phik = d.phi_k;
   const float h = d.wall_h;
-  const float cut = -lcut;
   // walls: static slabs across the seams; does this tile reach into one's support?
   // (rows [0, wall_lo) and [wall_hi, n) hold the nodes within h + cutoff of a seam)
   const bool wy = (d.wall_mask & 1u) && (y0 < d.wall_y_lo || y0 + TY > d.wall_y_hi);
@@ -591,11 +581,21 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
       lwx = h - fabsf(dx);
     }
     const int nsolid = nb + (wy ? 1 : 0) + (wx ? 1 : 0);
-    const int32_t *list = d.tile_list[p] + (int64_t)lt * d.list_cap;
-    const double *bs = d.bstate[p];
-    const int nbs = d.nbodies;
     const double xnode = (double)xc + 0.5, ynode = (double)yc + 0.5;
     const double dnx = (double)nx, dny = (double)ny;
+    // listed body j: its index (checked: a bad entry is flagged and skipped) and snapshot
+    auto body = [&](const int j, int &e, BodySnap &sj) -> bool {
+      e = j == 0 ? e0 : list[j];
+      if (e < 0 || e >= nbs) {
+        if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
+        return false;
+      }
+      if (j == 0)
+        sj = s0;
+      else
+        sj = load_snap(snap + e);
+      return true;
+    };
     float scale = 1.0f;
 
     // pass 1 (only where several supports meet): S = sum phi_b, w_b = phi_b min(1, 1/S)
@@ -603,75 +603,54 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
       float S = 0.f;
       if (wy && lwy >= lcut) S += phi_of(lwy, phik);
       if (wx && lwx >= lcut) S += phi_of(lwx, phik);
-      for (int c0 = 0; c0 < nb; c0 += kBodyChunk) {
-        const int cn = min(kBodyChunk, nb - c0);
-        __syncthreads();
-        if (tid < cn) stage_body(d, bs, nbs, list[c0 + tid], sb + tid, sidx + tid);
-        __syncthreads();
-        for (int j = 0; j < cn; ++j) {
-          const float rx = (float)min_image(xnode - sb[j].x, dnx);
-          const float ry = (float)min_image(ynode - sb[j].y, dny);
-          const float l = sb[j].r - sqrtf(rx * rx + ry * ry);
-          if (l >= lcut) S += phi_of(l, phik);
-        }
+      for (int j = 0; j < nb; ++j) {
+        int e;
+        BodySnap sj;
+        if (!body(j, e, sj)) continue;
+        const float rx = (float)min_image(xnode - sj.x, dnx);
+        const float ry = (float)min_image(ynode - sj.y, dny);
+        const float l = sj.r - sqrtf(rx * rx + ry * ry);
+        if (l >= lcut) S += phi_of(l, phik);
       }
       scale = S > 1.0f ? 1.0f / S : 1.0f;
     }
 
-    // pass 2: weights, sums for Eqs. (15) and (17), and per-body force/torque
+    // pass 2: weights, sums for Eqs. (15) and (17), and per-body force/torque (each wave
+    // sums its lanes in FP64 and adds the totals to the body's accumulators)
     const float kap = d.kappa;
-    for (int c0 = 0; c0 < nb; c0 += kBodyChunk) {
-      const int cn = min(kBodyChunk, nb - c0);
-      if (nsolid <= 1 || nb > kBodyChunk) {  // staged already when one chunk was used above
-        __syncthreads();
-        if (tid < cn) stage_body(d, bs, nbs, list[c0 + tid], sb + tid, sidx + tid);
-        __syncthreads();
+    double *__restrict__ acc = d.acc[p];
+    for (int j = 0; j < nb; ++j) {
+      int e;
+      BodySnap sj;
+      if (!body(j, e, sj)) continue;
+      const float rx = (float)min_image(xnode - sj.x, dnx);
+      const float ry = (float)min_image(ynode - sj.y, dny);
+      const float l = sj.r - sqrtf(rx * rx + ry * ry);
+      float fx = 0.f, fy = 0.f, tq = 0.f;
+      if (valid && !bnd && l >= lcut) {
+        const float w = scale * phi_of(l, phik);
+        // rigid-body solid velocity U + omega x r
+        const float ux_s = sj.u - sj.w * ry;
+        const float uy_s = sj.v + sj.w * rx;
+        Phi += w;
+        Ax += w * ux_s;
+        Ay += w * uy_s;
+        Mxx += w * ux_s * ux_s;
+        Mxy += w * ux_s * uy_s;
+        Myy += w * uy_s * uy_s;
+        // force on the body: -w rho (u_s - u*) (times the Eq. (18) scale)
+        fx = -kap * w * rho * (ux_s - usx);
+        fy = -kap * w * rho * (uy_s - usy);
+        tq = rx * fy - ry * fx;
       }
-      for (int j = 0; j < cn; ++j) {
-        const float rx = (float)min_image(xnode - sb[j].x, dnx);
-        const float ry = (float)min_image(ynode - sb[j].y, dny);
-        const float l = sb[j].r - sqrtf(rx * rx + ry * ry);
-        float fx = 0.f, fy = 0.f, tq = 0.f;
-        if (valid && !bnd && l >= lcut) {
-          const float w = scale * phi_of(l, phik);
-          // rigid-body solid velocity U + omega x r
-          const float ux_s = sb[j].u - sb[j].w * ry;
-          const float uy_s = sb[j].v + sb[j].w * rx;
-          Phi += w;
-          Ax += w * ux_s;
-          Ay += w * uy_s;
-          Mxx += w * ux_s * ux_s;
-          Mxy += w * ux_s * uy_s;
-          Myy += w * uy_s * uy_s;
-          // force on the body: -w rho (u_s - u*) (times the Eq. (18) scale)
-          fx = -kap * w * rho * (ux_s - usx);
-          fy = -kap * w * rho * (uy_s - usy);
-          tq = rx * fy - ry * fx;
-        }
-        if (MODE == kModeStep) {
-          const bool any = __ballot(fx != 0.f || fy != 0.f) != 0;
-          double sx = 0.0, sy = 0.0, st = 0.0;
-          if (any) {
-            sx = wave_sum((double)fx);
-            sy = wave_sum((double)fy);
-            st = wave_sum((double)tq);
-          }
-          if (lane == 0) {
-            red[j][wave][0] = sx;
-            red[j][wave][1] = sy;
-            red[j][wave][2] = st;
-          }
-        }
-      }
-      if (MODE == kModeStep) {
-        __syncthreads();
-        double *acc = d.acc[p];
-        for (int e = tid; e < 3 * cn; e += kBlockThreads) {
-          const int j = e / 3, c = e - 3 * j;
-          double v = 0.0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) v += red[j][w][c];
-          if (v != 0.0) unsafeAtomicAdd(&acc[3 * sidx[j] + c], v);
+      if (MODE == kModeStep && __ballot(fx != 0.f || fy != 0.f) != 0) {
+        const double sx = wave_sum((double)fx);
+        const double sy = wave_sum((double)fy);
+        const double st = wave_sum((double)tq);
+        if (lane == 0) {
+          unsafeAtomicAdd(&acc[3 * e], sx);
+          unsafeAtomicAdd(&acc[3 * e + 1], sy);
+          unsafeAtomicAdd(&acc[3 * e + 2], st);
         }
       }
     }
@@ -691,24 +670,12 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         fx += kap * w * rho * usx;
         fy += kap * w * rho * usy;
       }
-      if (MODE == kModeStep) {
-        const bool any = __ballot(fx != 0.f || fy != 0.f) != 0;
-        double sx = 0.0, sy = 0.0;
-        if (any) {
-          sx = wave_sum((double)fx);
-          sy = wave_sum((double)fy);
-        }
-        __syncthreads();
+      if (MODE == kModeStep && __ballot(fx != 0.f || fy != 0.f) != 0) {
+        const double sx = wave_sum((double)fx);
+        const double sy = wave_sum((double)fy);
         if (lane == 0) {
-          red[0][wave][0] = sx;
-          red[0][wave][1] = sy;
-        }
-        __syncthreads();
-        if (tid < 2) {
-          double v = 0.0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) v += red[0][w][tid];
-          if (v != 0.0) unsafeAtomicAdd(&d.acc[p][3 * nbs + tid], v);
+          unsafeAtomicAdd(&acc[3 * nbs], sx);
+          unsafeAtomicAdd(&acc[3 * nbs + 1], sy);
         }
       }
     }
@@ -819,9 +786,6 @@ template <class ST, int TX, int TY, int AM, bool OPEN>
 __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
-  __shared__ BodyLds sb[kBodyChunk];
-  __shared__ int32_t sidx[kBodyChunk];
-  __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
   const WorkSplit ws = xcd_split(hdr->total_tiles);
   const int solo = hdr->solo_slot;  // one member: no per-tile lookup
   for (int64_t t = ws.begin; t < ws.end; ++t) {
@@ -830,9 +794,8 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, sb, sidx, red,
-                                                  nullptr, nullptr, nullptr, Region{0, 0, 0, 0});
-    __syncthreads();  // LDS reuse by the next tile
+    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, nullptr, nullptr,
+                                                  nullptr, Region{0, 0, 0, 0});
   }
 }
 
@@ -842,9 +805,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
                                                           double *__restrict__ rho,
                                                           double *__restrict__ ux,
                                                           double *__restrict__ uy) {
-  __shared__ BodyLds sb[kBodyChunk];
-  __shared__ int32_t sidx[kBodyChunk];
-  __shared__ double red[kBodyChunk][kBlockThreads / 64][3];
   const SolveDesc &d = *desc;
   // tiles that intersect the region
   const int tx0 = region.x / TX, tx1 = (region.x + region.w - 1) / TX;
@@ -853,9 +813,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, sb, sidx, red, rho,
-                                                     ux, uy, region);
-    __syncthreads();
+    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, rho, ux, uy,
+                                                           region);
   }
 }
 
@@ -978,6 +937,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
         sn[4 * nb + b] = W;
       }
     }
+    // what the collide kernel of the step reads of this body
+    if (lane == 0) d.bsnap[q][b] = BodySnap{X, Y, (float)U, (float)V, (float)W, (float)R};
     // a blown-up body is flagged instead of binned (its tile indices would be garbage)
     if (!isfinite(X) || !isfinite(Y) || !isfinite(R)) {
       if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
