@@ -245,9 +245,9 @@ __device__ __forceinline__ WorkSplit xcd_split(int64_t T) {
   const int64_t per = T >> 3, r = T & 7;
   const int64_t lo = xcd * per + (xcd < r ? xcd : r);
   const int64_t count = per + (xcd < r ? 1 : 0);
-  const int64_t chunk = (count + nblk - 1) / nblk;
   const int64_t l = blockIdx.x >> 3;
   WorkSplit w;
+  const int64_t chunk = (count + nblk - 1) / nblk;
   w.begin = lo + min(count, l * chunk);
   w.end = lo + min(count, (l + 1) * chunk);
   return w;
@@ -788,7 +788,12 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     const BatchHeader *__restrict__ hdr, int k) {
   const WorkSplit ws = xcd_split(hdr->total_tiles);
   const int solo = hdr->solo_slot;  // one member: no per-tile lookup
-  for (int64_t t = ws.begin; t < ws.end; ++t) {
+  // Odd chunks are walked backwards: two neighbouring chunks then reach their common
+  // edge at about the same time, so the cache lines the x-shifted loads share across it
+  // are still in the XCD's L2 for the second reader.
+  const bool rev = (blockIdx.x >> 3) & 1;
+  for (int64_t i = ws.begin; i < ws.end; ++i) {
+    const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
     const int s = solo >= 0 ? solo : __builtin_amdgcn_readfirstlane(tile_solve[t]);
     const SolveDesc &d = descs[s];
     if (k >= d.active_steps) continue;
