@@ -725,13 +725,14 @@ class Engine {
   }
 
   int collide_grid_for(int64_t T) {
-    // a persistent grid: each block sweeps one contiguous chunk of tiles, and the grid is
-    // a multiple of the blocks resident at once (per-block set-up is paid once per chunk;
-    // shorter chunks keep the tiles in flight closer together)
+    // a persistent grid: each block sweeps one contiguous chunk of tiles of a set length
+    // (per-block set-up is paid once per chunk; shorter chunks keep the tiles in flight
+    // closer together), and at least the blocks resident at once while tiles last
     int &bpc = blocks_per_cu_[shape_][storage_][addr_][open_ ? 1 : 0];
     if (bpc == 0) bpc = std::max(1, collide_blocks_per_cu(shape_, storage_, addr_, open_));
-    const int mult = storage_ == DILBM_STORE_FP16 ? DILBM_GRID_MULT_FP16 : DILBM_GRID_MULT_FP32;
-    int64_t g = mult > 0 ? std::min<int64_t>(T, (int64_t)num_cu_ * bpc * mult) : T;
+    const int64_t chunk = storage_ == DILBM_STORE_FP16 ? DILBM_CHUNK_FP16 : DILBM_CHUNK_FP32;
+    const int64_t resident = (int64_t)num_cu_ * bpc;
+    int64_t g = chunk > 0 ? std::max(std::min(T, resident), (T + chunk - 1) / chunk) : T;
     g = std::min<int64_t>(g, (int64_t)1 << 30);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
