@@ -192,16 +192,37 @@ __device__ __forceinline__ BodySnap load_snap(const DILBM_CONST BodySnap *q) {
   return BodySnap{q->x, q->y, q->u, q->v, q->w, q->r};
 }
 
+// FP64 sum over a wave (every lane must be active).  DPP moves combine lanes at distance
+// 1 and 2 (quad permutes), then mirrored half-rows and rows, without going through LDS;
+// the four row totals are read out and added, so every lane gets the total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // (1 + tanh(2 l / eps)) / 2 written as the logistic 1 / (1 + e^(-4 l / eps)); phi_k holds
-// 4 / eps * log2(e) so one hardware exp2 and one reciprocal do it.
+// 4 / eps * log2(e) so one hardware exp2 and one reciprocal do it.  (The hardware
+// exp2 flushes results below 2^-126 to zero, where phi is 1 to FP32 precision anyway.)
 __device__ __forceinline__ float phi_of(float l, float phi_k) {
-  return __builtin_amdgcn_rcpf(1.0f + exp2f(-l * phi_k));
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-l * phi_k));
 }
 
 __device__ __forceinline__ double min_image(double d, double n) {
@@ -609,7 +630,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         if (!body(j, e, sj)) continue;
         const float rx = (float)min_image(xnode - sj.x, dnx);
         const float ry = (float)min_image(ynode - sj.y, dny);
-        const float l = sj.r - sqrtf(rx * rx + ry * ry);
+        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);  // within 1 ulp
         if (l >= lcut) S += phi_of(l, phik);
       }
       scale = S > 1.0f ? 1.0f / S : 1.0f;
@@ -625,7 +646,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
       if (!body(j, e, sj)) continue;
       const float rx = (float)min_image(xnode - sj.x, dnx);
       const float ry = (float)min_image(ynode - sj.y, dny);
-      const float l = sj.r - sqrtf(rx * rx + ry * ry);
+      const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
       float fx = 0.f, fy = 0.f, tq = 0.f;
       if (valid && !bnd && l >= lcut) {
         const float w = scale * phi_of(l, phik);
