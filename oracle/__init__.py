@@ -4,8 +4,10 @@ This package is the oracle the GPU library is checked against.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import it; the
 product package never does, and shares no code with it.
 
-The arithmetic lives in ``dilbm_oracle.c`` (plain C, FP64, compiled with
-``-O2 -ffp-contract=off``); this module only marshals numpy arrays through ctypes.
+The arithmetic lives in ``dilbm_oracle.c`` (two dimensions, D2Q9) and
+``dilbm3d_oracle.c`` (three dimensions, D3Q19, spheres), plain C in FP64 compiled with
+``-O2 -ffp-contract=off``; ``binding`` and ``binding3d`` only marshal numpy arrays through
+ctypes.
 """
 from .binding import (  # noqa: F401
     OracleParams,
@@ -22,3 +24,4 @@ from .binding import (  # noqa: F401
     body_update,
     num_threads,
 )
+from . import binding3d  # noqa: F401,E402

@@ -20,15 +20,23 @@ _ip = C.POINTER(C.c_int32)
 _u8p = C.POINTER(C.c_uint8)
 
 
-def build_oracle(force: bool = True) -> str:
-    """Compile ``libdilbm_oracle.so`` with gcc (FP64, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def compile_c(src: str, lib: str, force: bool) -> str:
+    """Compile one oracle source into a shared library with gcc (FP64, no FMA
+    contraction, OpenMP)."""
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+               "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile ``libdilbm_oracle.so`` and the three-dimensional ``libdilbm3d_oracle.so``."""
+    compile_c(os.path.join(_HERE, "dilbm3d_oracle.c"),
+              os.path.join(_HERE, "libdilbm3d_oracle.so"), force)
+    return compile_c(_SRC, _LIB, force)
 
 
 class _Params(C.Structure):
