@@ -1,0 +1,128 @@
+/*
+ * dilbm3d.h -- C ABI of the three-dimensional DI-LBM step in libdilbm.so (D3Q19 lattice,
+ * spherical particles), on MI355X (gfx950).
+ *
+ * The paper (Liu, Huang, Chai & Shi) states DI-LBM in two dimensions and motivates it by
+ * the cost of solid volume fractions in three.  These calls take the same step as
+ * dilbm.h, Section 2.3, with every equation carried over to three dimensions:
+ *   1. the diffuse solid field phi of Eq. (14) with l = R - |x - X| for a sphere;
+ *   2. the collision of Eq. (13) with the corrected velocity of Eq. (17), phi times the
+ *      force term of Eq. (15) and the uncorrected velocity of Eq. (16);
+ *   3. pull streaming over the D3Q19 velocities and the moments of Eq. (5);
+ *   4. the hydrodynamic force and torque of Eqs. (18)-(19) per sphere (torque r x F, a
+ *      vector; FP64 accumulation) and the motion of Eqs. (22)-(24) with the repulsion
+ *      of Eqs. (28)-(29) (FP64).
+ *
+ * Conventions (as dilbm.h unless stated):
+ *   - Lattice units.  Node (i, j, k) sits at (i + 0.5, j + 0.5, k + 0.5).
+ *   - D3Q19 directions: 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7..18 the edge
+ *     directions in opposite pairs: (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1),
+ *     (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  Weights
+ *     1/3, 1/18, 1/36; c_s^2 = 1/3.
+ *   - Field arrays are [nz][ny][nx]; population arrays are [19][nz][ny][nx] and hold
+ *     f_i - w_i * rho0 as FP64.  Per-sphere vectors are [n][3] (x, y, z).
+ *   - Host pointers; the caller owns every array; status codes and handle poisoning
+ *     as in dilbm.h (DILBM_EUNSTABLE and DILBM_ECAPACITY poison the handle).
+ *   - Populations are stored on the device in FP32 as f_i - w_i rho0 (structure of
+ *     arrays, one plane per direction); all arithmetic of the node update is FP32, the
+ *     sphere forces, torques and motion are FP64.
+ *   - A sphere's mass is rho_s * 4/3 pi R^3 and its moment of inertia 2/5 m R^2; the
+ *     spin update has no gyroscopic term (the inertia is isotropic).
+ *   - Streaming is periodic on all three axes; walls are static diffuse slabs across
+ *     the periodic seams, as in two dimensions.  Open inlet/outlet ends are not
+ *     available in three dimensions.
+ */
+#ifndef DILBM3D_H
+#define DILBM3D_H
+
+#include <stdint.h>
+
+#include "dilbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DILBM3D_ABI_VERSION 1u
+
+enum { DILBM3D_WALL_Y = 1u, DILBM3D_WALL_X = 2u, DILBM3D_WALL_Z = 4u };
+
+typedef struct dilbm3d_solver dilbm3d_solver;
+
+typedef struct dilbm3d_params {
+  uint32_t abi_version;        /* DILBM3D_ABI_VERSION, else DILBM_EABI */
+  int32_t nx, ny, nz;          /* >= 1 each; nx * ny * nz * 19 * 4 bytes per buffer < 4 GB */
+  double tau;                  /* BGK relaxation time, > 0.5 */
+  double rho0;                 /* rest density, > 0 */
+  double interface_width;      /* epsilon of Eq. (14), > 0 */
+  double phi_cutoff;           /* phi := 0 where l < -phi_cutoff * epsilon; > 0 */
+  double body_force[3];        /* uniform fluid body force density G */
+  double gravity[3];           /* g of Eq. (22): acts on the spheres only */
+  uint32_t wall_mask;          /* DILBM3D_WALL_* */
+  double wall_half_thickness;  /* h: slab surfaces at h and N - h on each walled axis */
+  int32_t force_mode;          /* DILBM_FORCE_MOMENTUM_EXCHANGE or DILBM_FORCE_PAPER_LITERAL */
+  double coll_eps_p, coll_eps_p_overlap, coll_eps_w, coll_eps_w_overlap, coll_xi; /* (28)-(29) */
+  int32_t list_capacity;       /* spheres listed per tile; 0 = min(n, 128); <= 1024 */
+  int32_t device;              /* HIP device ordinal */
+  void *stream;                /* hipStream_t to run on, or NULL for a library-owned one */
+} dilbm3d_params;
+
+/* Fill *p with defaults: abi_version, rho0 = 1, interface_width = 2, phi_cutoff = 4,
+ * wall_half_thickness = 4, collision constants 1e4 / 1e4 / 5e3 / 5e3 and xi = 1; the
+ * caller sets nx, ny, nz and tau.  Returns DILBM_EINVAL for p == NULL. */
+dilbm_status dilbm3d_params_init(dilbm3d_params *p);
+
+/* Create a solver with the fluid at rest (f = w rho0) and no spheres.  *out receives the
+ * handle (NULL on failure).  DILBM_EINVAL for bad parameters, DILBM_EABI for a version
+ * mismatch, DILBM_ENOMEM when the device buffers do not fit. */
+dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out);
+
+/* Replace the spheres: n >= 0; pos [n][3] (wrapped into the domain), radius [n] > 0 and
+ * density [n] > 0 are required, vel [n][3], omega [n][3] and fixed [n] (nonzero: the
+ * sphere keeps its velocity and spin and is not integrated) may be NULL (zero). */
+dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *pos,
+                                   const double *vel, const double *omega,
+                                   const double *radius, const double *density,
+                                   const uint8_t *fixed);
+
+/* Populations in and out, [19][nz][ny][nx] deviations f_i - w_i rho0 at the current step
+ * (stored as FP32: values are rounded on the way in). */
+dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev);
+dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev);
+
+/* Advance nsteps >= 0 steps; synchronous. */
+dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps);
+
+/* rho and the corrected velocity of Eq. (17) at every node, [nz][ny][nx] each; any
+ * pointer may be NULL. */
+dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, double *uy,
+                                double *uz);
+
+/* Hydrodynamic force [n][3] and torque [n][3] on each sphere from the last step
+ * (Eqs. (18)-(19)); either may be NULL. */
+dilbm_status dilbm3d_get_particle_forces(dilbm3d_solver *s, double *force, double *torque);
+
+/* Sphere state at the current step: pos, vel, omega, [n][3] each; any may be NULL. */
+dilbm_status dilbm3d_get_particles(dilbm3d_solver *s, double *pos, double *vel,
+                                   double *omega);
+
+/* Force of the fluid on the wall slabs in the last step, [3]. */
+dilbm_status dilbm3d_get_wall_force(dilbm3d_solver *s, double *force);
+
+/* Time every collide launch with HIP events on the solver's stream (enable != 0), and
+ * read the total milliseconds and launch count since timing was enabled. */
+dilbm_status dilbm3d_set_kernel_timing(dilbm3d_solver *s, int32_t enable);
+dilbm_status dilbm3d_get_kernel_timing(dilbm3d_solver *s, double *collide_ms,
+                                       int64_t *launches);
+
+/* Release the handle and its device memory; NULL is a no-op. */
+void dilbm3d_destroy(dilbm3d_solver *s);
+
+/* Message of the handle's last failure ("" if none); for s == NULL, the calling
+ * thread's last failure of a dilbm3d_* call. */
+const char *dilbm3d_last_error(const dilbm3d_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

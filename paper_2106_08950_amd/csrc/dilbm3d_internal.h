@@ -1,0 +1,85 @@
+// dilbm3d_internal.h -- device-visible structures of the three-dimensional DI-LBM path of
+// libdilbm (internal to the library).
+//
+// Memory layout of one 3-D solve in HBM:
+//   pop[2]        two population buffers, structure of arrays [19][nz][ny][nx] of FP32
+//                 deviations d_i = f_i - w_i rho0.  Pull scheme: node x at time t_n finds
+//                 f_i in pop[p][i][x - c_i].
+//   tile_count[2] per tile (64 x 4 x 1 nodes), the number of spheres whose phi support
+//                 may touch it; tile_list[2]: `list_cap` sphere indices per tile
+//   bstate[2]     sphere state SoA [9][nb]: x, y, z, u, v, w, omega_x, omega_y, omega_z
+//   bconst        sphere constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
+//   bsnap[2]      per sphere, what the collide kernel reads of it (SphereSnap, 64 B),
+//                 written with every sphere update
+//   acc[2]        FP64 accumulators [(nb + 1) * 6]: force (3) and torque (3) per sphere,
+//                 then the wall force in the last slot
+//   err           sticky error bits (kErrUnstable, kErrCapacity, kErrInternal)
+// Everything double-buffered is indexed by the step parity p: a step with parity p reads
+// slot p and writes slot 1 - p.
+#pragma once
+
+#include <stdint.h>
+
+namespace dilbm {
+
+constexpr int kQ3 = 19;
+constexpr int kTile3X = 64, kTile3Y = 4;  // one tile: 64 x 4 x 1 nodes, 256 threads
+constexpr int kMaxListCap3 = 1024;
+
+// Register budget of the collide kernel: compiled for at least this many waves per SIMD.
+#ifndef DILBM3D_COLLIDE_WAVES
+#define DILBM3D_COLLIDE_WAVES 4
+#endif
+
+// Chunk of tiles each collide block sweeps (the grid never drops below one resident
+// wave while tiles last).
+#ifndef DILBM3D_CHUNK
+#define DILBM3D_CHUNK 3
+#endif
+
+// One sphere as the collide kernel sees it at a step: centre in FP64 (node - centre
+// differences keep FP64 accuracy before they are rounded), velocity, spin and radius.
+struct SphereSnap {
+  double x, y, z;
+  float u, v, w;
+  float ox, oy, oz;
+  float r;
+  float pad[2];
+};
+
+struct Desc3 {
+  int32_t nx, ny, nz;
+  int32_t tiles_x, tiles_y;
+  int64_t ntiles;
+  int32_t nbodies;
+  int32_t list_cap;
+  // FP32 node-update constants
+  float omega;        // 1 / tau
+  float khalf;        // 1 - 1/(2 tau)
+  float rho0;
+  float Gx, Gy, Gz;
+  float kappa;        // force scale of Eq. (18): 1 or 1 - 1/(2 tau)
+  float lcut;         // -cutoff * eps
+  float phi_k;        // 4 / eps * log2(e)
+  float wall_h;
+  uint32_t wall_mask; // bit 0 y, bit 1 x, bit 2 z
+  // nodes within h + cutoff*eps of a walled seam: [0, lo) and [hi, n) on each axis
+  int32_t wall_lo[3], wall_hi[3];  // axis order x, y, z
+  // FP64 sphere constants
+  double rho0_d;
+  double gx, gy, gz;
+  double inv_eps_p, inv_eps_p1, inv_eps_w, inv_eps_w1, xi;
+  double wall_h_d;
+  double support;     // cutoff * eps
+  // device buffers
+  float *pop[2];
+  int32_t *tile_count[2];
+  int32_t *tile_list[2];
+  double *bstate[2];
+  const double *bconst;
+  SphereSnap *bsnap[2];
+  double *acc[2];
+  int32_t *err;
+};
+
+}  // namespace dilbm

@@ -1,0 +1,584 @@
+// engine3d.hip -- host runtime and C ABI of the three-dimensional DI-LBM path of libdilbm.
+//
+// A dilbm3d_solver owns the device state of one 3-D problem: two FP32 population buffers,
+// the per-tile sphere lists, the FP64 sphere state, snapshots and force accumulators,
+// and a small device descriptor.  A step is one k3_collide launch over every tile and
+// one k3_bodies launch over the spheres; dilbm3d_step polls the sticky error word once
+// after the last step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dilbm3d.h"
+#include "dilbm3d_internal.h"
+#include "dilbm_internal.h"
+#include "kernels.h"
+#include "kernels3d.h"
+
+namespace dilbm {
+namespace {
+
+struct Fail3 {
+  dilbm_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail3(dilbm_status st, const std::string &msg) { throw Fail3{st, msg}; }
+
+#define HIPCHK3(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      dilbm_status st_ = (e_ == hipErrorOutOfMemory) ? DILBM_ENOMEM : DILBM_EDEVICE;    \
+      fail3(st_, std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    }                                                                                   \
+  } while (0)
+
+thread_local std::string g_thread_error3;
+
+constexpr uint64_t kAlign3 = 256;
+inline uint64_t up3(uint64_t v) { return (v + kAlign3 - 1) / kAlign3 * kAlign3; }
+
+template <class F>
+dilbm_status guard3(std::string *err, F &&f) {
+  try {
+    f();
+    return DILBM_OK;
+  } catch (const Fail3 &e) {
+    if (err) *err = e.msg;
+    g_thread_error3 = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    if (err) *err = "host allocation failed";
+    g_thread_error3 = "host allocation failed";
+    return DILBM_ENOMEM;
+  } catch (...) {
+    if (err) *err = "unexpected exception";
+    g_thread_error3 = "unexpected exception";
+    return DILBM_EDEVICE;
+  }
+}
+
+void validate3(const dilbm3d_params *p) {
+  if (!p) fail3(DILBM_EINVAL, "params is NULL");
+  if (p->abi_version != DILBM3D_ABI_VERSION) fail3(DILBM_EABI, "abi_version mismatch");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) fail3(DILBM_EINVAL, "nx, ny, nz must be >= 1");
+  const uint64_t nodes = (uint64_t)p->nx * p->ny * p->nz;
+  if (nodes * kQ3 * 4ull >= (1ull << 32) - 256)
+    fail3(DILBM_EINVAL, "19 * 4 bytes * nx * ny * nz must stay under 4 GB");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) fail3(DILBM_EINVAL, "tau must be > 0.5");
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) fail3(DILBM_EINVAL, "rho0 must be > 0");
+  if (!(p->interface_width > 0.0) || !std::isfinite(p->interface_width))
+    fail3(DILBM_EINVAL, "interface_width must be > 0");
+  if (!(p->phi_cutoff > 0.0) || !std::isfinite(p->phi_cutoff))
+    fail3(DILBM_EINVAL, "phi_cutoff must be > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->body_force[a]) || !std::isfinite(p->gravity[a]))
+      fail3(DILBM_EINVAL, "body_force and gravity must be finite");
+  if (p->wall_mask & ~7u) fail3(DILBM_EINVAL, "wall_mask has unknown bits");
+  if (p->wall_mask && !(p->wall_half_thickness > 0.0))
+    fail3(DILBM_EINVAL, "wall_half_thickness must be > 0 with walls");
+  if (p->force_mode != DILBM_FORCE_MOMENTUM_EXCHANGE && p->force_mode != DILBM_FORCE_PAPER_LITERAL)
+    fail3(DILBM_EINVAL, "unknown force_mode");
+  if (!(p->coll_eps_p > 0.0) || !(p->coll_eps_p_overlap > 0.0) || !(p->coll_eps_w > 0.0) ||
+      !(p->coll_eps_w_overlap > 0.0) || !(p->coll_xi >= 0.0))
+    fail3(DILBM_EINVAL, "collision constants must be > 0 (xi >= 0)");
+  if (p->list_capacity < 0 || p->list_capacity > kMaxListCap3)
+    fail3(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
+}
+
+struct Mem3 {
+  void *ptr = nullptr;
+  uint64_t bytes = 0;
+};
+
+Mem3 alloc3(uint64_t bytes) {
+  Mem3 m;
+  m.bytes = up3(std::max<uint64_t>(bytes, 1));
+  HIPCHK3(hipMalloc(&m.ptr, m.bytes));
+  return m;
+}
+
+void free3(Mem3 &m) {
+  if (m.ptr) (void)hipFree(m.ptr);
+  m.ptr = nullptr;
+  m.bytes = 0;
+}
+
+}  // namespace
+}  // namespace dilbm
+
+using namespace dilbm;
+
+struct dilbm3d_solver {
+  dilbm3d_params prm{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int nb = 0;
+  int cap = 1;
+  int parity = 0;
+  int64_t steps = 0;
+  int grid = 8;
+  Mem3 pops, body;
+  uint64_t off_counts = 0, off_lists = 0, off_bstate = 0, off_bconst = 0, off_snap = 0,
+           off_acc = 0;
+  Desc3 h{};
+  Desc3 *d_desc = nullptr;
+  int32_t *d_err = nullptr;
+  dilbm_status poison = DILBM_OK;
+  std::string last_error;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double timed_ms = 0.0;
+  int64_t timed_launches = 0;
+};
+
+namespace dilbm {
+namespace {
+
+int64_t tiles_of(const dilbm3d_params &p) {
+  return (int64_t)((p.nx + kTile3X - 1) / kTile3X) * ((p.ny + kTile3Y - 1) / kTile3Y) * p.nz;
+}
+
+// lay out (and allocate) the sphere buffer for n spheres
+void body_layout3(dilbm3d_solver &s, int n) {
+  const uint64_t T = (uint64_t)tiles_of(s.prm);
+  s.cap = s.prm.list_capacity > 0 ? s.prm.list_capacity : std::max(1, std::min(n, 128));
+  const uint64_t nn = (uint64_t)std::max(n, 1);
+  uint64_t o = 0;
+  s.off_counts = o;
+  o += up3(2 * T * 4);
+  s.off_lists = o;
+  o += up3(2 * T * (uint64_t)s.cap * 4);
+  s.off_bstate = o;
+  o += up3(2 * 9 * nn * 8);
+  s.off_bconst = o;
+  o += up3(5 * nn * 8);
+  s.off_snap = o;
+  o += up3(2 * nn * sizeof(SphereSnap));
+  s.off_acc = o;
+  o += up3(2 * 6 * (uint64_t)(n + 1) * 8);
+  Mem3 fresh = alloc3(o);  // allocated before the old buffer goes
+  free3(s.body);
+  s.body = fresh;
+}
+
+void fill_desc3(dilbm3d_solver &s) {
+  const dilbm3d_params &p = s.prm;
+  Desc3 &d = s.h;
+  d = Desc3{};
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  d.tiles_x = (p.nx + kTile3X - 1) / kTile3X;
+  d.tiles_y = (p.ny + kTile3Y - 1) / kTile3Y;
+  d.ntiles = tiles_of(p);
+  d.nbodies = s.nb;
+  d.list_cap = s.cap;
+  d.omega = (float)(1.0 / p.tau);
+  d.khalf = (float)(1.0 - 0.5 / p.tau);
+  d.rho0 = (float)p.rho0;
+  d.Gx = (float)p.body_force[0];
+  d.Gy = (float)p.body_force[1];
+  d.Gz = (float)p.body_force[2];
+  d.kappa = p.force_mode == DILBM_FORCE_PAPER_LITERAL ? (float)(1.0 - 0.5 / p.tau) : 1.0f;
+  d.lcut = (float)(-p.phi_cutoff * p.interface_width);
+  d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
+  d.wall_h = (float)p.wall_half_thickness;
+  d.wall_mask = p.wall_mask;
+  const int n3[3] = {p.nx, p.ny, p.nz};
+  const double reach = p.wall_half_thickness + p.phi_cutoff * p.interface_width;
+  for (int a = 0; a < 3; ++a) {
+    // nodes k with k + 0.5 within reach of the seam: [0, lo) and [hi, n)
+    int lo = (int)std::min<double>(n3[a], std::ceil(reach - 0.5) + 1.0);
+    int hi = (int)std::max<double>(0.0, (double)n3[a] - (std::ceil(reach - 0.5) + 1.0));
+    d.wall_lo[a] = std::max(0, lo);
+    d.wall_hi[a] = std::min(n3[a], hi);
+  }
+  d.rho0_d = p.rho0;
+  d.gx = p.gravity[0];
+  d.gy = p.gravity[1];
+  d.gz = p.gravity[2];
+  d.inv_eps_p = 1.0 / p.coll_eps_p;
+  d.inv_eps_p1 = 1.0 / p.coll_eps_p_overlap;
+  d.inv_eps_w = 1.0 / p.coll_eps_w;
+  d.inv_eps_w1 = 1.0 / p.coll_eps_w_overlap;
+  d.xi = p.coll_xi;
+  d.wall_h_d = p.wall_half_thickness;
+  d.support = p.phi_cutoff * p.interface_width;
+  const uint64_t half = (uint64_t)kQ3 * p.nx * p.ny * p.nz * 4;
+  d.pop[0] = (float *)s.pops.ptr;
+  d.pop[1] = (float *)((char *)s.pops.ptr + half);
+  char *bb = (char *)s.body.ptr;
+  const uint64_t T = (uint64_t)d.ntiles, nn = (uint64_t)std::max(s.nb, 1);
+  d.tile_count[0] = (int32_t *)(bb + s.off_counts);
+  d.tile_count[1] = d.tile_count[0] + T;
+  d.tile_list[0] = (int32_t *)(bb + s.off_lists);
+  d.tile_list[1] = d.tile_list[0] + T * s.cap;
+  d.bstate[0] = (double *)(bb + s.off_bstate);
+  d.bstate[1] = d.bstate[0] + 9 * nn;
+  d.bconst = (const double *)(bb + s.off_bconst);
+  d.bsnap[0] = (SphereSnap *)(bb + s.off_snap);
+  d.bsnap[1] = d.bsnap[0] + nn;
+  d.acc[0] = (double *)(bb + s.off_acc);
+  d.acc[1] = d.acc[0] + 6 * (uint64_t)(s.nb + 1);
+  d.err = s.d_err;
+}
+
+void upload_desc3(dilbm3d_solver &s) {
+  HIPCHK3(hipMemcpyAsync(s.d_desc, &s.h, sizeof(Desc3), hipMemcpyHostToDevice, s.stream));
+  HIPCHK3(hipStreamSynchronize(s.stream));  // the host copy may change before the next call
+}
+
+void check_usable3(dilbm3d_solver *s) {
+  if (s->poison != DILBM_OK) fail3(DILBM_ESTATE, "handle poisoned: " + s->last_error);
+}
+
+void poll_errors3(dilbm3d_solver &s) {
+  int32_t e = 0;
+  HIPCHK3(hipMemcpyAsync(&e, s.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  HIPCHK3(hipStreamSynchronize(s.stream));
+  if (e & kErrInternal) {
+    s.poison = DILBM_EDEVICE;
+    fail3(DILBM_EDEVICE, "internal error: a kernel met an out-of-range sphere index");
+  }
+  if (e & kErrCapacity) {
+    s.poison = DILBM_ECAPACITY;
+    fail3(DILBM_ECAPACITY, "a tile sphere list overflowed; raise list_capacity");
+  }
+  if (e & kErrUnstable) {
+    s.poison = DILBM_EUNSTABLE;
+    fail3(DILBM_EUNSTABLE, "unstable: rho <= 0, |u| > 0.5 or a non-finite value");
+  }
+}
+
+void collect_timing3(dilbm3d_solver &s) {
+  for (auto &ev : s.events) {
+    HIPCHK3(hipEventSynchronize(ev.second));
+    float ms = 0.f;
+    HIPCHK3(hipEventElapsedTime(&ms, ev.first, ev.second));
+    s.timed_ms += ms;
+    ++s.timed_launches;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  s.events.clear();
+}
+
+// copy a host array into a fresh device buffer on the solver's stream
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+}  // namespace dilbm
+
+extern "C" {
+
+dilbm_status dilbm3d_params_init(dilbm3d_params *p) {
+  if (!p) return DILBM_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->abi_version = DILBM3D_ABI_VERSION;
+  p->rho0 = 1.0;
+  p->interface_width = 2.0;
+  p->phi_cutoff = 4.0;
+  p->wall_half_thickness = 4.0;
+  p->force_mode = DILBM_FORCE_MOMENTUM_EXCHANGE;
+  p->coll_eps_p = 1.0e4;
+  p->coll_eps_p_overlap = 1.0e4;
+  p->coll_eps_w = 0.5e4;
+  p->coll_eps_w_overlap = 0.5e4;
+  p->coll_xi = 1.0;
+  return DILBM_OK;
+}
+
+dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
+  if (!out) return DILBM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<dilbm3d_solver> h(new (std::nothrow) dilbm3d_solver);
+  if (!h) return DILBM_ENOMEM;
+  dilbm_status st = guard3(nullptr, [&] {
+    validate3(p);
+    int ndev = 0;
+    HIPCHK3(hipGetDeviceCount(&ndev));
+    if (p->device < 0 || p->device >= ndev) fail3(DILBM_EINVAL, "no such device");
+    dilbm3d_solver &s = *h;
+    s.prm = *p;
+    s.device = p->device;
+    HIPCHK3(hipSetDevice(s.device));
+    if (p->stream) {
+      s.stream = (hipStream_t)p->stream;
+    } else {
+      HIPCHK3(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+      s.own_stream = true;
+    }
+    const uint64_t half = (uint64_t)kQ3 * p->nx * p->ny * p->nz * 4;
+    s.pops = alloc3(2 * half);
+    HIPCHK3(hipMalloc(&s.d_desc, sizeof(Desc3)));
+    HIPCHK3(hipMalloc(&s.d_err, sizeof(int32_t)));
+    body_layout3(s, 0);
+    fill_desc3(s);
+    // the fluid at rest: every deviation zero in both buffers; empty lists
+    HIPCHK3(launch_zero_bytes(s.pops.ptr, (int64_t)s.pops.bytes, s.stream));
+    HIPCHK3(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, s.stream));
+    HIPCHK3(launch_zero_bytes(s.d_err, sizeof(int32_t), s.stream));
+    upload_desc3(s);
+    const int bpc = std::max(1, collide3_blocks_per_cu());
+    int cus = 0;
+    HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
+    const int64_t T = s.h.ntiles, resident = (int64_t)cus * bpc;
+    int64_t g = std::max(std::min(T, resident), (T + DILBM3D_CHUNK - 1) / DILBM3D_CHUNK);
+    g = std::min<int64_t>(g, (int64_t)1 << 30);
+    s.grid = (int)std::max<int64_t>(8, (g + 7) / 8 * 8);
+  });
+  if (st != DILBM_OK) {
+    dilbm3d_destroy(h.release());
+    return st;
+  }
+  *out = h.release();
+  return DILBM_OK;
+}
+
+dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *pos,
+                                   const double *vel, const double *omega, const double *radius,
+                                   const double *density, const uint8_t *fixed) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    check_usable3(s);
+    if (n < 0) fail3(DILBM_EINVAL, "n must be >= 0");
+    if (n > 0 && (!pos || !radius || !density))
+      fail3(DILBM_EINVAL, "pos, radius and density are required");
+    for (int32_t b = 0; b < n; ++b) {
+      for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(pos[3 * b + a])) fail3(DILBM_EINVAL, "sphere position not finite");
+        if (vel && !std::isfinite(vel[3 * b + a])) fail3(DILBM_EINVAL, "sphere velocity not finite");
+        if (omega && !std::isfinite(omega[3 * b + a])) fail3(DILBM_EINVAL, "sphere spin not finite");
+      }
+      if (!(radius[b] > 0.0) || !std::isfinite(radius[b])) fail3(DILBM_EINVAL, "radius must be > 0");
+      if (!(density[b] > 0.0) || !std::isfinite(density[b]))
+        fail3(DILBM_EINVAL, "density must be > 0");
+    }
+    HIPCHK3(hipSetDevice(s->device));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+    const int nn = std::max(n, 1);
+    std::vector<double> state(9 * (size_t)nn, 0.0), cst(5 * (size_t)nn, 0.0);
+    const double N[3] = {(double)s->prm.nx, (double)s->prm.ny, (double)s->prm.nz};
+    for (int32_t b = 0; b < n; ++b) {
+      for (int a = 0; a < 3; ++a) {
+        double c = std::fmod(pos[3 * b + a], N[a]);
+        if (c < 0) c += N[a];
+        if (c >= N[a]) c -= N[a];
+        state[(size_t)a * n + b] = c;
+        state[(size_t)(3 + a) * n + b] = vel ? vel[3 * b + a] : 0.0;
+        state[(size_t)(6 + a) * n + b] = omega ? omega[3 * b + a] : 0.0;
+      }
+      const double R = radius[b], m = density[b] * 4.0 / 3.0 * M_PI * R * R * R;
+      cst[b] = R;
+      cst[(size_t)n + b] = density[b];
+      cst[2 * (size_t)n + b] = m;
+      cst[3 * (size_t)n + b] = 0.4 * m * R * R;
+      cst[4 * (size_t)n + b] = (fixed && fixed[b]) ? 1.0 : 0.0;
+    }
+    body_layout3(*s, n);
+    s->nb = n;
+    fill_desc3(*s);
+    HIPCHK3(launch_zero_bytes(s->body.ptr, (int64_t)s->body.bytes, s->stream));
+    const int p = s->parity;
+    if (n > 0) {
+      HIPCHK3(hipMemcpyAsync(s->h.bstate[p], state.data(), sizeof(double) * 9 * n,
+                             hipMemcpyHostToDevice, s->stream));
+      HIPCHK3(hipMemcpyAsync((void *)s->h.bconst, cst.data(), sizeof(double) * 5 * n,
+                             hipMemcpyHostToDevice, s->stream));
+    }
+    upload_desc3(*s);
+    HIPCHK3(launch3_bodies(true, n, s->stream, s->d_desc, p));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+    poll_errors3(*s);
+  });
+}
+
+dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev) {
+  if (!s || !f_dev) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    check_usable3(s);
+    HIPCHK3(hipSetDevice(s->device));
+    const int64_t count = (int64_t)kQ3 * s->prm.nx * s->prm.ny * s->prm.nz;
+    DevBuf tmp;
+    HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
+    HIPCHK3(hipMemcpyAsync(tmp.p, f_dev, sizeof(double) * count, hipMemcpyHostToDevice,
+                           s->stream));
+    HIPCHK3(launch3_set_pops(count, s->stream, s->d_desc, s->parity, (const double *)tmp.p));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+  });
+}
+
+dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev) {
+  if (!s || !f_dev) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    HIPCHK3(hipSetDevice(s->device));
+    const int64_t count = (int64_t)kQ3 * s->prm.nx * s->prm.ny * s->prm.nz;
+    DevBuf tmp;
+    HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
+    HIPCHK3(launch3_get_pops(count, s->stream, s->d_desc, s->parity, (double *)tmp.p));
+    HIPCHK3(hipMemcpyAsync(f_dev, tmp.p, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+  });
+}
+
+dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    check_usable3(s);
+    if (nsteps < 0) fail3(DILBM_EINVAL, "nsteps must be >= 0");
+    HIPCHK3(hipSetDevice(s->device));
+    for (int64_t k = 0; k < nsteps; ++k) {
+      const int p = s->parity;
+      if (s->timing) {
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        HIPCHK3(hipEventCreate(&ev.first));
+        HIPCHK3(hipEventCreate(&ev.second));
+        HIPCHK3(hipEventRecord(ev.first, s->stream));
+        HIPCHK3(launch3_collide(s->grid, s->stream, s->d_desc, p));
+        HIPCHK3(hipEventRecord(ev.second, s->stream));
+        s->events.push_back(ev);
+        if (s->events.size() >= 4096) collect_timing3(*s);
+      } else {
+        HIPCHK3(launch3_collide(s->grid, s->stream, s->d_desc, p));
+      }
+      HIPCHK3(launch3_bodies(false, s->nb, s->stream, s->d_desc, p));
+      s->parity ^= 1;
+      ++s->steps;
+    }
+    HIPCHK3(hipStreamSynchronize(s->stream));
+    poll_errors3(*s);
+  });
+}
+
+dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, double *uy,
+                                double *uz) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    HIPCHK3(hipSetDevice(s->device));
+    const int64_t n = (int64_t)s->prm.nx * s->prm.ny * s->prm.nz;
+    DevBuf tmp;
+    HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * 4 * n));
+    double *t = (double *)tmp.p;
+    HIPCHK3(launch3_fields(s->h.ntiles, s->stream, s->d_desc, s->parity, t, t + n, t + 2 * n,
+                           t + 3 * n));
+    double *outs[4] = {rho, ux, uy, uz};
+    for (int k = 0; k < 4; ++k)
+      if (outs[k])
+        HIPCHK3(hipMemcpyAsync(outs[k], t + k * n, sizeof(double) * n, hipMemcpyDeviceToHost,
+                               s->stream));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+  });
+}
+
+dilbm_status dilbm3d_get_particle_forces(dilbm3d_solver *s, double *force, double *torque) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    HIPCHK3(hipSetDevice(s->device));
+    const int n = s->nb;
+    if (n == 0) return;
+    // the last step (parity ^ 1) accumulated into acc[parity ^ 1]
+    std::vector<double> a(6 * (size_t)n);
+    HIPCHK3(hipMemcpyAsync(a.data(), s->h.acc[s->parity ^ 1], sizeof(double) * 6 * n,
+                           hipMemcpyDeviceToHost, s->stream));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < 3; ++c) {
+        if (force) force[3 * b + c] = s->steps ? a[6 * b + c] : 0.0;
+        if (torque) torque[3 * b + c] = s->steps ? a[6 * b + 3 + c] : 0.0;
+      }
+  });
+}
+
+dilbm_status dilbm3d_get_particles(dilbm3d_solver *s, double *pos, double *vel, double *omega) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    HIPCHK3(hipSetDevice(s->device));
+    const int n = s->nb;
+    if (n == 0) return;
+    std::vector<double> st(9 * (size_t)n);
+    HIPCHK3(hipMemcpyAsync(st.data(), s->h.bstate[s->parity], sizeof(double) * 9 * n,
+                           hipMemcpyDeviceToHost, s->stream));
+    HIPCHK3(hipStreamSynchronize(s->stream));
+    for (int b = 0; b < n; ++b)
+      for (int a = 0; a < 3; ++a) {
+        if (pos) pos[3 * b + a] = st[(size_t)a * n + b];
+        if (vel) vel[3 * b + a] = st[(size_t)(3 + a) * n + b];
+        if (omega) omega[3 * b + a] = st[(size_t)(6 + a) * n + b];
+      }
+  });
+}
+
+dilbm_status dilbm3d_get_wall_force(dilbm3d_solver *s, double *force) {
+  if (!s || !force) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    HIPCHK3(hipSetDevice(s->device));
+    double a[3] = {0.0, 0.0, 0.0};
+    if (s->steps) {
+      HIPCHK3(hipMemcpyAsync(a, s->h.acc[s->parity ^ 1] + 6 * (size_t)s->nb, sizeof(a),
+                             hipMemcpyDeviceToHost, s->stream));
+      HIPCHK3(hipStreamSynchronize(s->stream));
+    }
+    for (int c = 0; c < 3; ++c) force[c] = a[c];
+  });
+}
+
+dilbm_status dilbm3d_set_kernel_timing(dilbm3d_solver *s, int32_t enable) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    collect_timing3(*s);
+    s->timing = enable != 0;
+    s->timed_ms = 0.0;
+    s->timed_launches = 0;
+  });
+}
+
+dilbm_status dilbm3d_get_kernel_timing(dilbm3d_solver *s, double *collide_ms,
+                                       int64_t *launches) {
+  if (!s) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    collect_timing3(*s);
+    if (collide_ms) *collide_ms = s->timed_ms;
+    if (launches) *launches = s->timed_launches;
+  });
+}
+
+void dilbm3d_destroy(dilbm3d_solver *s) {
+  if (!s) return;
+  try {
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto &ev : s->events) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    free3(s->pops);
+    free3(s->body);
+    if (s->d_desc) (void)hipFree(s->d_desc);
+    if (s->d_err) (void)hipFree(s->d_err);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  } catch (...) {
+  }
+  delete s;
+}
+
+const char *dilbm3d_last_error(const dilbm3d_solver *s) {
+  if (!s) return g_thread_error3.c_str();
+  return s->last_error.c_str();
+}
+
+}  // extern "C"

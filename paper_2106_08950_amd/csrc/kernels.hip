@@ -19,6 +19,7 @@
 // contiguous band of tiles (neighbouring tiles share L2 lines at their edges).
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "dilbm_internal.h"
 #include "kernels.h"
 
@@ -36,17 +37,6 @@ constexpr int CX[kQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int CY[kQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr float KQ[kQ] = {16.0f, 4.0f, 4.0f, 4.0f, 4.0f, 1.0f, 1.0f, 1.0f, 1.0f};
 
-// Global-address-space access.  Pointers read from a descriptor are generic, and generic
-// accesses compile to flat instructions with a 64-bit address per lane; casting the
-// (uniform) plane base to the global address space and adding a 32-bit byte offset lets
-// each access be one global_load/global_store with a scalar base.
-#define DILBM_GLOBAL __attribute__((address_space(1)))
-// Constant address space: wave-uniform reads of data no kernel writes while it is read
-// compile to scalar loads.
-#define DILBM_CONST __attribute__((address_space(4)))
-
-// Buffer resource word 3 for raw 32-bit buffer access on gfx9-family parts.
-constexpr int kBufferFlags = 0x00020000;
 
 struct StoreF32 {
   using T = float;
@@ -192,87 +182,9 @@ __device__ __forceinline__ BodySnap load_snap(const DILBM_CONST BodySnap *q) {
   return BodySnap{q->x, q->y, q->u, q->v, q->w, q->r};
 }
 
-// FP64 sum over a wave (every lane must be active).  DPP moves combine lanes at distance
-// 1 and 2 (quad permutes), then mirrored half-rows and rows, without going through LDS;
-// the four row totals are read out and added, so every lane gets the total.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
-  const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
 
-// (1 + tanh(2 l / eps)) / 2 written as the logistic 1 / (1 + e^(-4 l / eps)); phi_k holds
-// 4 / eps * log2(e) so one hardware exp2 and one reciprocal do it.  (The hardware
-// exp2 flushes results below 2^-126 to zero, where phi is 1 to FP32 precision anyway.)
-__device__ __forceinline__ float phi_of(float l, float phi_k) {
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-l * phi_k));
-}
 
-__device__ __forceinline__ double min_image(double d, double n) {
-  if (d >= 0.5 * n) return d - n;
-  if (d < -0.5 * n) return d + n;
-  return d;
-}
 
-// Tile range along one axis: the tiles holding nodes k with |k + 0.5 - X| <= H (wrapped
-// onto [0, n)); up to two disjoint ranges [a0, a1] and [b0, b1].
-struct AxisTiles {
-  int a0, a1, b0, b1;
-};
-
-__device__ __forceinline__ AxisTiles axis_tiles(double X, double H, int n, int t, int ntiles) {
-  const double lo = ceil(X - H - 0.5);
-  const double hi = floor(X + H - 0.5);
-  if (hi - lo + 1.0 >= (double)n) return {0, ntiles - 1, 0, -1};
-  int lw = (int)(lo - (double)n * floor(lo / (double)n));
-  int hw = (int)(hi - (double)n * floor(hi / (double)n));
-  if (lw >= n) lw -= n;
-  if (hw >= n) hw -= n;
-  if (lw <= hw) return {lw / t, hw / t, 0, -1};
-  const int a0 = lw / t, b1 = hw / t;
-  if (b1 >= a0) return {0, ntiles - 1, 0, -1};
-  return {a0, ntiles - 1, 0, b1};
-}
-
-// Static split of [0, T) into contiguous chunks: workgroup b runs on XCD b % 8 and sweeps
-// chunk b / 8 of that XCD's contiguous eighth.  The grid holds several times the blocks a
-// CU keeps resident: those resident at any moment cover a compact band of tiles (tiles
-// share L2 lines at their edges, so a band re-reads little), and blocks that finish early
-// make room for the next ones, which evens out tiles made slow by bodies.
-struct WorkSplit {
-  int64_t begin, end;
-};
-
-__device__ __forceinline__ WorkSplit xcd_split(int64_t T) {
-  const int64_t nblk = gridDim.x >> 3;  // blocks per XCD group (the grid is a multiple of 8)
-  const int xcd = blockIdx.x & 7;
-  const int64_t per = T >> 3, r = T & 7;
-  const int64_t lo = xcd * per + (xcd < r ? xcd : r);
-  const int64_t count = per + (xcd < r ? 1 : 0);
-  const int64_t l = blockIdx.x >> 3;
-  WorkSplit w;
-  const int64_t chunk = (count + nblk - 1) / nblk;
-  w.begin = lo + min(count, l * chunk);
-  w.end = lo + min(count, (l + 1) * chunk);
-  return w;
-}
 
 enum TileMode { kModeStep = 0, kModeFields = 1 };
 

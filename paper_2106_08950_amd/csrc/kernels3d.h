@@ -1,0 +1,27 @@
+// kernels3d.h -- launch wrappers of the three-dimensional gfx950 kernels (internal to
+// libdilbm).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dilbm3d_internal.h"
+
+namespace dilbm {
+
+// one step's collide over all tiles of the solve (parity p), persistent grid
+hipError_t launch3_collide(int grid, hipStream_t stream, const Desc3 *desc, int p);
+// blocks of the collide kernel resident on one CU at once (0 on error)
+int collide3_blocks_per_cu();
+// rho and corrected u of parity p's state into [nz][ny][nx] device arrays
+hipError_t launch3_fields(int64_t ntiles, hipStream_t stream, const Desc3 *desc, int p,
+                          double *rho, double *ux, double *uy, double *uz);
+// the sphere step of parity p (or, bin_only, the binning of parity p's state)
+hipError_t launch3_bodies(bool bin_only, int nbodies, hipStream_t stream, const Desc3 *desc,
+                          int p);
+// populations in / out of parity p's buffer (count = 19 nx ny nz), device FP64 arrays
+hipError_t launch3_set_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+                            const double *fin);
+hipError_t launch3_get_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+                            double *fout);
+
+}  // namespace dilbm

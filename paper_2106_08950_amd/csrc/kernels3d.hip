@@ -1,0 +1,616 @@
+// kernels3d.hip -- gfx950 kernels of the three-dimensional DI-LBM step (D3Q19, spheres).
+//
+// The step is the one of kernels.hip carried to three dimensions (Section 2.3 of the
+// paper with Eqs. (13)-(19), (22)-(24), (28)-(29)); see dilbm3d.h for the readings.
+//
+//   k3_collide  one launch per step over all tiles (64 x 4 x 1 nodes, 256 threads, one
+//               node per lane): pull streaming of the 19 populations, moments, the solid
+//               field of the listed spheres and walls, Eq. (17), the Eq. (13) collision,
+//               write-back, and the per-sphere FP64 force and torque sums.
+//   k3_bodies   one wave per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
+//               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists.
+//   k3_fields   rho and the corrected velocity of Eq. (17) (output only).
+//
+// Populations are kept as g_i = 36 (f_i - w_i rho0) in FP32: the weights 1/3, 1/18, 1/36
+// enter as the exact integers K_i = 12, 2, 1, so every constant on the mass and momentum
+// path is exact in binary and what remains is unbiased round-to-nearest.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+#include "dilbm3d_internal.h"
+#include "dilbm_internal.h"
+#include "kernels3d.h"
+
+namespace dilbm {
+
+namespace {
+
+// D3Q19: rest, the six axis directions, the twelve edge directions; opposite directions
+// are neighbours (i, i + 1) for odd i.
+constexpr int C3X[kQ3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int C3Y[kQ3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int C3Z[kQ3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr float K3[kQ3] = {12.0f, 2.0f, 2.0f, 2.0f, 2.0f, 2.0f, 2.0f, 1.0f, 1.0f, 1.0f,
+                           1.0f,  1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f};
+constexpr float kInv36 = 1.0f / 36.0f;
+
+// x / 36 correctly rounded: the reciprocal product corrected by one FMA residual step
+__device__ __forceinline__ float div36_3(float x) {
+  const float q = x * kInv36;
+  return fmaf(fmaf(-36.0f, q, x), kInv36, q);
+}
+
+__device__ __forceinline__ SphereSnap load_snap3(const DILBM_CONST SphereSnap *q) {
+  SphereSnap s;
+  s.x = q->x;
+  s.y = q->y;
+  s.z = q->z;
+  s.u = q->u;
+  s.v = q->v;
+  s.w = q->w;
+  s.ox = q->ox;
+  s.oy = q->oy;
+  s.oz = q->oz;
+  s.r = q->r;
+  s.pad[0] = s.pad[1] = 0.0f;
+  return s;
+}
+
+__device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
+
+enum Mode3 { kStep3 = 0, kFields3 = 1 };
+
+// One tile.  MODE kStep3: the full step; kFields3: rho and u of the current state.
+template <int MODE>
+__device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
+                                      double *__restrict__ out_rho, double *__restrict__ out_ux,
+                                      double *__restrict__ out_uy,
+                                      double *__restrict__ out_uz) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int64_t trow = lt / d.tiles_x;
+  const int txi = (int)(lt - trow * d.tiles_x);
+  const int z = (int)(trow / d.tiles_y);
+  const int tyi = (int)(trow - (int64_t)z * d.tiles_y);
+  const int x0 = txi * kTile3X, y0 = tyi * kTile3Y;
+  const int x = x0 + lane;
+  const int y = __builtin_amdgcn_readfirstlane(y0 + (tid >> 6));  // a wave is one row
+  const bool valid = x < nx && y < ny;
+  const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+
+  // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) ------------------------------
+  // one buffer resource per population buffer; the row of every direction is
+  // wave-uniform (scalar offset), the column is one of three per-lane offsets
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
+  const uint32_t pb = plane * 4u;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(kQ3 * pb), kBufferFlags);
+  const uint32_t vx0 = (uint32_t)xc * 4u;
+  const uint32_t vxm = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * 4u;  // source x - 1
+  const uint32_t vxp = (uint32_t)(xc + 1 == nx ? 0 : xc + 1) * 4u;  // source x + 1
+  uint32_t row[3][3];  // row[dz + 1][dy + 1]: byte offset of row (y + dy, z + dz)
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+      row[dz + 1][dy + 1] = __builtin_amdgcn_readfirstlane(
+          ((uint32_t)wrapi(z + dz, nz) * (uint32_t)ny + (uint32_t)wrapi(yc + dy, ny)) *
+          (uint32_t)nx * 4u);
+  float g[kQ3];
+#pragma unroll
+  for (int i = 0; i < kQ3; ++i) {
+    const uint32_t v = C3X[i] == 0 ? vx0 : (C3X[i] > 0 ? vxm : vxp);
+    const uint32_t s = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
+    g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, s, 0));
+  }
+
+  // the tile's sphere count, its first listed sphere and that sphere's snapshot (scalar
+  // loads in flight with the populations; the first entry is clamped into range for the
+  // snapshot load and used only when the count lists it)
+  const int nb = min(*(const DILBM_CONST int32_t *)(d.tile_count[p] + lt), d.list_cap);
+  const int nbs = d.nbodies;
+  const DILBM_CONST int32_t *list =
+      (const DILBM_CONST int32_t *)(d.tile_list[p] + lt * d.list_cap);
+  const DILBM_CONST SphereSnap *snap = (const DILBM_CONST SphereSnap *)d.bsnap[p];
+  int e0 = -1;
+  SphereSnap s0{};
+  if (nbs > 0) {
+    e0 = list[0];
+    s0 = load_snap3(snap + min(max(e0, 0), nbs - 1));
+  }
+  if (MODE == kStep3) {
+    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
+    if (lt == 0) {
+      double *a = d.acc[p ^ 1];
+      for (int i = tid; i < 6 * (nbs + 1); i += 256) a[i] = 0.0;
+    }
+  }
+
+  // ---- moments, Eqs. (5) and (16), in g units (D = 36 drho, J = 36 j) ------------------
+  float D = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ3; ++i) {
+    D += g[i];
+    if (C3X[i]) Jx += C3X[i] > 0 ? g[i] : -g[i];
+    if (C3Y[i]) Jy += C3Y[i] > 0 ? g[i] : -g[i];
+    if (C3Z[i]) Jz += C3Z[i] > 0 ? g[i] : -g[i];
+  }
+  const float R = 36.0f * d.rho0 + D;  // 36 rho
+  const float rho = R * kInv36;
+  const float drho = D * kInv36;
+  float Rinv = __builtin_amdgcn_rcpf(R);
+  Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
+  // 36 rho u* = 36 (j + G/2)
+  const float Jgx = Jx + 18.0f * d.Gx, Jgy = Jy + 18.0f * d.Gy, Jgz = Jz + 18.0f * d.Gz;
+  const float usx = Jgx * Rinv, usy = Jgy * Rinv, usz = Jgz * Rinv;
+
+  // ---- diffuse solid field, Eq. (14), and its sums over spheres and walls ---------------
+  float Phi = 0.f, Ax = 0.f, Ay = 0.f, Az = 0.f;
+  float Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
+  const float lcut = d.lcut, phik = d.phi_k, kap = d.kappa;
+  // walls: does this tile reach into the support of a slab? (axis order x, y, z)
+  const bool wx = (d.wall_mask & 2u) && (x0 < d.wall_lo[0] || x0 + kTile3X > d.wall_hi[0]);
+  const bool wy = (d.wall_mask & 1u) && (y0 < d.wall_lo[1] || y0 + kTile3Y > d.wall_hi[1]);
+  const bool wz = (d.wall_mask & 4u) && (z < d.wall_lo[2] || z + 1 > d.wall_hi[2]);
+  const bool any_solid = nb > 0 || wx || wy || wz;
+  if (any_solid) {
+    float lw[3] = {-1e30f, -1e30f, -1e30f};
+    if (wx) {
+      float c = (float)xc + 0.5f;
+      if (c >= 0.5f * (float)nx) c -= (float)nx;
+      lw[0] = d.wall_h - fabsf(c);
+    }
+    if (wy) {
+      float c = (float)yc + 0.5f;
+      if (c >= 0.5f * (float)ny) c -= (float)ny;
+      lw[1] = d.wall_h - fabsf(c);
+    }
+    if (wz) {
+      float c = (float)z + 0.5f;
+      if (c >= 0.5f * (float)nz) c -= (float)nz;
+      lw[2] = d.wall_h - fabsf(c);
+    }
+    const double xn = (double)xc + 0.5, yn = (double)yc + 0.5, zn = (double)z + 0.5;
+    const double dnx = nx, dny = ny, dnz = nz;
+    auto body = [&](const int j, int &e, SphereSnap &sj) -> bool {
+      e = j == 0 ? e0 : list[j];
+      if (e < 0 || e >= nbs) {
+        if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
+        return false;
+      }
+      if (j == 0)
+        sj = s0;
+      else
+        sj = load_snap3(snap + e);
+      return true;
+    };
+    // pass 1 (only where several supports meet): S = sum phi_b, w_b = phi_b min(1, 1/S)
+    float scale = 1.0f;
+    const int nsolid = nb + (wx ? 1 : 0) + (wy ? 1 : 0) + (wz ? 1 : 0);
+    if (nsolid > 1) {
+      float S = 0.f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (lw[a] >= lcut) S += phi_of(lw[a], phik);
+      for (int j = 0; j < nb; ++j) {
+        int e;
+        SphereSnap sj;
+        if (!body(j, e, sj)) continue;
+        const float rx = (float)min_image(xn - sj.x, dnx);
+        const float ry = (float)min_image(yn - sj.y, dny);
+        const float rz = (float)min_image(zn - sj.z, dnz);
+        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
+        if (l >= lcut) S += phi_of(l, phik);
+      }
+      scale = S > 1.0f ? 1.0f / S : 1.0f;
+    }
+    // pass 2: weights, the sums of Eqs. (15) and (17), and per-sphere force and torque
+    // (each wave sums its lanes in FP64 and adds the totals to the accumulators)
+    double *__restrict__ acc = d.acc[p];
+    for (int j = 0; j < nb; ++j) {
+      int e;
+      SphereSnap sj;
+      if (!body(j, e, sj)) continue;
+      const float rx = (float)min_image(xn - sj.x, dnx);
+      const float ry = (float)min_image(yn - sj.y, dny);
+      const float rz = (float)min_image(zn - sj.z, dnz);
+      const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+      if (valid && l >= lcut) {
+        const float w = scale * phi_of(l, phik);
+        // rigid-body velocity of the solid at the node: U + omega x r
+        const float vx = sj.u + (sj.oy * rz - sj.oz * ry);
+        const float vy = sj.v + (sj.oz * rx - sj.ox * rz);
+        const float vz = sj.w + (sj.ox * ry - sj.oy * rx);
+        Phi += w;
+        Ax += w * vx;
+        Ay += w * vy;
+        Az += w * vz;
+        Mxx += w * vx * vx;
+        Myy += w * vy * vy;
+        Mzz += w * vz * vz;
+        Mxy += w * vx * vy;
+        Mxz += w * vx * vz;
+        Myz += w * vy * vz;
+        // force on the sphere: -w rho (u_s - u*) (times the Eq. (18) scale)
+        const float k = -kap * w * rho;
+        fx = k * (vx - usx);
+        fy = k * (vy - usy);
+        fz = k * (vz - usz);
+      }
+      if (MODE == kStep3 && __ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0) {
+        const double sx = wave_sum((double)fx), sy = wave_sum((double)fy);
+        const double sz = wave_sum((double)fz);
+        const double tx = wave_sum((double)(ry * fz - rz * fy));
+        const double ty = wave_sum((double)(rz * fx - rx * fz));
+        const double tz = wave_sum((double)(rx * fy - ry * fx));
+        if (lane == 0) {
+          double *a = acc + 6 * e;
+          unsafeAtomicAdd(a + 0, sx);
+          unsafeAtomicAdd(a + 1, sy);
+          unsafeAtomicAdd(a + 2, sz);
+          unsafeAtomicAdd(a + 3, tx);
+          unsafeAtomicAdd(a + 4, ty);
+          unsafeAtomicAdd(a + 5, tz);
+        }
+      }
+    }
+    // wall slabs: solid velocity 0; their force goes to the last accumulator slot
+    if (wx || wy || wz) {
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (valid && lw[a] >= lcut) {
+          const float w = scale * phi_of(lw[a], phik);
+          Phi += w;
+          const float k = kap * w * rho;
+          fx += k * usx;
+          fy += k * usy;
+          fz += k * usz;
+        }
+      }
+      if (MODE == kStep3 && __ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0) {
+        const double sx = wave_sum((double)fx), sy = wave_sum((double)fy);
+        const double sz = wave_sum((double)fz);
+        if (lane == 0) {
+          double *a = acc + 6 * nbs;
+          unsafeAtomicAdd(a + 0, sx);
+          unsafeAtomicAdd(a + 1, sy);
+          unsafeAtomicAdd(a + 2, sz);
+        }
+      }
+    }
+  }
+
+  // ---- corrected velocity, Eq. (17): 36 rho u = 36 rho u* + 18 P, P = rho (A - Phi u*) --
+  const float Px = rho * (Ax - Phi * usx), Py = rho * (Ay - Phi * usy);
+  const float Pz = rho * (Az - Phi * usz);
+  const float Mx = fmaf(18.0f, Px, Jgx), My = fmaf(18.0f, Py, Jgy), Mz = fmaf(18.0f, Pz, Jgz);
+  const float ux = Mx * Rinv, uy = My * Rinv, uz = Mz * Rinv;
+
+  if (MODE == kFields3) {
+    if (valid) {
+      const int64_t o = ((int64_t)z * ny + y) * nx + x;
+      out_rho[o] = (double)rho;
+      out_ux[o] = (double)ux;
+      out_uy[o] = (double)uy;
+      out_uz[o] = (double)uz;
+    }
+    return;
+  }
+
+  // ---- collision, Eq. (13), in g units ------------------------------------------------
+  // g_i* = g_i + omega (geq_i - g_i) + khalf K_i S_i with
+  //   geq_i = K_i [drho + 3 c.(rho u) + rho (4.5 (c.u)^2 - 1.5 u.u)],
+  //   S_i   = 3 (c - u).G + 9 (c.u)(c.G)            (uniform body force)
+  //         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q           (spheres and walls, Eq. (15) summed)
+  // taken per pair of opposite directions, which share the even part.
+  const float mx = div36_3(Mx), my = div36_3(My), mz = div36_3(Mz);  // rho u
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float Gx = d.Gx, Gy = d.Gy, Gz = d.Gz;
+  const float uG = ux * Gx + uy * Gy + uz * Gz;
+  float Qxx = 0.f, Qyy = 0.f, Qzz = 0.f, Qxy = 0.f, Qxz = 0.f, Qyz = 0.f, trQ = 0.f;
+  if (any_solid) {
+    Qxx = rho * (Mxx - Phi * usx * usx);
+    Qyy = rho * (Myy - Phi * usy * usy);
+    Qzz = rho * (Mzz - Phi * usz * usz);
+    Qxy = rho * (Mxy - Phi * usx * usy);
+    Qxz = rho * (Mxz - Phi * usx * usz);
+    Qyz = rho * (Myz - Phi * usy * usz);
+    trQ = Qxx + Qyy + Qzz;
+  }
+  const float om = d.omega, kh = d.khalf;
+  const float base = drho - 1.5f * rho * uu;            // even part shared by all i
+  const float sbase = -3.0f * uG - 1.5f * trQ;          // even part of S shared by all i
+  float out[kQ3];
+  out[0] = g[0] + om * (K3[0] * base - g[0]) + kh * K3[0] * sbase;
+#pragma unroll
+  for (int i = 1; i < kQ3; i += 2) {
+    const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
+    const float cu = cx * ux + cy * uy + cz * uz;
+    const float cm = cx * mx + cy * my + cz * mz;
+    const float cG = cx * Gx + cy * Gy + cz * Gz;
+    const float cP = cx * Px + cy * Py + cz * Pz;
+    const float cQc = cx * cx * Qxx + cy * cy * Qyy + cz * cz * Qzz +
+                      2.0f * (cx * cy * Qxy + cx * cz * Qxz + cy * cz * Qyz);
+    const float K = K3[i];
+    const float ev = K * (base + 4.5f * rho * cu * cu);     // even part of geq
+    const float od = K * 3.0f * cm;                           // odd part of geq
+    const float sev = K * (sbase + 9.0f * cu * cG + 4.5f * cQc);
+    const float sod = K * 3.0f * (cG + cP);
+    out[i] = g[i] + om * (ev + od - g[i]) + kh * (sev + sod);
+    out[i + 1] = g[i + 1] + om * (ev - od - g[i + 1]) + kh * (sev - sod);
+  }
+
+  const float vv = ux * ux + uy * uy + uz * uz;
+  if (__ballot(valid && !(rho > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
+    atomicOr(d.err, (int32_t)kErrUnstable);
+  if (valid) {
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)d.pop[p ^ 1], (short)0, (int)(kQ3 * pb), kBufferFlags);
+    const uint32_t s0r = row[1][1];
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
+                                            (uint32_t)i * pb + s0r, 0);
+  }
+}
+
+__global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
+    const Desc3 *__restrict__ desc, int p) {
+  const Desc3 &d = *desc;
+  const WorkSplit ws = xcd_split(d.ntiles);
+  // odd chunks are walked backwards, so neighbouring chunks reach their common edge
+  // together (the x-shifted loads share cache lines across it)
+  const bool rev = (blockIdx.x >> 3) & 1;
+  for (int64_t i = ws.begin; i < ws.end; ++i) {
+    const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
+    tile3<kStep3>(d, t, p, nullptr, nullptr, nullptr, nullptr);
+  }
+}
+
+__global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
+                                                 double *__restrict__ rho,
+                                                 double *__restrict__ ux,
+                                                 double *__restrict__ uy,
+                                                 double *__restrict__ uz) {
+  const Desc3 &d = *desc;
+  for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) tile3<kFields3>(d, t, p, rho, ux, uy, uz);
+}
+
+// One wave per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
+// parity p (after set_particles); otherwise do the sphere step of parity p and bin the
+// moved spheres into the lists of parity p ^ 1.
+template <bool BIN_ONLY>
+__global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
+  const Desc3 &d = *desc;
+  const int lane = threadIdx.x & 63;
+  const int nb = d.nbodies;
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= nb) return;  // wave-uniform
+  const double *st = d.bstate[p];
+  const double N[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
+  double X[3] = {st[b], st[nb + b], st[2 * nb + b]};
+  double U[3] = {st[3 * nb + b], st[4 * nb + b], st[5 * nb + b]};
+  double W[3] = {st[6 * nb + b], st[7 * nb + b], st[8 * nb + b]};
+  const double R = d.bconst[b], rho_s = d.bconst[nb + b];
+  const double m = d.bconst[2 * nb + b], I = d.bconst[3 * nb + b];
+  const bool fixed = d.bconst[4 * nb + b] != 0.0;
+  int q = p;
+  if (!BIN_ONLY) {
+    // hydrodynamic force and torque of the step (read now: in flight with the pair loads)
+    const double *acc = d.acc[p] + 6 * b;
+    double F[3] = {acc[0], acc[1], acc[2]};
+    const double T[3] = {acc[3], acc[4], acc[5]};
+    // Eq. (28): repulsion from every other sphere (minimum image); partners are read
+    // kU rounds of 64 at a time so the loop pays one memory latency per batch
+    double f[3] = {0.0, 0.0, 0.0};
+    constexpr int kU = 8;
+    for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
+      double px[kU], py[kU], pz[kU], pr[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = min(j0 + 64 * u + lane, nb - 1);  // clamped: a valid index
+        px[u] = st[j];
+        py[u] = st[nb + j];
+        pz[u] = st[2 * nb + j];
+        pr[u] = d.bconst[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + 64 * u + lane;
+        const double dx = min_image(X[0] - px[u], N[0]);
+        const double dy = min_image(X[1] - py[u], N[1]);
+        const double dz = min_image(X[2] - pz[u], N[2]);
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double rr = R + pr[u];
+        if (j >= nb || j == b || d2 > (rr + d.xi) * (rr + d.xi)) continue;
+        const double dist = sqrt(d2);
+        const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
+                                     : (rr + d.xi - dist) * (rr + d.xi - dist) * d.inv_eps_p;
+        f[0] += kk * dx;
+        f[1] += kk * dy;
+        f[2] += kk * dz;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] = wave_sum(f[a]);
+    // Eq. (29): the image across the nearer surface of each wall slab
+    const double hw = d.wall_h_d;
+    const int axis_of_bit[3] = {1, 0, 2};
+    for (int bit = 0; bit < 3; ++bit) {
+      if (!(d.wall_mask & (1u << bit))) continue;
+      const int a = axis_of_bit[bit];
+      const double c = X[a], n = N[a];
+      const double dd = (c - hw <= (n - hw) - c) ? 2.0 * (c - hw) : -2.0 * ((n - hw) - c);
+      const double dist = fabs(dd);
+      double kk = 0.0;
+      if (dist <= 2.0 * R)
+        kk = (2.0 * R - dist) * d.inv_eps_w1;
+      else if (dist <= 2.0 * R + d.xi)
+        kk = (2.0 * R + d.xi - dist) * (2.0 * R + d.xi - dist) * d.inv_eps_w;
+      f[a] += kk * dd;
+    }
+    // Eq. (22): hydrodynamic force plus (rho_f / rho_s - 1) m g, rho_f = rho0
+    const double gfac = (d.rho0_d / rho_s - 1.0) * m;
+    F[0] += f[0] + gfac * d.gx;
+    F[1] += f[1] + gfac * d.gy;
+    F[2] += f[2] + gfac * d.gz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (fixed) {
+        X[a] += U[a];  // prescribed motion
+      } else {
+        // Eqs. (22)-(24), dt = 1: Euler velocity and spin, trapezoidal position
+        const double Un = U[a] + F[a] / m;
+        X[a] += 0.5 * (U[a] + Un);
+        U[a] = Un;
+        W[a] += T[a] / I;
+      }
+      X[a] = X[a] - N[a] * floor(X[a] / N[a]);
+      if (X[a] >= N[a]) X[a] -= N[a];
+    }
+    q = p ^ 1;
+    if (lane == 0) {
+      double *sn = d.bstate[q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sn[a * nb + b] = X[a];
+        sn[(3 + a) * nb + b] = U[a];
+        sn[(6 + a) * nb + b] = W[a];
+      }
+    }
+  }
+  if (lane == 0) {
+    SphereSnap s;
+    s.x = X[0];
+    s.y = X[1];
+    s.z = X[2];
+    s.u = (float)U[0];
+    s.v = (float)U[1];
+    s.w = (float)U[2];
+    s.ox = (float)W[0];
+    s.oy = (float)W[1];
+    s.oz = (float)W[2];
+    s.r = (float)R;
+    s.pad[0] = s.pad[1] = 0.0f;
+    d.bsnap[q][b] = s;
+  }
+  // a blown-up sphere is flagged instead of binned (its tile indices would be garbage)
+  if (!isfinite(X[0]) || !isfinite(X[1]) || !isfinite(X[2]) || !isfinite(R)) {
+    if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
+    return;
+  }
+  // bin into the tile lists of parity q: every tile holding a node within R + support
+  const double H = R + d.support + 1e-3;
+  const AxisTiles ax = axis_tiles(X[0], H, d.nx, kTile3X, d.tiles_x);
+  const AxisTiles ay = axis_tiles(X[1], H, d.ny, kTile3Y, d.tiles_y);
+  const AxisTiles az = axis_tiles(X[2], H, d.nz, 1, d.nz);
+  const int na1 = ax.a1 - ax.a0 + 1, nb1 = ay.a1 - ay.a0 + 1, nc1 = az.a1 - az.a0 + 1;
+  const int na = na1 + max(0, ax.b1 - ax.b0 + 1);
+  const int nbb = nb1 + max(0, ay.b1 - ay.b0 + 1);
+  const int nc = nc1 + max(0, az.b1 - az.b0 + 1);
+  int32_t *cnt = d.tile_count[q];
+  int32_t *lst = d.tile_list[q];
+  for (int e = lane; e < na * nbb * nc; e += 64) {
+    const int ia = e % na, r = e / na;
+    const int ib = r % nbb, ic = r / nbb;
+    const int tx = ia < na1 ? ax.a0 + ia : ax.b0 + (ia - na1);
+    const int ty = ib < nb1 ? ay.a0 + ib : ay.b0 + (ib - nb1);
+    const int tz = ic < nc1 ? az.a0 + ic : az.b0 + (ic - nc1);
+    const int64_t tile = ((int64_t)tz * d.tiles_y + ty) * d.tiles_x + tx;
+    const int slot = atomicAdd(&cnt[tile], 1);
+    if (slot < d.list_cap)
+      lst[tile * d.list_cap + slot] = b;
+    else
+      atomicOr(d.err, (int32_t)kErrCapacity);
+  }
+}
+
+// Populations in and out: fin / fout are [19][nz][ny][nx] FP64 deviations f_i - w_i rho0
+// of the current state; node x keeps f_i at x - c_i (pull layout), as g = 36 (f - w rho0).
+__global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, const double *__restrict__ fin) {
+  const Desc3 &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / plane);
+    const int64_t n = e - i * plane;
+    const int x = (int)(n % d.nx);
+    const int64_t r = n / d.nx;
+    const int y = (int)(r % d.ny), z = (int)(r / d.ny);
+    const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
+    const int zs = wrapi(z - C3Z[i], d.nz);
+    d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] = (float)(36.0 * fin[e]);
+  }
+}
+
+__global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, double *__restrict__ fout) {
+  const Desc3 &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / plane);
+    const int64_t n = e - i * plane;
+    const int x = (int)(n % d.nx);
+    const int64_t r = n / d.nx;
+    const int y = (int)(r % d.ny), z = (int)(r / d.ny);
+    const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
+    const int zs = wrapi(z - C3Z[i], d.nz);
+    fout[e] = (double)d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] / 36.0;
+  }
+}
+
+int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap)); }
+
+}  // namespace
+
+hipError_t launch3_collide(int grid, hipStream_t stream, const Desc3 *desc, int p) {
+  hipLaunchKernelGGL(k3_collide, dim3(grid), dim3(256), 0, stream, desc, p);
+  return hipGetLastError();
+}
+
+int collide3_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(k3_collide),
+                                                   256, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
+hipError_t launch3_fields(int64_t ntiles, hipStream_t stream, const Desc3 *desc, int p,
+                          double *rho, double *ux, double *uy, double *uz) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
+  hipLaunchKernelGGL(k3_fields, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
+  return hipGetLastError();
+}
+
+hipError_t launch3_bodies(bool bin_only, int nbodies, hipStream_t stream, const Desc3 *desc,
+                          int p) {
+  if (nbodies <= 0) return hipSuccess;
+  const int grid = (nbodies + 3) / 4;
+  if (bin_only)
+    hipLaunchKernelGGL(k3_bodies<true>, dim3(grid), dim3(256), 0, stream, desc, p);
+  else
+    hipLaunchKernelGGL(k3_bodies<false>, dim3(grid), dim3(256), 0, stream, desc, p);
+  return hipGetLastError();
+}
+
+hipError_t launch3_set_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+                            const double *fin) {
+  hipLaunchKernelGGL(k3_set_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
+                     fin);
+  return hipGetLastError();
+}
+
+hipError_t launch3_get_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+                            double *fout) {
+  hipLaunchKernelGGL(k3_get_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
+                     fout);
+  return hipGetLastError();
+}
+
+}  // namespace dilbm
