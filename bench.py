@@ -1,7 +1,7 @@
 """Benchmark of the DI-LBM time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs fp32,fp16,open_ends,batched,served]
+                    [--legs fp32,fp16,open_ends,suspension3d,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -12,6 +12,8 @@ HBM before the timed region starts.  Further legs, reported in the same JSON lin
 * fp16: the same workload with FP16 storage (36 B per node update);
 * open_ends: a 4096 x 2048 inflow channel (velocity inlet, zero-gradient outlet, 300
   fixed discs), FP32;
+* suspension3d: the three-dimensional path, 256^3 D3Q19 nodes with 400 free spheres
+  (seed 8), FP32 (152 B per node update);
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -139,6 +141,35 @@ def single_solve(wl, storage, steps, warmup, tile, stream):
     return wl.nodes * steps / dt / 1e6, dt, collide_ms / max(launches, 1), launches
 
 
+def suspension3d_leg(steps, warmup, stream):
+    """The three-dimensional path: 256^3 periodic D3Q19 nodes with 400 free spheres, FP32
+    (19 x 4 bytes read + 19 x 4 written = 152 B per node update)."""
+    import torch
+
+    from paper_2106_08950_amd import dilbm3d, inputs3d
+
+    w3 = inputs3d.suspension3d()
+    s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w3, device=0, stream=stream.cuda_stream))
+    s.set_particles(w3.pos, w3.radius, w3.density, w3.vel, w3.omega, w3.fixed)
+    s.step(warmup)
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n = s.kernel_timing()
+    s.close()
+    avg = ms / max(n, 1)
+    a3 = 152 * w3.nodes / (avg * 1e-3) / 1e9
+    return {"workload": w3.name, "value": round(w3.nodes * steps / dt / 1e6, 1),
+            "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
+            "roofline": {"bound": "hbm", "achieved": round(a3, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(a3 / HBM_PEAK_GBS, 4),
+                         "kernel": "k3_collide", "bytes_per_node": 152,
+                         "avg_launch_ms": round(avg, 5), "launches": n}}
+
+
 def batched_leg(stream, steps_per_solve=2000):
     """256-solve ensemble: one pool vs one plain solve after another."""
     import torch
@@ -207,7 +238,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--legs", default="fp32,fp16,open_ends,batched,served")
+    ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--served-count", type=int, default=500)
@@ -282,6 +313,9 @@ def main():
                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                          "frac": round(ao / HBM_PEAK_GBS, 4),
                                          "bytes_per_node": 72, "avg_launch_ms": round(avgo, 5)}}
+    if "suspension3d" in legs:
+        log("suspension3d")
+        out["suspension3d"] = suspension3d_leg(args.steps // 2, args.warmup, stream)
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

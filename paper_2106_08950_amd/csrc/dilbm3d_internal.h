@@ -5,7 +5,7 @@
 //   pop[2]        two population buffers, structure of arrays [19][nz][ny][nx] of FP32
 //                 deviations d_i = f_i - w_i rho0.  Pull scheme: node x at time t_n finds
 //                 f_i in pop[p][i][x - c_i].
-//   tile_count[2] per tile (64 x 4 x 1 nodes), the number of spheres whose phi support
+//   tile_count[2] per tile (64 x 4 x 1 or 256 x 1 x 1 nodes), the number of spheres whose phi support
 //                 may touch it; tile_list[2]: `list_cap` sphere indices per tile
 //   bstate[2]     sphere state SoA [9][nb]: x, y, z, u, v, w, omega_x, omega_y, omega_z
 //   bconst        sphere constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
@@ -23,7 +23,11 @@
 namespace dilbm {
 
 constexpr int kQ3 = 19;
-constexpr int kTile3X = 64, kTile3Y = 4;  // one tile: 64 x 4 x 1 nodes, 256 threads
+// Tiles are tile_x x (256 / tile_x) x 1 nodes, 256 threads: tile_x = 256 (a whole row of
+// up to 256 nodes per block) when nx >= DILBM3D_WIDE_MIN, else 64 (64 x 4 x 1).
+#ifndef DILBM3D_WIDE_MIN
+#define DILBM3D_WIDE_MIN 192
+#endif
 constexpr int kMaxListCap3 = 1024;
 
 // Register budget of the collide kernel: compiled for at least this many waves per SIMD.
@@ -49,6 +53,7 @@ struct SphereSnap {
 
 struct Desc3 {
   int32_t nx, ny, nz;
+  int32_t tile_x;     // 64 or 256
   int32_t tiles_x, tiles_y;
   int64_t ntiles;
   int32_t nbodies;

@@ -8,13 +8,14 @@
 
 namespace dilbm {
 
-// one step's collide over all tiles of the solve (parity p), persistent grid
-hipError_t launch3_collide(int grid, hipStream_t stream, const Desc3 *desc, int p);
+// one step's collide over all tiles of the solve (parity p), persistent grid; tile_x is
+// the tile width (64: tiles of 64 x 4 x 1 nodes; 256: 256 x 1 x 1)
+hipError_t launch3_collide(int tile_x, int grid, hipStream_t stream, const Desc3 *desc, int p);
 // blocks of the collide kernel resident on one CU at once (0 on error)
-int collide3_blocks_per_cu();
+int collide3_blocks_per_cu(int tile_x);
 // rho and corrected u of parity p's state into [nz][ny][nx] device arrays
-hipError_t launch3_fields(int64_t ntiles, hipStream_t stream, const Desc3 *desc, int p,
-                          double *rho, double *ux, double *uy, double *uz);
+hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const Desc3 *desc,
+                          int p, double *rho, double *ux, double *uy, double *uz);
 // the sphere step of parity p (or, bin_only, the binning of parity p's state)
 hipError_t launch3_bodies(bool bin_only, int nbodies, hipStream_t stream, const Desc3 *desc,
                           int p);

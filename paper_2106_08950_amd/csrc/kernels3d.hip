@@ -62,8 +62,9 @@ __device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >
 
 enum Mode3 { kStep3 = 0, kFields3 = 1 };
 
-// One tile.  MODE kStep3: the full step; kFields3: rho and u of the current state.
-template <int MODE>
+// One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
+// MODE kStep3: the full step; kFields3: rho and u of the current state.
+template <int MODE, int TX>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
                                       double *__restrict__ out_uy,
@@ -75,9 +76,10 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const int txi = (int)(lt - trow * d.tiles_x);
   const int z = (int)(trow / d.tiles_y);
   const int tyi = (int)(trow - (int64_t)z * d.tiles_y);
-  const int x0 = txi * kTile3X, y0 = tyi * kTile3Y;
-  const int x = x0 + lane;
-  const int y = __builtin_amdgcn_readfirstlane(y0 + (tid >> 6));  // a wave is one row
+  constexpr int TY = 256 / TX;
+  const int x0 = txi * TX, y0 = tyi * TY;
+  const int x = x0 + tid % TX;
+  const int y = __builtin_amdgcn_readfirstlane(y0 + tid / TX);  // a wave is part of one row
   const bool valid = x < nx && y < ny;
   const int xc = min(x, nx - 1), yc = min(y, ny - 1);
 
@@ -152,8 +154,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   float Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
   const float lcut = d.lcut, phik = d.phi_k, kap = d.kappa;
   // walls: does this tile reach into the support of a slab? (axis order x, y, z)
-  const bool wx = (d.wall_mask & 2u) && (x0 < d.wall_lo[0] || x0 + kTile3X > d.wall_hi[0]);
-  const bool wy = (d.wall_mask & 1u) && (y0 < d.wall_lo[1] || y0 + kTile3Y > d.wall_hi[1]);
+  const bool wx = (d.wall_mask & 2u) && (x0 < d.wall_lo[0] || x0 + TX > d.wall_hi[0]);
+  const bool wy = (d.wall_mask & 1u) && (y0 < d.wall_lo[1] || y0 + TY > d.wall_hi[1]);
   const bool wz = (d.wall_mask & 4u) && (z < d.wall_lo[2] || z + 1 > d.wall_hi[2]);
   const bool any_solid = nb > 0 || wx || wy || wz;
   if (any_solid) {
@@ -175,6 +177,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     }
     const double xn = (double)xc + 0.5, yn = (double)yc + 0.5, zn = (double)z + 0.5;
     const double dnx = nx, dny = ny, dnz = nz;
+    // listed sphere j: its index (checked: a bad entry is flagged and skipped) and snapshot
     auto body = [&](const int j, int &e, SphereSnap &sj) -> bool {
       e = j == 0 ? e0 : list[j];
       if (e < 0 || e >= nbs) {
@@ -359,6 +362,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   }
 }
 
+template <int TX>
 __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
     const Desc3 *__restrict__ desc, int p) {
   const Desc3 &d = *desc;
@@ -368,17 +372,19 @@ __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3>(d, t, p, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX>(d, t, p, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
+template <int TX>
 __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
                                                  double *__restrict__ rho,
                                                  double *__restrict__ ux,
                                                  double *__restrict__ uy,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
-  for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x) tile3<kFields3>(d, t, p, rho, ux, uy, uz);
+  for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
+    tile3<kFields3, TX>(d, t, p, rho, ux, uy, uz);
 }
 
 // One wave per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
@@ -506,8 +512,8 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   }
   // bin into the tile lists of parity q: every tile holding a node within R + support
   const double H = R + d.support + 1e-3;
-  const AxisTiles ax = axis_tiles(X[0], H, d.nx, kTile3X, d.tiles_x);
-  const AxisTiles ay = axis_tiles(X[1], H, d.ny, kTile3Y, d.tiles_y);
+  const AxisTiles ax = axis_tiles(X[0], H, d.nx, d.tile_x, d.tiles_x);
+  const AxisTiles ay = axis_tiles(X[1], H, d.ny, 256 / d.tile_x, d.tiles_y);
   const AxisTiles az = axis_tiles(X[2], H, d.nz, 1, d.nz);
   const int na1 = ax.a1 - ax.a0 + 1, nb1 = ay.a1 - ay.a0 + 1, nc1 = az.a1 - az.a0 + 1;
   const int na = na1 + max(0, ax.b1 - ax.b0 + 1);
@@ -568,23 +574,29 @@ int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min
 
 }  // namespace
 
-hipError_t launch3_collide(int grid, hipStream_t stream, const Desc3 *desc, int p) {
-  hipLaunchKernelGGL(k3_collide, dim3(grid), dim3(256), 0, stream, desc, p);
+hipError_t launch3_collide(int tile_x, int grid, hipStream_t stream, const Desc3 *desc, int p) {
+  if (tile_x == 256)
+    hipLaunchKernelGGL(k3_collide<256>, dim3(grid), dim3(256), 0, stream, desc, p);
+  else
+    hipLaunchKernelGGL(k3_collide<64>, dim3(grid), dim3(256), 0, stream, desc, p);
   return hipGetLastError();
 }
 
-int collide3_blocks_per_cu() {
+int collide3_blocks_per_cu(int tile_x) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(k3_collide),
-                                                   256, 0) != hipSuccess)
-    return 0;
+  const void *f = tile_x == 256 ? reinterpret_cast<const void *>(k3_collide<256>)
+                                : reinterpret_cast<const void *>(k3_collide<64>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) return 0;
   return n;
 }
 
-hipError_t launch3_fields(int64_t ntiles, hipStream_t stream, const Desc3 *desc, int p,
-                          double *rho, double *ux, double *uy, double *uz) {
+hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const Desc3 *desc,
+                          int p, double *rho, double *ux, double *uy, double *uz) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
-  hipLaunchKernelGGL(k3_fields, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
+  if (tile_x == 256)
+    hipLaunchKernelGGL(k3_fields<256>, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
+  else
+    hipLaunchKernelGGL(k3_fields<64>, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ CASES = [
     (4, (64, 8, 12), 5, 7),                       # exact tiles, walls on every axis
     (5, (40, 12, 1), 2, 0),                       # a single z layer
     (6, (33, 30, 20), 8, inputs3d.WALL_X),
+    (7, (200, 6, 5), 4, inputs3d.WALL_Y),         # 256-wide tiles, one partial
+    (8, (300, 5, 4), 5, 6),                       # 256-wide tiles, the second ragged
 ]
 
 
@@ -140,17 +142,31 @@ def test_channel_with_fixed_sphere():
     assert abs(Wg[0] - Wo[0]) <= 1e-4 * abs(Wo[0])
 
 
-def test_fluid_only_and_rest_state():
-    wl = inputs3d.Workload3D(name="fluid", nx=48, ny=20, nz=24, tau=0.7, nsteps=1,
-                             G=(2e-5, 1e-5, 0.0))
-    log_case("3d fluid only 48x20x24, 100 steps")
+@pytest.mark.parametrize("dims,walls", [((48, 20, 24), 0),
+                                         ((300, 6, 10), inputs3d.WALL_Y | inputs3d.WALL_Z)])
+def test_fluid_only(dims, walls):
+    """Without spheres; rows of 192 nodes or more run as whole-row tiles (a partial second
+    tile here)."""
+    nx, ny, nz = dims
+    wl = inputs3d.Workload3D(name="fluid", nx=nx, ny=ny, nz=nz, tau=0.7, nsteps=1,
+                             G=(2e-5, 1e-5, -5e-6), wall_mask=walls, wall_h=2.0)
+    log_case(f"3d fluid only {dims} walls={walls}, 100 steps")
     o = oracle3(wl)
     g = gpu3(wl)
+    f0 = inputs3d.random_deviations3d(nx, ny, nz, amp=2e-4, seed=21)
+    o.set_populations(f0)
+    g.set_populations(f0)
     o.step(100)
     g.step(100)
     _, *uo = o.get_fields()
     _, *ug = g.get_fields()
     assert vel_l2(ug, uo) < 1e-5
+    if walls:
+        Wo, Wg = o.get_wall_force(), g.get_wall_force()
+        assert np.abs(Wg - Wo).max() <= 1e-4 * np.abs(Wo).max()
+
+
+def test_rest_state():
     # at rest with neutrally buoyant spheres: nothing moves
     sp = inputs3d.spheres([[10.0, 10.0, 12.0], [30.0, 10.0, 12.0]], [4.0, 5.0], [1.0, 1.0])
     wr = inputs3d.Workload3D(name="rest", nx=48, ny=20, nz=24, tau=0.7, nsteps=1,
@@ -209,9 +225,34 @@ def test_list_overflow_and_instability_poison_the_handle():
     w2 = inputs3d.Workload3D(name="unstable", nx=16, ny=8, nz=8, tau=0.8, nsteps=1)
     g = gpu3(w2)
     f = np.zeros((19, 8, 8, 16))
-    f[1] = 0.5  # a strong +x stream: |u| > 0.5
+    f[1] = 2.0  # a strong +x stream: rho = 3, u = 2/3 > 0.5
     g.set_populations(f)
     assert g.step_status(1) == dilbm.EUNSTABLE
     assert g.step_status(1) == dilbm.ESTATE
     g.get_fields()  # reads still work
     g.close()
+
+
+def test_spheres_set_after_fluid_steps():
+    """Spheres set on a solve that has been stepping without them: the tile layout changes
+    from whole rows to 64 x 4 x 1 under the same populations."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    dims = (256, 12, 10)
+    sp = inputs3d.random_spheres(rng, dims, 4, rmin=2.5, rmax=4.0, speed=0.01)
+    wl = inputs3d.Workload3D(name="late", nx=256, ny=12, nz=10, tau=0.75, nsteps=1,
+                             G=(1e-5, 0.0, 0.0))
+    log_case("3d spheres set after 30 fluid steps, 256x12x10")
+    o = oracle3(wl)
+    g = gpu3(wl)
+    o.step(30)
+    g.step(30)
+    o.set_particles(sp["pos"], sp["radius"], sp["density"], sp["vel"], sp["omega"])
+    g.set_particles(sp["pos"], sp["radius"], sp["density"], sp["vel"], sp["omega"])
+    o.step(30)
+    g.step(30)
+    _, *uo = o.get_fields()
+    _, *ug = g.get_fields()
+    assert vel_l2(ug, uo) < 1e-5
+    xo, _, _ = o.get_particles()
+    xg, _, _ = g.get_particles()
+    assert np.abs(xg - xo).max() < 1e-6
