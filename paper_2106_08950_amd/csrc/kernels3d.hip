@@ -66,6 +66,7 @@ enum Mode3 { kStep3 = 0, kFields3 = 1 };
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
 template <int MODE, int TX>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
+                                      float (*red)[6][64],
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
                                       double *__restrict__ out_uy,
                                       double *__restrict__ out_uz) {
@@ -245,20 +246,29 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         fz = k * (vz - usz);
       }
       if (MODE == kStep3 && __ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0) {
-        const double sx = wave_sum((double)fx), sy = wave_sum((double)fy);
-        const double sz = wave_sum((double)fz);
-        const double tx = wave_sum((double)(ry * fz - rz * fy));
-        const double ty = wave_sum((double)(rz * fx - rx * fz));
-        const double tz = wave_sum((double)(rx * fy - ry * fx));
-        if (lane == 0) {
-          double *a = acc + 6 * e;
-          unsafeAtomicAdd(a + 0, sx);
-          unsafeAtomicAdd(a + 1, sy);
-          unsafeAtomicAdd(a + 2, sz);
-          unsafeAtomicAdd(a + 3, tx);
-          unsafeAtomicAdd(a + 4, ty);
-          unsafeAtomicAdd(a + 5, tz);
+        // the wave's six sums by a transpose through its own LDS rows: each lane stores its
+        // force and torque, lanes 8k..8k+7 add the 64 values of component k (eight each, in
+        // FP64), three DPP steps combine the eight, and one atomic instruction with six
+        // active lanes adds the totals
+        float(*r)[64] = red[tid >> 6];
+        r[0][lane] = fx;
+        r[1][lane] = fy;
+        r[2][lane] = fz;
+        r[3][lane] = ry * fz - rz * fy;
+        r[4][lane] = rz * fx - rx * fz;
+        r[5][lane] = rx * fy - ry * fx;
+        __builtin_amdgcn_wave_barrier();
+        double part = 0.0;
+        if (lane < 48) {
+          const float *q = &r[lane >> 3][(lane & 7) * 8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) part += (double)q[k];
         }
+        __builtin_amdgcn_wave_barrier();
+        part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
+        part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
+        part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
+        if (lane < 48 && (lane & 7) == 0) unsafeAtomicAdd(acc + 6 * e + (lane >> 3), part);
       }
     }
     // wall slabs: solid velocity 0; their force goes to the last accumulator slot
@@ -365,6 +375,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
 template <int TX>
 __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
     const Desc3 *__restrict__ desc, int p) {
+  __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   const Desc3 &d = *desc;
   const WorkSplit ws = xcd_split(d.ntiles);
   // odd chunks are walked backwards, so neighbouring chunks reach their common edge
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX>(d, t, p, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX>(d, t, p, red, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX>(d, t, p, rho, ux, uy, uz);
+    tile3<kFields3, TX>(d, t, p, nullptr, rho, ux, uy, uz);
 }
 
 // One wave per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
