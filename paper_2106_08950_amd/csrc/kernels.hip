@@ -337,7 +337,7 @@ __device__ void nee_node(const SolveDesc &d, const typename ST::T *src, int64_t 
 // One tile of one solve.  MODE kModeStep: full step; kModeFields: moments only.
 template <class ST, int TX, int TY, int MODE, int AM, bool OPEN>
 __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, const int p,
-                                             const int64_t t,
+                                             const int64_t t, float (*red)[3][64],
                                              double *__restrict__ out_rho,
                                              double *__restrict__ out_ux,
                                              double *__restrict__ out_uy,
@@ -577,14 +577,26 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         tq = rx * fy - ry * fx;
       }
       if (MODE == kModeStep && __ballot(fx != 0.f || fy != 0.f) != 0) {
-        const double sx = wave_sum((double)fx);
-        const double sy = wave_sum((double)fy);
-        const double st = wave_sum((double)tq);
-        if (lane == 0) {
-          unsafeAtomicAdd(&acc[3 * e], sx);
-          unsafeAtomicAdd(&acc[3 * e + 1], sy);
-          unsafeAtomicAdd(&acc[3 * e + 2], st);
+        // the wave's three sums by a transpose through its own LDS rows: each lane stores
+        // its force and torque, lanes 8k..8k+7 add the 64 values of component k (eight
+        // each, in FP64), three DPP steps combine the eight, and one atomic instruction
+        // with three active lanes adds the totals
+        float(*r)[64] = red[tid >> 6];
+        r[0][lane] = fx;
+        r[1][lane] = fy;
+        r[2][lane] = tq;
+        __builtin_amdgcn_wave_barrier();
+        double part = 0.0;
+        if (lane < 24) {
+          const float *q = &r[lane >> 3][(lane & 7) * 8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) part += (double)q[k];
         }
+        __builtin_amdgcn_wave_barrier();
+        part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
+        part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
+        part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
+        if (lane < 24 && (lane & 7) == 0) unsafeAtomicAdd(&acc[3 * e + (lane >> 3)], part);
       }
     }
 
@@ -719,6 +731,7 @@ template <class ST, int TX, int TY, int AM, bool OPEN>
 __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
+  __shared__ float red[kBlockThreads / 64][3][64];  // per wave: its lanes' force and torque
   const WorkSplit ws = xcd_split(hdr->total_tiles);
   const int solo = hdr->solo_slot;  // one member: no per-tile lookup
   // Odd chunks are walked backwards: two neighbouring chunks then reach their common
@@ -732,8 +745,8 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     if (k >= d.active_steps) continue;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, nullptr, nullptr,
-                                                  nullptr, Region{0, 0, 0, 0});
+    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, red, nullptr,
+                                                  nullptr, nullptr, Region{0, 0, 0, 0});
   }
 }
 
@@ -751,8 +764,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, rho, ux, uy,
-                                                           region);
+    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, nullptr, rho, ux,
+                                                           uy, region);
   }
 }
 
