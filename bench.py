@@ -33,28 +33,31 @@ METRIC = "MLUPS + % HBM roofline, FP32 vs batched/FP16; p50/p99 latency of serve
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_08950_amd", "csrc", "kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp32_hbm_counters.txt")
+KERNEL3_SRC = os.path.join(ROOT, "paper_2106_08950_amd", "csrc", "kernels3d.hip")
+COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm_counters.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(src=None):
     import hashlib
 
-    with open(KERNEL_SRC, "rb") as f:
+    with open(src or KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_collide launch from the committed rocprofv3 counter summary, or
-    None when the kernel source has changed since the counters were taken."""
+def measured_traffic(counters=None, src=None):
+    """HBM bytes per collide launch from a committed rocprofv3 counter summary (default:
+    the 2-D headline's), or None when the kernel source has changed since the counters
+    were taken."""
     try:
-        with open(COUNTERS) as f:
+        with open(counters or COUNTERS) as f:
             kv = dict(ln.split(":", 1) for ln in f.read().splitlines() if ":" in ln)
     except OSError:
         return None
-    if kv.get("kernel_source_sha256_16", "").strip() != kernel_source_hash():
+    if kv.get("kernel_source_sha256_16", "").strip() != kernel_source_hash(src):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -166,6 +169,7 @@ def suspension3d_leg(steps, warmup, stream):
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(a3, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(a3 / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(COUNTERS3, KERNEL3_SRC),
                          "kernel": "k3_collide", "bytes_per_node": 152,
                          "avg_launch_ms": round(avg, 5), "launches": n}}
 

@@ -31,3 +31,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_three_dimensional_traffic_follows_its_own_source(tmp_path):
+    bench = _bench()
+    f = tmp_path / "counters3.txt"
+    h3 = bench.kernel_source_hash(bench.KERNEL3_SRC)
+    f.write_text(f"hbm_bytes_per_launch: 7654321\nkernel_source_sha256_16: {h3}\n")
+    assert bench.measured_traffic(str(f), bench.KERNEL3_SRC) == 7654321.0
+    # the 2-D source's hash does not validate the 3-D summary
+    if bench.kernel_source_hash() != h3:
+        assert bench.measured_traffic(str(f)) is None
