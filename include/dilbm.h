@@ -99,7 +99,8 @@ typedef struct dilbm_params {
   int32_t storage;             /* DILBM_STORE_*: population storage; arithmetic is FP32 */
   int32_t fp16_scale_log2;     /* FP16 storage keeps 36 (f - w rho0) * 2^k; k in [0, 24] */
   int32_t list_capacity;       /* bodies per tile list; 0 = min(n_bodies, 128) */
-  int32_t tile;                /* tile shape id (dilbm_tile_shape); -1 = default */
+  int32_t tile;                /* tile shape id (dilbm_tile_shape); -1 = default: 256 x 1
+                                  for FP32 storage with nx >= 1024, else 64 x 4 */
   int32_t x_boundary;          /* DILBM_XBC_*; INLET_OUTLET needs nx >= 3, no DILBM_WALL_X */
   int32_t inlet_kind;          /* DILBM_INLET_*: VELOCITY prescribes inlet_velocity and
                                   takes rho from the neighbour; PRESSURE prescribes

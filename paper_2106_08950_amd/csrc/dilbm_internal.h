@@ -123,7 +123,7 @@ struct BatchHeader {
   int32_t total_bodies;
   int32_t nsolves;
   int32_t solo_slot;           // descriptor slot of the only member, or -1
-  int32_t reserved;
+  int32_t natural;             // collide order: 1 = tile b to block b (grid-stride), 0 = chunks
 };
 
 }  // namespace dilbm

@@ -231,6 +231,12 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   return L;
 }
 
+// Default tile shape of a plain solve: whole-row 256 x 1 tiles (natural collide order)
+// for FP32 populations on rows of 1024 nodes or more, else 64 x 4.
+int default_shape(const dilbm_params &p) {
+  return (p.storage == DILBM_STORE_FP32 && p.nx >= 1024) ? 2 : 0;
+}
+
 uint64_t pop_bytes(const dilbm_params &p) {
   return align_up(2ull * kQ * (uint64_t)p.nx * p.ny * (p.storage == DILBM_STORE_FP16 ? 2 : 4));
 }
@@ -488,7 +494,7 @@ class Engine {
     hh->total_bodies = s.nb;
     hh->nsolves = 1;
     hh->solo_slot = 0;
-    hh->reserved = 0;
+    hh->natural = 0;
     HIPCHK(hipMemcpyAsync(d_one_hdr_, hh, sizeof(BatchHeader), hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(table_ev_, st));
     HIPCHK(launch_bodies(true, std::max(1, (s.nb + 3) / 4), st, dd, d_one_bodies_, d_one_hdr_, 0));
@@ -686,7 +692,7 @@ class Engine {
     hh.total_bodies = (int32_t)B;
     hh.nsolves = (int32_t)members_.size();
     hh.solo_slot = members_.size() == 1 ? members_[0]->slot : -1;
-    hh.reserved = 0;
+    hh.natural = natural_order() ? 1 : 0;
     if (T) HIPCHK(hipMemcpyAsync(d_tile_solve_, h_tile_solve_, sizeof(int32_t) * T,
                                  hipMemcpyHostToDevice, stream_));
     if (B) HIPCHK(hipMemcpyAsync(d_body_solve_, h_body_solve_, sizeof(int32_t) * B,
@@ -724,7 +730,15 @@ class Engine {
     dirty_ = false;
   }
 
+  // Collide order: FP32 populations in whole-row 256 x 1 tiles go tile b -> block b, so
+  // consecutive tiles (neighbouring row segments) run on the eight XCDs at once: 5.8 TB/s
+  // against 5.4 for the best chunked order in a copy probe with the same access pattern,
+  // 6% faster for the FP32 step.  Other shapes, and FP16 (whose natural-order step is 25%
+  // slower), sweep XCD-contiguous chunks.
+  bool natural_order() const { return storage_ == DILBM_STORE_FP32 && kTileTX[shape_] == 256; }
+
   int collide_grid_for(int64_t T) {
+    if (natural_order()) return (int)std::max<int64_t>(1, std::min<int64_t>(T, (int64_t)1 << 30));
     // a persistent grid: each block sweeps one contiguous chunk of tiles of a set length
     // (per-block set-up is paid once per chunk; shorter chunks keep the tiles in flight
     // closer together), and at least the blocks resident at once while tiles last
@@ -1116,7 +1130,7 @@ dilbm_status dilbm_create(const dilbm_params *p, dilbm_solver **out) {
     Solve &s = h->s;
     s.prm = *p;
     s.nb = 0;
-    s.shape = p->tile >= 0 ? p->tile : 0;
+    s.shape = p->tile >= 0 ? p->tile : default_shape(*p);
     h->eng->set_storage(p->storage);
     h->eng->set_shape(s.shape);
     s.L = body_layout(*p, 0);

@@ -732,22 +732,28 @@ __global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
   __shared__ float red[kBlockThreads / 64][3][64];  // per wave: its lanes' force and torque
-  const WorkSplit ws = xcd_split(hdr->total_tiles);
   const int solo = hdr->solo_slot;  // one member: no per-tile lookup
-  // Odd chunks are walked backwards: two neighbouring chunks then reach their common
-  // edge at about the same time, so the cache lines the x-shifted loads share across it
-  // are still in the XCD's L2 for the second reader.
-  const bool rev = (blockIdx.x >> 3) & 1;
-  for (int64_t i = ws.begin; i < ws.end; ++i) {
-    const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
+  auto run = [&](const int64_t t) {
     const int s = solo >= 0 ? solo : __builtin_amdgcn_readfirstlane(tile_solve[t]);
     const SolveDesc &d = descs[s];
-    if (k >= d.active_steps) continue;
+    if (k >= d.active_steps) return;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
     process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, red, nullptr,
                                                   nullptr, nullptr, Region{0, 0, 0, 0});
+  };
+  if (hdr->natural) {
+    // tile b to block b: consecutive tiles (neighbouring row segments) run on the eight
+    // XCDs at once
+    for (int64_t t = blockIdx.x; t < hdr->total_tiles; t += gridDim.x) run(t);
+    return;
   }
+  const WorkSplit ws = xcd_split(hdr->total_tiles);
+  // Odd chunks are walked backwards: two neighbouring chunks then reach their common
+  // edge at about the same time, so the cache lines the x-shifted loads share across it
+  // are still in the XCD's L2 for the second reader.
+  const bool rev = (blockIdx.x >> 3) & 1;
+  for (int64_t i = ws.begin; i < ws.end; ++i) run(rev ? ws.end - 1 - (i - ws.begin) : i);
 }
 
 template <class ST, int TX, int TY>
