@@ -145,9 +145,10 @@ namespace dilbm {
 namespace {
 
 // Tile width: without spheres and with long rows, a whole row of up to 256 nodes per
-// block (every x-shifted load then shares its edge lines inside the block: 2-3% faster);
-// with spheres, 64 x 4 x 1 (a sphere's support then spans fewer waves: a 256-wide row
-// makes every wave of the row take each listed sphere, 25% slower on the 256^3 suspension).
+// block, in natural order (tile b to block b: 467 us against 519 us for 64 x 4 x 1 chunks
+// on 256^3 without spheres); with spheres, 64 x 4 x 1 in XCD-contiguous chunks (a
+// sphere's support then spans fewer waves: with whole rows every wave of a row takes
+// each listed sphere, 10-25% slower on the 256^3 suspension in either order).
 int tile_x_for(const dilbm3d_params &p, int nb) {
   return (nb == 0 && p.nx >= DILBM3D_WIDE_MIN) ? 256 : 64;
 }
@@ -157,8 +158,13 @@ int64_t tiles_of(const dilbm3d_params &p, int tile_x) {
   return (int64_t)((p.nx + tile_x - 1) / tile_x) * ((p.ny + ty - 1) / ty) * p.nz;
 }
 
-// the persistent collide grid: chunks of DILBM3D_CHUNK tiles, at least one resident wave
+// the collide grid: one block per tile for whole-row tiles (natural order); otherwise a
+// persistent grid of chunks of DILBM3D_CHUNK tiles, at least one resident wave
 void size_grid3(dilbm3d_solver &s) {
+  if (s.tile_x == 256) {
+    s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_of(s.prm, 256), (int64_t)1 << 30));
+    return;
+  }
   const int bpc = std::max(1, collide3_blocks_per_cu(s.tile_x));
   int cus = 0;
   HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));

@@ -377,6 +377,13 @@ __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
     const Desc3 *__restrict__ desc, int p) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   const Desc3 &d = *desc;
+  if (TX == 256) {
+    // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
+    // XCDs at once
+    for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
+      tile3<kStep3, TX>(d, t, p, red, nullptr, nullptr, nullptr, nullptr);
+    return;
+  }
   const WorkSplit ws = xcd_split(d.ntiles);
   // odd chunks are walked backwards, so neighbouring chunks reach their common edge
   // together (the x-shifted loads share cache lines across it)
