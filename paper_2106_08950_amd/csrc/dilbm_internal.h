@@ -11,7 +11,7 @@
 //                 post-collision values: node x at time t_n finds f_i in
 //                 pop[p][i][x - c_i].
 //   tile_count[2] per tile, number of bodies whose phi support may touch the tile
-//   tile_list[2]  per tile, `list_cap` body indices
+//   tile_list[2]  per tile, `list_cap` entries: body index and four-wave mask
 //   bstate[2]     body state SoA [5][nb]: x, y, ux, uy, omega (FP64)
 //   bconst        body constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per body, what the collide kernel reads of it (BodySnap, 32 B): written
@@ -34,6 +34,11 @@ constexpr int kTileTX[kNumTileShapes] = {64, 128, 256, 32, 16};
 constexpr int kTileTY[kNumTileShapes] = {4, 2, 1, 8, 16};
 constexpr int kBlockThreads = 256;       // every tile shape has 256 nodes
 constexpr int kMaxListCap = 1024;
+// A tile-list entry: the body index in the low 27 bits and, in bits 27-30, which of the
+// tile's four waves hold a node within the body's support (set by the binning; a wave
+// skips a body whose bit is clear).
+constexpr int kListIndexBits = 27;
+constexpr int32_t kListIndexMask = (1 << kListIndexBits) - 1;
 
 // Register budget of the collide kernel: it is compiled for at least this many waves per
 // SIMD (512 / N VGPRs per lane).  The step streams populations, so waves in flight are

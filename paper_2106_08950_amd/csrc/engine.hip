@@ -191,6 +191,7 @@ void validate(const dilbm_params *p) {
 void validate_bodies(int32_t n, const double *pos, const double *vel, const double *omega,
                      const double *radius, const double *density) {
   if (n < 0) fail(DILBM_EINVAL, "negative body count");
+  if (n > kListIndexMask) fail(DILBM_EINVAL, "at most 134217727 bodies per solve");
   if (n > 0 && (!pos || !radius || !density))
     fail(DILBM_EINVAL, "pos, radius and density are required");
   for (int32_t b = 0; b < n; ++b) {

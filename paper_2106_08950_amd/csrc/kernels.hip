@@ -444,11 +444,11 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const DILBM_CONST int32_t *list =
       (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
   const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
-  int e0 = -1;
+  int32_t raw0 = 0;
   BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
   if (nbs > 0) {
-    e0 = list[0];
-    s0 = load_snap(snap + min(max(e0, 0), nbs - 1));
+    raw0 = list[0];
+    s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
   }
   if (MODE == kModeStep) {
     if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
@@ -516,13 +516,17 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     const int nsolid = nb + (wy ? 1 : 0) + (wx ? 1 : 0);
     const double xnode = (double)xc + 0.5, ynode = (double)yc + 0.5;
     const double dnx = (double)nx, dny = (double)ny;
-    // listed body j: its index (checked: a bad entry is flagged and skipped) and snapshot
+    // listed body j: its index (checked: a bad entry is flagged and skipped), whether its
+    // support reaches this wave's nodes (the entry's wave mask), and its snapshot
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     auto body = [&](const int j, int &e, BodySnap &sj) -> bool {
-      e = j == 0 ? e0 : list[j];
-      if (e < 0 || e >= nbs) {
+      const int32_t raw = j == 0 ? raw0 : list[j];
+      e = raw & kListIndexMask;
+      if (e >= nbs) {
         if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
         return false;
       }
+      if (!((raw >> (kListIndexBits + wave)) & 1)) return false;
       if (j == 0)
         sj = s0;
       else
@@ -914,10 +918,32 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       const int ia = e % na, ib = e / na;
       const int tx = ia < na1 ? ax.a0 + ia : ax.b0 + (ia - na1);
       const int ty = ib < nb1 ? ay.a0 + ib : ay.b0 + (ib - nb1);
+      // which of the tile's four waves hold a node within H of the centre: per wave, the
+      // distance from the centre to its rectangle of nodes is bounded from below on each
+      // axis by the distance to the rectangle's middle less half its extent (the periodic
+      // distance is 1-Lipschitz), so no reached wave is left out
+      uint32_t mask = 0;
+      for (int w = 0; w < 4; ++w) {
+        int xa, xb, ya, yb;
+        if (d.tx >= 64) {
+          ya = yb = ty * d.ty + (64 * w) / d.tx;
+          xa = tx * d.tx + (64 * w) % d.tx;
+          xb = xa + 63;
+        } else {
+          ya = ty * d.ty + w * (64 / d.tx);
+          yb = ya + 64 / d.tx - 1;
+          xa = tx * d.tx;
+          xb = xa + d.tx - 1;
+        }
+        const double gx = fmax(fabs(min_image(0.5 * (xa + xb + 1) - X, dnx)) - 0.5 * (xb - xa), 0.0);
+        const double gy = fmax(fabs(min_image(0.5 * (ya + yb + 1) - Y, dny)) - 0.5 * (yb - ya), 0.0);
+        if (gx * gx + gy * gy <= H * H) mask |= 1u << w;
+      }
+      if (mask == 0) continue;  // the support misses every node of the tile
       const int tile = ty * d.tiles_x + tx;
       const int slot = atomicAdd(&cnt[tile], 1);
       if (slot < d.list_cap)
-        lst[(int64_t)tile * d.list_cap + slot] = b;
+        lst[(int64_t)tile * d.list_cap + slot] = b | (int32_t)(mask << kListIndexBits);
       else
         atomicOr(d.err, (int32_t)kErrCapacity);
     }
