@@ -38,7 +38,7 @@ def _submit(pool, wl, **kw):
                        wl.fixed)
 
 
-@pytest.mark.parametrize("tile,graph_steps", [(0, 32), (1, 8), (3, 16)])
+@pytest.mark.parametrize("tile,graph_steps", [(0, 32), (1, 8), (3, 16), (2, 16)])
 def test_alone_vs_in_the_mix(tile, graph_steps):
     wls = _members(5, 6)
     log_case(f"pool alone-vs-mix tile={tile} K={graph_steps}")
