@@ -140,7 +140,7 @@ dilbm_status dilbm_create(const dilbm_params *p, dilbm_solver **out);
  * pos/vel are [n][2], omega/radius/density [n]; vel, omega and fixed may be NULL (zero).
  * radius and density must be > 0.  fixed[b] != 0 makes body b move with its given
  * velocity and spin (its hydrodynamic force is still computed).  Positions are wrapped
- * into [0, nx) x [0, ny).  n may be 0. */
+ * into [0, nx) x [0, ny).  0 <= n <= 2^27 - 1 (DILBM_EINVAL beyond). */
 dilbm_status dilbm_set_particles(dilbm_solver *s, int32_t n, const double *pos,
                                  const double *vel, const double *omega, const double *radius,
                                  const double *density, const uint8_t *fixed);

@@ -77,7 +77,7 @@ dilbm_status dilbm3d_params_init(dilbm3d_params *p);
  * mismatch, DILBM_ENOMEM when the device buffers do not fit. */
 dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out);
 
-/* Replace the spheres: n >= 0; pos [n][3] (wrapped into the domain), radius [n] > 0 and
+/* Replace the spheres: 0 <= n <= 2^27 - 1 (DILBM_EINVAL beyond); pos [n][3] (wrapped into the domain), radius [n] > 0 and
  * density [n] > 0 are required, vel [n][3], omega [n][3] and fixed [n] (nonzero: the
  * sphere keeps its velocity and spin and is not integrated) may be NULL (zero). */
 dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *pos,

@@ -144,14 +144,12 @@ struct dilbm3d_solver {
 namespace dilbm {
 namespace {
 
-// Tile width: without spheres and with long rows, a whole row of up to 256 nodes per
-// block, in natural order (tile b to block b: 467 us against 519 us for 64 x 4 x 1 chunks
-// on 256^3 without spheres); with spheres, 64 x 4 x 1 in XCD-contiguous chunks (a
-// sphere's support then spans fewer waves: with whole rows every wave of a row takes
-// each listed sphere, 10-25% slower on the 256^3 suspension in either order).
-int tile_x_for(const dilbm3d_params &p, int nb) {
-  return (nb == 0 && p.nx >= DILBM3D_WIDE_MIN) ? 256 : 64;
-}
+// Tile width: with long rows, a whole row of up to 256 nodes per block in natural order
+// (tile b to block b); on the 256^3 suspension this takes 467 us per collide launch
+// without spheres and 521 us with its 400 spheres, against 519 and 530 us for 64 x 4 x 1
+// tiles in XCD-contiguous chunks, which short rows keep.  The per-wave masks of the tile
+// lists let a wave skip the listed spheres whose support misses its 64 nodes.
+int tile_x_for(const dilbm3d_params &p) { return p.nx >= DILBM3D_WIDE_MIN ? 256 : 64; }
 
 int64_t tiles_of(const dilbm3d_params &p, int tile_x) {
   const int ty = 256 / tile_x;
@@ -356,7 +354,7 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
     s.pops = alloc3(2 * half);
     HIPCHK3(hipMalloc(&s.d_desc, sizeof(Desc3)));
     HIPCHK3(hipMalloc(&s.d_err, sizeof(int32_t)));
-    s.tile_x = tile_x_for(*p, 0);
+    s.tile_x = tile_x_for(*p);
     body_layout3(s, 0);
     fill_desc3(s);
     // the fluid at rest: every deviation zero in both buffers; empty lists
@@ -381,6 +379,7 @@ dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *p
   return guard3(&s->last_error, [&] {
     check_usable3(s);
     if (n < 0) fail3(DILBM_EINVAL, "n must be >= 0");
+    if (n > kListIndexMask) fail3(DILBM_EINVAL, "at most 134217727 spheres per solve");
     if (n > 0 && (!pos || !radius || !density))
       fail3(DILBM_EINVAL, "pos, radius and density are required");
     for (int32_t b = 0; b < n; ++b) {
@@ -414,14 +413,7 @@ dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *p
       cst[3 * (size_t)n + b] = 0.4 * m * R * R;
       cst[4 * (size_t)n + b] = (fixed && fixed[b]) ? 1.0 : 0.0;
     }
-    const int tile_x = s->tile_x;
-    s->tile_x = tile_x_for(s->prm, n);
-    try {
-      body_layout3(*s, n);
-    } catch (...) {
-      s->tile_x = tile_x;  // the old layout stays
-      throw;
-    }
+    body_layout3(*s, n);
     s->nb = n;
     fill_desc3(*s);
     size_grid3(*s);
@@ -434,7 +426,7 @@ dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *p
                              hipMemcpyHostToDevice, s->stream));
     }
     upload_desc3(*s);
-    HIPCHK3(launch3_bodies(true, n, s->stream, s->d_desc, p));
+    HIPCHK3(launch3_bodies(true, n, s->tile_x, s->stream, s->d_desc, p));
     HIPCHK3(hipStreamSynchronize(s->stream));
     poll_errors3(*s);
   });
@@ -489,7 +481,7 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
       } else {
         HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p));
       }
-      HIPCHK3(launch3_bodies(false, s->nb, s->stream, s->d_desc, p));
+      HIPCHK3(launch3_bodies(false, s->nb, s->tile_x, s->stream, s->d_desc, p));
       s->parity ^= 1;
       ++s->steps;
     }

@@ -16,9 +16,10 @@ int collide3_blocks_per_cu(int tile_x);
 // rho and corrected u of parity p's state into [nz][ny][nx] device arrays
 hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const Desc3 *desc,
                           int p, double *rho, double *ux, double *uy, double *uz);
-// the sphere step of parity p (or, bin_only, the binning of parity p's state)
-hipError_t launch3_bodies(bool bin_only, int nbodies, hipStream_t stream, const Desc3 *desc,
-                          int p);
+// the sphere step of parity p (or, bin_only, the binning of parity p's state) into the
+// lists of tiles tile_x wide (64 or 256)
+hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t stream,
+                          const Desc3 *desc, int p);
 // populations in / out of parity p's buffer (count = 19 nx ny nz), device FP64 arrays
 hipError_t launch3_set_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
                             const double *fin);

@@ -3,12 +3,13 @@
 // The step is the one of kernels.hip carried to three dimensions (Section 2.3 of the
 // paper with Eqs. (13)-(19), (22)-(24), (28)-(29)); see dilbm3d.h for the readings.
 //
-//   k3_collide  one launch per step over all tiles (64 x 4 x 1 nodes, 256 threads, one
-//               node per lane): pull streaming of the 19 populations, moments, the solid
+//   k3_collide  one launch per step over all tiles (whole rows of 256 nodes, or 64 x 4 x 1
+//               nodes for short rows; 256 threads, one node per lane): pull streaming of the 19 populations, moments, the solid
 //               field of the listed spheres and walls, Eq. (17), the Eq. (13) collision,
 //               write-back, and the per-sphere FP64 force and torque sums.
 //   k3_bodies   one wave per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
-//               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists.
+//               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists
+//               (each entry carries which of the tile's four waves the support reaches).
 //   k3_fields   rho and the corrected velocity of Eq. (17) (output only).
 //
 // Populations are kept as g_i = 36 (f_i - w_i rho0) in FP32: the weights 1/3, 1/18, 1/36
@@ -118,11 +119,11 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const DILBM_CONST int32_t *list =
       (const DILBM_CONST int32_t *)(d.tile_list[p] + lt * d.list_cap);
   const DILBM_CONST SphereSnap *snap = (const DILBM_CONST SphereSnap *)d.bsnap[p];
-  int e0 = -1;
+  int32_t raw0 = 0;
   SphereSnap s0{};
   if (nbs > 0) {
-    e0 = list[0];
-    s0 = load_snap3(snap + min(max(e0, 0), nbs - 1));
+    raw0 = list[0];
+    s0 = load_snap3(snap + min(raw0 & kListIndexMask, nbs - 1));
   }
   if (MODE == kStep3) {
     if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
@@ -178,13 +179,17 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     }
     const double xn = (double)xc + 0.5, yn = (double)yc + 0.5, zn = (double)z + 0.5;
     const double dnx = nx, dny = ny, dnz = nz;
-    // listed sphere j: its index (checked: a bad entry is flagged and skipped) and snapshot
+    // listed sphere j: its index (checked: a bad entry is flagged and skipped), whether its
+    // support reaches this wave's nodes (the entry's wave mask), and its snapshot
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     auto body = [&](const int j, int &e, SphereSnap &sj) -> bool {
-      e = j == 0 ? e0 : list[j];
-      if (e < 0 || e >= nbs) {
+      const int32_t raw = j == 0 ? raw0 : list[j];
+      e = raw & kListIndexMask;
+      if (e >= nbs) {
         if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
         return false;
       }
+      if (!((raw >> (kListIndexBits + wave)) & 1)) return false;
       if (j == 0)
         sj = s0;
       else
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
 // One wave per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
 // parity p (after set_particles); otherwise do the sphere step of parity p and bin the
 // moved spheres into the lists of parity p ^ 1.
-template <bool BIN_ONLY>
+template <bool BIN_ONLY, int TX>
 __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
   const Desc3 &d = *desc;
   const int lane = threadIdx.x & 63;
@@ -539,18 +544,57 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   const int nc = nc1 + max(0, az.b1 - az.b0 + 1);
   int32_t *cnt = d.tile_count[q];
   int32_t *lst = d.tile_list[q];
-  for (int e = lane; e < na * nbb * nc; e += 64) {
-    const int ia = e % na, r = e / na;
-    const int ib = r % nbb, ic = r / nbb;
+  // which of the tile's four waves (each 64 nodes of one row) hold a node within H of the
+  // centre: per wave, each axis bounds the distance from below by the distance to the
+  // middle of the wave's node range less half its extent (the periodic distance is
+  // 1-Lipschitz), so no reached wave is left out; 0 when the support misses the tile
+  // Candidates run x fastest over the box of na x nbb x nc tiles; the index is split with
+  // FP64 reciprocals (the quotients are exact at these magnitudes), not integer division.
+  const int ncand = na * nbb * nc;
+  const double inv_na = 1.0 / (double)na, inv_nbb = 1.0 / (double)nbb;
+  auto candidate = [&](const int e, int64_t &tile) -> uint32_t {
+    if (e >= ncand) return 0u;
+    const int r = (int)(((double)e + 0.5) * inv_na);
+    const int ia = e - r * na;
+    const int ic = (int)(((double)r + 0.5) * inv_nbb);
+    const int ib = r - ic * nbb;
     const int tx = ia < na1 ? ax.a0 + ia : ax.b0 + (ia - na1);
     const int ty = ib < nb1 ? ay.a0 + ib : ay.b0 + (ib - nb1);
     const int tz = ic < nc1 ? az.a0 + ic : az.b0 + (ic - nc1);
-    const int64_t tile = ((int64_t)tz * d.tiles_y + ty) * d.tiles_x + tx;
-    const int slot = atomicAdd(&cnt[tile], 1);
-    if (slot < d.list_cap)
-      lst[tile * d.list_cap + slot] = b;
-    else
-      atomicOr(d.err, (int32_t)kErrCapacity);
+    const double gz = fabs(min_image((double)tz + 0.5 - X[2], (double)d.nz));
+    uint32_t mask = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int ya = ty * (256 / TX) + (64 * w) / TX;
+      const int xa = tx * TX + (64 * w) % TX;
+      const double gx = fmax(fabs(min_image((double)xa + 32.0 - X[0], (double)d.nx)) - 31.5, 0.0);
+      const double gy = fabs(min_image((double)ya + 0.5 - X[1], (double)d.ny));
+      if (gx * gx + gy * gy + gz * gz <= H * H) mask |= 1u << w;
+    }
+    tile = ((int64_t)tz * d.tiles_y + ty) * d.tiles_x + tx;
+    return mask;
+  };
+  // kB candidates per lane at a time: their slot claims are in flight together
+  constexpr int kB = 4;
+  for (int e0 = lane; e0 < ncand; e0 += 64 * kB) {
+    int64_t tile[kB];
+    uint32_t mask[kB];
+    int slot[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) mask[u] = candidate(e0 + 64 * u, tile[u]);
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (mask[u])
+        slot[u] = __hip_atomic_fetch_add((DILBM_GLOBAL int32_t *)(cnt + tile[u]), 1,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      if (!mask[u]) continue;
+      if (slot[u] < d.list_cap)
+        lst[tile[u] * d.list_cap + slot[u]] = b | (int32_t)(mask[u] << kListIndexBits);
+      else
+        atomicOr(d.err, (int32_t)kErrCapacity);
+    }
   }
 }
 
@@ -618,14 +662,13 @@ hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const 
   return hipGetLastError();
 }
 
-hipError_t launch3_bodies(bool bin_only, int nbodies, hipStream_t stream, const Desc3 *desc,
-                          int p) {
+hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t stream,
+                          const Desc3 *desc, int p) {
   if (nbodies <= 0) return hipSuccess;
   const int grid = (nbodies + 3) / 4;
-  if (bin_only)
-    hipLaunchKernelGGL(k3_bodies<true>, dim3(grid), dim3(256), 0, stream, desc, p);
-  else
-    hipLaunchKernelGGL(k3_bodies<false>, dim3(grid), dim3(256), 0, stream, desc, p);
+  auto k = bin_only ? (tile_x == 256 ? k3_bodies<true, 256> : k3_bodies<true, 64>)
+                    : (tile_x == 256 ? k3_bodies<false, 256> : k3_bodies<false, 64>);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, desc, p);
   return hipGetLastError();
 }
 

@@ -61,8 +61,8 @@ CASES = [
     (4, (64, 8, 12), 5, 7),                       # exact tiles, walls on every axis
     (5, (40, 12, 1), 2, 0),                       # a single z layer
     (6, (33, 30, 20), 8, inputs3d.WALL_X),
-    (7, (200, 6, 5), 4, inputs3d.WALL_Y),         # 256-wide tiles, one partial
-    (8, (300, 5, 4), 5, 6),                       # 256-wide tiles, the second ragged
+    (7, (200, 6, 5), 4, inputs3d.WALL_Y),         # whole-row tiles, one partial
+    (8, (300, 5, 4), 5, 6),                       # whole-row tiles, the second ragged
 ]
 
 
@@ -70,6 +70,28 @@ CASES = [
 def test_one_step_matches_oracle(seed, dims, nsph, walls):
     wl, f0 = _case(seed, dims, nsph, walls)
     log_case(f"3d one step seed={seed} {dims} spheres={wl.nbodies} walls={walls}")
+    _check_one_step(wl, f0)
+
+
+def test_one_step_spheres_on_wave_seams():
+    """Whole-row tiles (nx = 260: the second tile ragged) with supports that straddle the
+    seams between the 64-node waves of a row and the periodic x boundary, overlapping near
+    x = 0: every wave a support reaches must take the sphere."""
+    nx, ny, nz = 260, 10, 6
+    sp = inputs3d.spheres(
+        [[63.9, 5.0, 3.0], [0.3, 2.0, 0.5], [128.0, 8.7, 5.5], [192.05, 5.0, 3.0],
+         [259.6, 7.0, 2.0], [255.7, 1.0, 4.0]],
+        [3.0, 2.5, 4.0, 3.5, 3.0, 2.0], [1.2] * 6,
+        vel=[[0.01, 0.0, 0.0], [0.0, -0.01, 0.0], [0.0, 0.0, 0.01], [-0.01, 0.0, 0.0],
+             [0.0, 0.01, 0.0], [0.0, 0.0, -0.01]])
+    wl = inputs3d.Workload3D(name="seams", nx=nx, ny=ny, nz=nz, tau=0.7, nsteps=1,
+                             G=(1e-5, 0.0, 0.0), **sp)
+    log_case(f"3d one step, spheres on wave seams, {(nx, ny, nz)}")
+    _check_one_step(wl, inputs3d.random_deviations3d(nx, ny, nz, amp=1e-3, seed=41))
+
+
+def _check_one_step(wl, f0):
+    walls = wl.wall_mask
     o = oracle3(wl)
     o.set_populations(f0)
     o.step(1)
@@ -101,7 +123,8 @@ def test_one_step_matches_oracle(seed, dims, nsph, walls):
 
 
 @pytest.mark.parametrize("seed,dims,nsph,walls", [(11, (64, 40, 32), 6, 0),
-                                                  (12, (50, 44, 36), 5, inputs3d.WALL_Y)])
+                                                  (12, (50, 44, 36), 5, inputs3d.WALL_Y),
+                                                  (13, (200, 24, 16), 6, inputs3d.WALL_Z)])
 def test_many_steps_match_oracle(seed, dims, nsph, walls):
     wl, f0 = _case(seed, dims, nsph, walls, overlap=False, amp=2e-4, rmax=5.0)
     log_case(f"3d 300 steps seed={seed} {dims} spheres={wl.nbodies} walls={walls}")
@@ -234,8 +257,8 @@ def test_list_overflow_and_instability_poison_the_handle():
 
 
 def test_spheres_set_after_fluid_steps():
-    """Spheres set on a solve that has been stepping without them: the tile layout changes
-    from whole rows to 64 x 4 x 1 under the same populations."""
+    """Spheres set on a solve that has been stepping without them (whole-row tiles): the
+    sphere buffers are laid out anew under the same populations."""
     rng = np.random.Generator(np.random.PCG64(31))
     dims = (256, 12, 10)
     sp = inputs3d.random_spheres(rng, dims, 4, rmin=2.5, rmax=4.0, speed=0.01)
