@@ -59,7 +59,6 @@ struct StoreF32 {
   static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float) {
     *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = v;
   }
-  static __device__ __forceinline__ float round_out(float v, float, uint32_t) { return v; }
 };
 
 // FP16 storage keeps 11 significant bits of g_i 2^k.  Rounded to nearest, a population
@@ -71,16 +70,39 @@ struct StoreF32 {
 // (values that are already representable, zero included, are stored exactly).  Host
 // conversions in and out round to nearest.  FP16 needs no moving frame: its storage
 // rounding dwarfs the FP32 arithmetic drift the frame removes.
+typedef _Float16 F16x2 __attribute__((ext_vector_type(2)));
+
 struct StoreF16 {
   using T = _Float16;
   static constexpr bool kFrame = false;
   static constexpr int kRefLog2 = 0;
   static constexpr bool kStochastic = true;
-  // v * scale rounded stochastically to a value FP16 holds exactly (normal range); r8
-  // is 8 random bits
-  static __device__ __forceinline__ float round_out(float v, float scale, uint32_t r8) {
-    const uint32_t b = __builtin_bit_cast(uint32_t, v * scale);
-    return __builtin_bit_cast(float, (b + ((r8 << 5) | 0x10u)) & 0xFFFFE000u);
+  // v * scale rounded stochastically to FP16, with byte k of h as the random bits.  The
+  // gfx950 conversion v_cvt_sr_f16_f32 adds the top 13 bits of its random operand to the
+  // 13 FP32 mantissa bits that FP16 drops, then truncates (normal range).  The operand is
+  // byte k on top and one set bit below it (a single v_perm_b32 builds it), so the
+  // rounding point sits at (r + 1/2) / 256 of an ulp, r uniform on 0..255: the stored
+  // value rounds up with its distance from the lower neighbour, to 1/256 ulp.
+  static __device__ __forceinline__ uint16_t round_bits(float v, float scale, uint32_t h,
+                                                        int k) {
+    const uint32_t rnd =
+        __builtin_amdgcn_perm(h, 0x00800000u, ((4u + (uint32_t)k) << 24) | 0x00020C0Cu);
+    const float x = v * scale;
+    // the conversion writes the low half of its destination; seeding that register with
+    // x itself costs no move (its high half is never stored)
+    F16x2 z = __builtin_bit_cast(F16x2, x);
+    z = __builtin_amdgcn_cvt_sr_f16_f32(z, x, rnd, false);
+    return __builtin_bit_cast(uint16_t, z.x);
+  }
+  static __device__ __forceinline__ void stb_bits(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff, uint16_t h) {
+    __builtin_amdgcn_raw_buffer_store_b16(h, r, voff, soff, 0);
+  }
+  static __device__ __forceinline__ void st_bits(T *p, int64_t i, uint16_t h) {
+    ((uint16_t *)p)[i] = h;
+  }
+  static __device__ __forceinline__ void sto_bits(T *plane, uint32_t byte_off, uint16_t h) {
+    *(DILBM_GLOBAL uint16_t *)((DILBM_GLOBAL char *)plane + byte_off) = h;
   }
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                               uint32_t soff, float inv) {
@@ -692,7 +714,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float usq = uxr * uxr + uyr * uyr;
   if (__ballot(valid && !(rho_r > 0.0f && usq <= 0.25f)) != 0 && lane == 0)
     atomicOr(d.err, (int32_t)kErrUnstable);
-  float sc = d.store_scale;
+  const float sc = d.store_scale;
+  uint16_t hb[kQ];  // FP16: the stochastically rounded halves
   if constexpr (ST::kStochastic) {
     // 8 random bits per population from one hash of (node, step) and two xorshifts
     const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
@@ -700,11 +723,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     const uint32_t h1 = xorshift32(h0);
     const uint32_t h2 = xorshift32(h1);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const uint32_t h = i < 4 ? h0 : (i < 8 ? h1 : h2);
-      out[i] = ST::round_out(out[i], sc, (h >> (8 * (i & 3))) & 0xFFu);
-    }
-    sc = 1.0f;  // already scaled
+    for (int i = 0; i < kQ; ++i)
+      hb[i] = ST::round_bits(out[i], sc, i < 4 ? h0 : (i < 8 ? h1 : h2), i & 3);
   }
   if (valid) {
     if (AM == kAddrBuf && TX >= 64) {
@@ -712,21 +732,41 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
           __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
       const uint32_t s0 = __builtin_amdgcn_readfirstlane(o_r0);
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) ST::stb(rd, o_x0, i * pb + s0, out[i], sc);
+      for (int i = 0; i < kQ; ++i) {
+        if constexpr (ST::kStochastic)
+          ST::stb_bits(rd, o_x0, i * pb + s0, hb[i]);
+        else
+          ST::stb(rd, o_x0, i * pb + s0, out[i], sc);
+      }
     } else if (AM == kAddrBuf) {
       const __amdgpu_buffer_rsrc_t rd =
           __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
       const uint32_t o = o_r0 + o_x0;
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) ST::stb(rd, o, i * pb, out[i], sc);
+      for (int i = 0; i < kQ; ++i) {
+        if constexpr (ST::kStochastic)
+          ST::stb_bits(rd, o, i * pb, hb[i]);
+        else
+          ST::stb(rd, o, i * pb, out[i], sc);
+      }
     } else if (AM == kAddrG32) {
       const uint32_t o = o_r0 + o_x0;
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) ST::sto(dst + i * plane, o, out[i], sc);
+      for (int i = 0; i < kQ; ++i) {
+        if constexpr (ST::kStochastic)
+          ST::sto_bits(dst + i * plane, o, hb[i]);
+        else
+          ST::sto(dst + i * plane, o, out[i], sc);
+      }
     } else {
       const int64_t o = (int64_t)yc * nx + xc;
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) ST::st(dst, i * plane + o, out[i], sc);
+      for (int i = 0; i < kQ; ++i) {
+        if constexpr (ST::kStochastic)
+          ST::st_bits(dst, i * plane + o, hb[i]);
+        else
+          ST::st(dst, i * plane + o, out[i], sc);
+      }
     }
   }
 }
