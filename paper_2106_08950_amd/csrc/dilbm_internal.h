@@ -10,8 +10,11 @@
 //                 FP32/FP16 rounding from accumulating a bias.  The pull scheme keeps
 //                 post-collision values: node x at time t_n finds f_i in
 //                 pop[p][i][x - c_i].
-//   tile_count[2] per tile, number of bodies whose phi support may touch the tile
-//   tile_list[2]  per tile, `list_cap` entries: body index and four-wave mask
+//   tile_head[2]  per tile two words: the number of bodies whose phi support may touch
+//                 the tile, and the first of their list entries (one 8-byte scalar load
+//                 per tile, from a dense array)
+//   tile_list[2]  per tile, `list_cap` entries: body index and four-wave mask (entry 0
+//                 lives in the tile's head; its slot here is unused)
 //   bstate[2]     body state SoA [5][nb]: x, y, ux, uy, omega (FP64)
 //   bconst        body constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per body, what the collide kernel reads of it (BodySnap, 32 B): written
@@ -109,7 +112,7 @@ struct SolveDesc {
   double support;              // cutoff * eps: phi support beyond the radius
   // device buffers
   void *pop[2];
-  int32_t *tile_count[2];
+  int32_t *tile_head[2];
   int32_t *tile_list[2];
   double *bstate[2];
   const double *bconst;

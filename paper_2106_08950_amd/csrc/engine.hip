@@ -208,7 +208,7 @@ void validate_bodies(int32_t n, const double *pos, const double *vel, const doub
 
 struct BodyLayout {
   int cap = 1;
-  uint64_t counts = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, acc = 0, total = 0;
+  uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, acc = 0, total = 0;
 };
 
 BodyLayout body_layout(const dilbm_params &p, int nb) {
@@ -216,8 +216,8 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   L.cap = p.list_capacity > 0 ? p.list_capacity : std::max(1, std::min(nb, 128));
   const uint64_t mt = (uint64_t)max_tiles_for(p.nx, p.ny);
   uint64_t o = 0;
-  L.counts = o;
-  o += align_up(2 * mt * 4);
+  L.heads = o;
+  o += align_up(2 * mt * 8);
   L.lists = o;
   o += align_up(2 * mt * (uint64_t)L.cap * 4);
   L.bstate = o;
@@ -334,8 +334,8 @@ void fill_desc(Solve &s) {
   d.pop[1] = pp + half;
   char *bb = (char *)s.body.ptr;
   const uint64_t mt = (uint64_t)max_tiles_for(p.nx, p.ny);
-  d.tile_count[0] = (int32_t *)(bb + s.L.counts);
-  d.tile_count[1] = d.tile_count[0] + mt;
+  d.tile_head[0] = (int32_t *)(bb + s.L.heads);
+  d.tile_head[1] = d.tile_head[0] + 2 * mt;
   d.tile_list[0] = (int32_t *)(bb + s.L.lists);
   d.tile_list[1] = d.tile_list[0] + mt * s.L.cap;
   const uint64_t nbs = (uint64_t)std::max(s.nb, 1);
@@ -478,7 +478,7 @@ class Engine {
   // Bin the bodies of s's current state into its current-parity lists.
   void bin_current(Solve &s, hipStream_t st) {
     const int p = s.parity();
-    HIPCHK(launch_fill_i32(s.desc.tile_count[p], max_tiles_for(s.prm.nx, s.prm.ny), 0, st));
+    HIPCHK(launch_fill_i32(s.desc.tile_head[p], 2 * max_tiles_for(s.prm.nx, s.prm.ny), 0, st));
     if (s.nb == 0) return;
     SolveDesc *dd = one_desc(s, st, 0);
     if (s.nb > one_bodies_cap_) {

@@ -456,24 +456,22 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
   }
 
-  // the tile's body count, its first listed body and that body's snapshot (wave-uniform
-  // scalar loads, in flight with the populations).  The first entry is read before the
-  // count is known: it is clamped into range for the snapshot load and used only when the
+  // the tile's head (body count and first list entry, one scalar load) and that body's
+  // snapshot, in flight with the populations.  The first entry is used before the count
+  // is known: it is clamped into range for the snapshot load and used only when the
   // count lists it.  An overflowed list (count > capacity) is flagged by the binning:
   // read only what fits.
-  const int nb = min(*(const DILBM_CONST int32_t *)(d.tile_count[p] + lt), d.list_cap);
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * (int64_t)lt);
+  const int32_t raw0 = (int32_t)(hv >> 32);
+  const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
   const int nbs = d.nbodies;
   const DILBM_CONST int32_t *list =
       (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
   const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
-  int32_t raw0 = 0;
   BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
-  if (nbs > 0) {
-    raw0 = list[0];
-    s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
-  }
+  if (nbs > 0) s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
   if (MODE == kModeStep) {
-    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
+    if (tid == 0) d.tile_head[p ^ 1][2 * (int64_t)lt] = 0;  // lists of the next step start empty
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
       for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
@@ -952,7 +950,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     const int na = (ax.a1 - ax.a0 + 1) + max(0, ax.b1 - ax.b0 + 1);
     const int nbb = (ay.a1 - ay.a0 + 1) + max(0, ay.b1 - ay.b0 + 1);
     const int na1 = ax.a1 - ax.a0 + 1, nb1 = ay.a1 - ay.a0 + 1;
-    int32_t *cnt = d.tile_count[q];
+    int32_t *hd = d.tile_head[q];
     int32_t *lst = d.tile_list[q];
     for (int e = lane; e < na * nbb; e += 64) {
       const int ia = e % na, ib = e / na;
@@ -981,9 +979,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       }
       if (mask == 0) continue;  // the support misses every node of the tile
       const int tile = ty * d.tiles_x + tx;
-      const int slot = atomicAdd(&cnt[tile], 1);
-      if (slot < d.list_cap)
-        lst[(int64_t)tile * d.list_cap + slot] = b | (int32_t)(mask << kListIndexBits);
+      const int32_t entry = b | (int32_t)(mask << kListIndexBits);
+      const int slot = atomicAdd(&hd[2 * (int64_t)tile], 1);
+      if (slot == 0)
+        hd[2 * (int64_t)tile + 1] = entry;  // the first entry sits in the tile's head
+      else if (slot < d.list_cap)
+        lst[(int64_t)tile * d.list_cap + slot] = entry;
       else
         atomicOr(d.err, (int32_t)kErrCapacity);
     }
