@@ -5,8 +5,10 @@
 //   pop[2]        two population buffers, structure of arrays [19][nz][ny][nx] of FP32
 //                 deviations d_i = f_i - w_i rho0.  Pull scheme: node x at time t_n finds
 //                 f_i in pop[p][i][x - c_i].
-//   tile_count[2] per tile (64 x 4 x 1 or 256 x 1 x 1 nodes), the number of spheres whose phi support
-//                 may touch it; tile_list[2]: `list_cap` sphere indices per tile
+//   tile_head[2]  per tile (64 x 4 x 1 or 256 x 1 x 1 nodes) two words: the number of
+//                 spheres whose phi support may touch it and the first list entry;
+//                 tile_list[2]: `list_cap` entries per tile (sphere index and four-wave
+//                 mask; entry 0 lives in the head)
 //   bstate[2]     sphere state SoA [9][nb]: x, y, z, u, v, w, omega_x, omega_y, omega_z
 //   bconst        sphere constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per sphere, what the collide kernel reads of it (SphereSnap, 64 B),
@@ -79,7 +81,7 @@ struct Desc3 {
   double support;     // cutoff * eps
   // device buffers
   float *pop[2];
-  int32_t *tile_count[2];
+  int32_t *tile_head[2];
   int32_t *tile_list[2];
   double *bstate[2];
   const double *bconst;

@@ -127,7 +127,7 @@ struct dilbm3d_solver {
   int grid = 8;
   int tile_x = 64;  // tile width of the current layout (64 or 256)
   Mem3 pops, body;
-  uint64_t off_counts = 0, off_lists = 0, off_bstate = 0, off_bconst = 0, off_snap = 0,
+  uint64_t off_heads = 0, off_lists = 0, off_bstate = 0, off_bconst = 0, off_snap = 0,
            off_acc = 0;
   Desc3 h{};
   Desc3 *d_desc = nullptr;
@@ -179,7 +179,7 @@ void body_layout3(dilbm3d_solver &s, int n) {
   const int cap = s.prm.list_capacity > 0 ? s.prm.list_capacity : std::max(1, std::min(n, 128));
   const uint64_t nn = (uint64_t)std::max(n, 1);
   uint64_t off[6], o = 0;
-  const uint64_t sizes[6] = {2 * T * 4, 2 * T * (uint64_t)cap * 4, 2 * 9 * nn * 8, 5 * nn * 8,
+  const uint64_t sizes[6] = {2 * T * 8, 2 * T * (uint64_t)cap * 4, 2 * 9 * nn * 8, 5 * nn * 8,
                              2 * nn * sizeof(SphereSnap), 2 * 6 * (uint64_t)(n + 1) * 8};
   for (int k = 0; k < 6; ++k) {
     off[k] = o;
@@ -189,7 +189,7 @@ void body_layout3(dilbm3d_solver &s, int n) {
   free3(s.body);
   s.body = fresh;
   s.cap = cap;
-  s.off_counts = off[0];
+  s.off_heads = off[0];
   s.off_lists = off[1];
   s.off_bstate = off[2];
   s.off_bconst = off[3];
@@ -246,8 +246,8 @@ void fill_desc3(dilbm3d_solver &s) {
   d.pop[1] = (float *)((char *)s.pops.ptr + half);
   char *bb = (char *)s.body.ptr;
   const uint64_t T = (uint64_t)d.ntiles, nn = (uint64_t)std::max(s.nb, 1);
-  d.tile_count[0] = (int32_t *)(bb + s.off_counts);
-  d.tile_count[1] = d.tile_count[0] + T;
+  d.tile_head[0] = (int32_t *)(bb + s.off_heads);
+  d.tile_head[1] = d.tile_head[0] + 2 * T;
   d.tile_list[0] = (int32_t *)(bb + s.off_lists);
   d.tile_list[1] = d.tile_list[0] + T * s.cap;
   d.bstate[0] = (double *)(bb + s.off_bstate);

@@ -111,22 +111,20 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, s, 0));
   }
 
-  // the tile's sphere count, its first listed sphere and that sphere's snapshot (scalar
-  // loads in flight with the populations; the first entry is clamped into range for the
-  // snapshot load and used only when the count lists it)
-  const int nb = min(*(const DILBM_CONST int32_t *)(d.tile_count[p] + lt), d.list_cap);
+  // the tile's head (sphere count and first list entry, one scalar load) and that
+  // sphere's snapshot, in flight with the populations; the first entry is clamped into
+  // range for the snapshot load and used only when the count lists it
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * lt);
+  const int32_t raw0 = (int32_t)(hv >> 32);
+  const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
   const int nbs = d.nbodies;
   const DILBM_CONST int32_t *list =
       (const DILBM_CONST int32_t *)(d.tile_list[p] + lt * d.list_cap);
   const DILBM_CONST SphereSnap *snap = (const DILBM_CONST SphereSnap *)d.bsnap[p];
-  int32_t raw0 = 0;
   SphereSnap s0{};
-  if (nbs > 0) {
-    raw0 = list[0];
-    s0 = load_snap3(snap + min(raw0 & kListIndexMask, nbs - 1));
-  }
+  if (nbs > 0) s0 = load_snap3(snap + min(raw0 & kListIndexMask, nbs - 1));
   if (MODE == kStep3) {
-    if (tid == 0) d.tile_count[p ^ 1][lt] = 0;  // lists of the next step start empty
+    if (tid == 0) d.tile_head[p ^ 1][2 * lt] = 0;  // lists of the next step start empty
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
       for (int i = tid; i < 6 * (nbs + 1); i += 256) a[i] = 0.0;
@@ -542,7 +540,7 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   const int na = na1 + max(0, ax.b1 - ax.b0 + 1);
   const int nbb = nb1 + max(0, ay.b1 - ay.b0 + 1);
   const int nc = nc1 + max(0, az.b1 - az.b0 + 1);
-  int32_t *cnt = d.tile_count[q];
+  int32_t *hd = d.tile_head[q];
   int32_t *lst = d.tile_list[q];
   // which of the tile's four waves (each 64 nodes of one row) hold a node within H of the
   // centre: per wave, each axis bounds the distance from below by the distance to the
@@ -585,13 +583,16 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
 #pragma unroll
     for (int u = 0; u < kB; ++u)
       if (mask[u])
-        slot[u] = __hip_atomic_fetch_add((DILBM_GLOBAL int32_t *)(cnt + tile[u]), 1,
+        slot[u] = __hip_atomic_fetch_add((DILBM_GLOBAL int32_t *)(hd + 2 * tile[u]), 1,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
       if (!mask[u]) continue;
-      if (slot[u] < d.list_cap)
-        lst[tile[u] * d.list_cap + slot[u]] = b | (int32_t)(mask[u] << kListIndexBits);
+      const int32_t entry = b | (int32_t)(mask[u] << kListIndexBits);
+      if (slot[u] == 0)
+        hd[2 * tile[u] + 1] = entry;  // the first entry sits in the tile's head
+      else if (slot[u] < d.list_cap)
+        lst[tile[u] * d.list_cap + slot[u]] = entry;
       else
         atomicOr(d.err, (int32_t)kErrCapacity);
     }
