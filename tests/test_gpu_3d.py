@@ -233,6 +233,31 @@ def test_full_size_suspension_one_step():
     assert np.abs(xg - xo).max() < 1e-9
 
 
+@pytest.mark.parametrize("cap,nx", [(1, 48), (2, 48), (2, 200)])
+def test_lists_filled_to_capacity_match_oracle(cap, nx):
+    """Lists exactly as long as the spheres need: with capacity 1 every entry sits in the
+    tiles' heads; with 2, shared tiles hold the second entry in the list array (64 x 4 x 1
+    tiles at nx = 48, whole rows at nx = 200)."""
+    pos = [[20.0, 10.0, 8.0]] if cap == 1 else [[16.0, 10.0, 8.0], [30.0, 11.0, 9.0]]
+    vel = [[0.01, 0.0, 0.004]] if cap == 1 else [[0.01, 0.0, 0.0], [-0.005, 0.004, 0.0]]
+    sp = inputs3d.spheres(pos, [4.0] * len(pos), [1.3] * len(pos), vel=vel)
+    wl = inputs3d.Workload3D(name="cap_exact", nx=nx, ny=20, nz=16, tau=0.7, nsteps=100,
+                             G=(1e-5, 0.0, 0.0), **sp)
+    log_case(f"3d lists filled to capacity {cap}, nx={nx}, 100 steps")
+    g = dilbm3d.Solver3D(dilbm3d.params_from_workload(wl, list_capacity=cap))
+    g.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
+    o = oracle3(wl)
+    g.step(100)
+    o.step(100)
+    _, *ug = g.get_fields()
+    _, *uo = o.get_fields()
+    assert vel_l2(ug, uo) < 1e-5
+    xg, _, _ = g.get_particles()
+    xo, _, _ = o.get_particles()
+    assert np.abs(xg - xo).max() < 1e-4
+    g.close()
+
+
 def test_list_overflow_and_instability_poison_the_handle():
     sp = inputs3d.spheres([[10.0, 6.0, 6.0], [12.0, 6.0, 6.0]], [4.0, 4.0], [1.2, 1.2])
     wl = inputs3d.Workload3D(name="cap", nx=32, ny=12, nz=12, tau=0.8, nsteps=1, **sp)

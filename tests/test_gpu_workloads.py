@@ -203,6 +203,29 @@ def test_maximum_lattice_size_by_windows():
     g.close()
 
 
+@pytest.mark.parametrize("cap,tile", [(1, 0), (2, 0), (2, 2)])
+def test_lists_filled_to_capacity_match_oracle(cap, tile):
+    """Lists exactly as long as the bodies need.  With capacity 1 every entry sits in the
+    tiles' heads; with 2, the tiles the two bodies share hold their second entry in the
+    list array."""
+    pos = [[30.0, 32.0]] if cap == 1 else [[22.0, 32.0], [40.0, 33.5]]
+    vel = [[0.01, 0.004]] if cap == 1 else [[0.01, 0.0], [-0.005, 0.006]]
+    wl = inputs.Workload(name="cap_exact", nx=96, ny=64, tau=0.7, nsteps=200, G=(1e-5, 0.0),
+                         **inputs._bodies(pos, [5.0] * len(pos), [1.3] * len(pos), vel=vel))
+    log_case(f"lists filled to capacity {cap}, tile shape {tile}, 200 steps")
+    g = gpu_solver(wl, list_capacity=cap, tile=tile)
+    o = oracle_solver(wl)
+    g.step(200)
+    o.step(200)
+    _, ux, uy = g.get_fields()
+    _, uxo, uyo = o.get_fields()
+    assert velocity_rel_l2(ux, uy, uxo, uyo) < 1e-5
+    xg, _, _ = g.get_particles()
+    xo, _, _ = o.get_particles()
+    assert np.abs(xg - xo).max() < 1e-4
+    g.close()
+
+
 def test_capacity_overflow_poisons_handle():
     wl = inputs.Workload(name="cap", nx=64, ny=64, tau=0.8, nsteps=1,
                          **inputs._bodies([[30.0, 30.0], [34.0, 31.0], [20.0, 40.0]],
