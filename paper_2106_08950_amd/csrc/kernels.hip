@@ -533,7 +533,6 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
       if (dx >= 0.5f * (float)nx) dx -= (float)nx;
       lwx = h - fabsf(dx);
     }
-    const int nsolid = nb + (wy ? 1 : 0) + (wx ? 1 : 0);
     const double xnode = (double)xc + 0.5, ynode = (double)yc + 0.5;
     const double dnx = (double)nx, dny = (double)ny;
     // listed body j: its index (checked: a bad entry is flagged and skipped), whether its
@@ -553,39 +552,50 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         sj = load_snap(snap + e);
       return true;
     };
-    float scale = 1.0f;
-
-    // pass 1 (only where several supports meet): S = sum phi_b, w_b = phi_b min(1, 1/S)
-    if (nsolid > 1) {
-      float S = 0.f;
-      if (wy && lwy >= lcut) S += phi_of(lwy, phik);
-      if (wx && lwx >= lcut) S += phi_of(lwx, phik);
-      for (int j = 0; j < nb; ++j) {
-        int e;
-        BodySnap sj;
-        if (!body(j, e, sj)) continue;
-        const float rx = (float)min_image(xnode - sj.x, dnx);
-        const float ry = (float)min_image(ynode - sj.y, dny);
-        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);  // within 1 ulp
-        if (l >= lcut) S += phi_of(l, phik);
-      }
-      scale = S > 1.0f ? 1.0f / S : 1.0f;
-    }
-
-    // pass 2: weights, sums for Eqs. (15) and (17), and per-body force/torque (each wave
-    // sums its lanes in FP64 and adds the totals to the body's accumulators)
+    // One pass over the listed bodies with unit weights.  The weights of several
+    // overlapping supports are w_b = phi_b min(1, 1/S), S = sum of phi over the bodies
+    // and walls; every sum below is linear in the weights, so the node-local sums are
+    // scaled once afterwards, and the force sums, already added, are corrected by a
+    // second pass only in waves where some node has S > 1.
     const float kap = d.kappa;
     double *__restrict__ acc = d.acc[p];
+    const bool own = valid && !bnd;  // a node whose solid field this tile computes
+    float S = 0.f;
+    if (own && wy && lwy >= lcut) S += phi_of(lwy, phik);
+    if (own && wx && lwx >= lcut) S += phi_of(lwx, phik);
+    // the wave's three sums of one body's force and torque, by a transpose through its own
+    // LDS rows: each lane stores its three values, lanes 8k..8k+7 add the 64 values of
+    // component k (eight each, in FP64), three DPP steps combine the eight, and one atomic
+    // instruction with three active lanes adds the totals
+    auto reduce3 = [&](const int e, const float fx, const float fy, const float tq) {
+      float(*r)[64] = red[tid >> 6];
+      r[0][lane] = fx;
+      r[1][lane] = fy;
+      r[2][lane] = tq;
+      __builtin_amdgcn_wave_barrier();
+      double part = 0.0;
+      if (lane < 24) {
+        const float *q = &r[lane >> 3][(lane & 7) * 8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) part += (double)q[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+      part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
+      part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
+      part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
+      if (lane < 24 && (lane & 7) == 0) unsafeAtomicAdd(&acc[3 * e + (lane >> 3)], part);
+    };
     for (int j = 0; j < nb; ++j) {
       int e;
       BodySnap sj;
       if (!body(j, e, sj)) continue;
       const float rx = (float)min_image(xnode - sj.x, dnx);
       const float ry = (float)min_image(ynode - sj.y, dny);
-      const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+      const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);  // within 1 ulp
       float fx = 0.f, fy = 0.f, tq = 0.f;
-      if (valid && !bnd && l >= lcut) {
-        const float w = scale * phi_of(l, phik);
+      if (own && l >= lcut) {
+        const float w = phi_of(l, phik);
+        S += w;
         // rigid-body solid velocity U + omega x r
         const float ux_s = sj.u - sj.w * ry;
         const float uy_s = sj.v + sj.w * rx;
@@ -600,27 +610,35 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         fy = -kap * w * rho * (uy_s - usy);
         tq = rx * fy - ry * fx;
       }
-      if (MODE == kModeStep && __ballot(fx != 0.f || fy != 0.f) != 0) {
-        // the wave's three sums by a transpose through its own LDS rows: each lane stores
-        // its force and torque, lanes 8k..8k+7 add the 64 values of component k (eight
-        // each, in FP64), three DPP steps combine the eight, and one atomic instruction
-        // with three active lanes adds the totals
-        float(*r)[64] = red[tid >> 6];
-        r[0][lane] = fx;
-        r[1][lane] = fy;
-        r[2][lane] = tq;
-        __builtin_amdgcn_wave_barrier();
-        double part = 0.0;
-        if (lane < 24) {
-          const float *q = &r[lane >> 3][(lane & 7) * 8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) part += (double)q[k];
+      if (MODE == kModeStep && __ballot(fx != 0.f || fy != 0.f) != 0) reduce3(e, fx, fy, tq);
+    }
+    const float scale = S > 1.0f ? 1.0f / S : 1.0f;
+    Phi *= scale;
+    Ax *= scale;
+    Ay *= scale;
+    Mxx *= scale;
+    Mxy *= scale;
+    Myy *= scale;
+    // where S > 1 the forces above took phi_b for w_b: add (scale - 1) times them
+    if (MODE == kModeStep && __ballot(own && S > 1.0f) != 0) {
+      const float c = scale - 1.0f;  // 0 where S <= 1
+      for (int j = 0; j < nb; ++j) {
+        int e;
+        BodySnap sj;
+        if (!body(j, e, sj)) continue;
+        const float rx = (float)min_image(xnode - sj.x, dnx);
+        const float ry = (float)min_image(ynode - sj.y, dny);
+        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+        float fx = 0.f, fy = 0.f, tq = 0.f;
+        if (own && c != 0.0f && l >= lcut) {
+          const float w = phi_of(l, phik);
+          const float ux_s = sj.u - sj.w * ry;
+          const float uy_s = sj.v + sj.w * rx;
+          fx = c * (-kap * w * rho * (ux_s - usx));
+          fy = c * (-kap * w * rho * (uy_s - usy));
+          tq = rx * fy - ry * fx;
         }
-        __builtin_amdgcn_wave_barrier();
-        part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
-        part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
-        part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
-        if (lane < 24 && (lane & 7) == 0) unsafeAtomicAdd(&acc[3 * e + (lane >> 3)], part);
+        if (__ballot(fx != 0.f || fy != 0.f) != 0) reduce3(e, fx, fy, tq);
       }
     }
 

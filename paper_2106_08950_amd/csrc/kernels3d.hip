@@ -194,29 +194,42 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         sj = load_snap3(snap + e);
       return true;
     };
-    // pass 1 (only where several supports meet): S = sum phi_b, w_b = phi_b min(1, 1/S)
-    float scale = 1.0f;
-    const int nsolid = nb + (wx ? 1 : 0) + (wy ? 1 : 0) + (wz ? 1 : 0);
-    if (nsolid > 1) {
-      float S = 0.f;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        if (lw[a] >= lcut) S += phi_of(lw[a], phik);
-      for (int j = 0; j < nb; ++j) {
-        int e;
-        SphereSnap sj;
-        if (!body(j, e, sj)) continue;
-        const float rx = (float)min_image(xn - sj.x, dnx);
-        const float ry = (float)min_image(yn - sj.y, dny);
-        const float rz = (float)min_image(zn - sj.z, dnz);
-        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
-        if (l >= lcut) S += phi_of(l, phik);
-      }
-      scale = S > 1.0f ? 1.0f / S : 1.0f;
-    }
-    // pass 2: weights, the sums of Eqs. (15) and (17), and per-sphere force and torque
-    // (each wave sums its lanes in FP64 and adds the totals to the accumulators)
+    // One pass over the listed spheres with unit weights.  The weights of several
+    // overlapping supports are w_b = phi_b min(1, 1/S), S = sum of phi over the spheres
+    // and walls; every sum below is linear in the weights, so the node-local sums are
+    // scaled once afterwards, and the force sums, already added, are corrected by a
+    // second pass only in waves where some node has S > 1.
     double *__restrict__ acc = d.acc[p];
+    float S = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (valid && lw[a] >= lcut) S += phi_of(lw[a], phik);
+    // the wave's six sums of one sphere's force and torque, by a transpose through its own
+    // LDS rows: each lane stores its six values, lanes 8k..8k+7 add the 64 values of
+    // component k (eight each, in FP64), three DPP steps combine the eight, and one atomic
+    // instruction with six active lanes adds the totals
+    auto reduce6 = [&](const int e, const float fx, const float fy, const float fz,
+                       const float rx, const float ry, const float rz) {
+      float(*r)[64] = red[tid >> 6];
+      r[0][lane] = fx;
+      r[1][lane] = fy;
+      r[2][lane] = fz;
+      r[3][lane] = ry * fz - rz * fy;
+      r[4][lane] = rz * fx - rx * fz;
+      r[5][lane] = rx * fy - ry * fx;
+      __builtin_amdgcn_wave_barrier();
+      double part = 0.0;
+      if (lane < 48) {
+        const float *q = &r[lane >> 3][(lane & 7) * 8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) part += (double)q[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+      part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
+      part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
+      part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
+      if (lane < 48 && (lane & 7) == 0) unsafeAtomicAdd(acc + 6 * e + (lane >> 3), part);
+    };
     for (int j = 0; j < nb; ++j) {
       int e;
       SphereSnap sj;
@@ -227,7 +240,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
       float fx = 0.f, fy = 0.f, fz = 0.f;
       if (valid && l >= lcut) {
-        const float w = scale * phi_of(l, phik);
+        const float w = phi_of(l, phik);
+        S += w;
         // rigid-body velocity of the solid at the node: U + omega x r
         const float vx = sj.u + (sj.oy * rz - sj.oz * ry);
         const float vy = sj.v + (sj.oz * rx - sj.ox * rz);
@@ -248,30 +262,43 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         fy = k * (vy - usy);
         fz = k * (vz - usz);
       }
-      if (MODE == kStep3 && __ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0) {
-        // the wave's six sums by a transpose through its own LDS rows: each lane stores its
-        // force and torque, lanes 8k..8k+7 add the 64 values of component k (eight each, in
-        // FP64), three DPP steps combine the eight, and one atomic instruction with six
-        // active lanes adds the totals
-        float(*r)[64] = red[tid >> 6];
-        r[0][lane] = fx;
-        r[1][lane] = fy;
-        r[2][lane] = fz;
-        r[3][lane] = ry * fz - rz * fy;
-        r[4][lane] = rz * fx - rx * fz;
-        r[5][lane] = rx * fy - ry * fx;
-        __builtin_amdgcn_wave_barrier();
-        double part = 0.0;
-        if (lane < 48) {
-          const float *q = &r[lane >> 3][(lane & 7) * 8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) part += (double)q[k];
+      if (MODE == kStep3 && __ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0)
+        reduce6(e, fx, fy, fz, rx, ry, rz);
+    }
+    const float scale = S > 1.0f ? 1.0f / S : 1.0f;
+    Phi *= scale;
+    Ax *= scale;
+    Ay *= scale;
+    Az *= scale;
+    Mxx *= scale;
+    Myy *= scale;
+    Mzz *= scale;
+    Mxy *= scale;
+    Mxz *= scale;
+    Myz *= scale;
+    // where S > 1 the forces above took phi_b for w_b: add (scale - 1) times them
+    if (MODE == kStep3 && __ballot(valid && S > 1.0f) != 0) {
+      const float c = scale - 1.0f;  // 0 where S <= 1
+      for (int j = 0; j < nb; ++j) {
+        int e;
+        SphereSnap sj;
+        if (!body(j, e, sj)) continue;
+        const float rx = (float)min_image(xn - sj.x, dnx);
+        const float ry = (float)min_image(yn - sj.y, dny);
+        const float rz = (float)min_image(zn - sj.z, dnz);
+        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        if (valid && c != 0.0f && l >= lcut) {
+          const float w = phi_of(l, phik);
+          const float vx = sj.u + (sj.oy * rz - sj.oz * ry);
+          const float vy = sj.v + (sj.oz * rx - sj.ox * rz);
+          const float vz = sj.w + (sj.ox * ry - sj.oy * rx);
+          const float k = -kap * w * rho;
+          fx = c * (k * (vx - usx));
+          fy = c * (k * (vy - usy));
+          fz = c * (k * (vz - usz));
         }
-        __builtin_amdgcn_wave_barrier();
-        part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
-        part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
-        part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
-        if (lane < 48 && (lane & 7) == 0) unsafeAtomicAdd(acc + 6 * e + (lane >> 3), part);
+        if (__ballot(fx != 0.f || fy != 0.f || fz != 0.f) != 0) reduce6(e, fx, fy, fz, rx, ry, rz);
       }
     }
     // wall slabs: solid velocity 0; their force goes to the last accumulator slot
