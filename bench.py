@@ -253,8 +253,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the slab decomposition is described in DESIGN.md); use --gpus 1",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a slab decomposition along y is designed, not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
