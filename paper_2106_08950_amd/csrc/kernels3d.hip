@@ -7,7 +7,7 @@
 //               nodes for short rows; 256 threads, one node per lane): pull streaming of the 19 populations, moments, the solid
 //               field of the listed spheres and walls, Eq. (17), the Eq. (13) collision,
 //               write-back, and the per-sphere FP64 force and torque sums.
-//   k3_bodies   one wave per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
+//   k3_bodies   one block per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
 //               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists
 //               (each entry carries which of the tile's four waves the support reaches).
 //   k3_fields   rho and the corrected velocity of Eq. (17) (output only).
@@ -435,16 +435,19 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
     tile3<kFields3, TX>(d, t, p, nullptr, rho, ux, uy, uz);
 }
 
-// One wave per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
+// One block per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
 // parity p (after set_particles); otherwise do the sphere step of parity p and bin the
-// moved spheres into the lists of parity p ^ 1.
+// moved spheres into the lists of parity p ^ 1.  Each of the four waves computes the same
+// update (the same instructions on the same data: bitwise the same result), thread 0
+// writes it, and the binning's candidate tiles are spread over all 256 threads: a sphere
+// of R = 8 has about 1 100 candidate rows, whose slot claims are most of the kernel's time.
 template <bool BIN_ONLY, int TX>
 __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
   const Desc3 &d = *desc;
   const int lane = threadIdx.x & 63;
   const int nb = d.nbodies;
-  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (b >= nb) return;  // wave-uniform
+  const int b = blockIdx.x;
+  if (b >= nb) return;  // block-uniform
   const double *st = d.bstate[p];
   const double N[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
   double X[3] = {st[b], st[nb + b], st[2 * nb + b]};
@@ -528,7 +531,7 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
       if (X[a] >= N[a]) X[a] -= N[a];
     }
     q = p ^ 1;
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
       double *sn = d.bstate[q];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
       }
     }
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     SphereSnap s;
     s.x = X[0];
     s.y = X[1];
@@ -601,12 +604,12 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   };
   // kB candidates per lane at a time: their slot claims are in flight together
   constexpr int kB = 4;
-  for (int e0 = lane; e0 < ncand; e0 += 64 * kB) {
+  for (int e0 = threadIdx.x; e0 < ncand; e0 += 256 * kB) {
     int64_t tile[kB];
     uint32_t mask[kB];
     int slot[kB];
 #pragma unroll
-    for (int u = 0; u < kB; ++u) mask[u] = candidate(e0 + 64 * u, tile[u]);
+    for (int u = 0; u < kB; ++u) mask[u] = candidate(e0 + 256 * u, tile[u]);
 #pragma unroll
     for (int u = 0; u < kB; ++u)
       if (mask[u])
@@ -693,7 +696,7 @@ hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const 
 hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t stream,
                           const Desc3 *desc, int p) {
   if (nbodies <= 0) return hipSuccess;
-  const int grid = (nbodies + 3) / 4;
+  const int grid = nbodies;
   auto k = bin_only ? (tile_x == 256 ? k3_bodies<true, 256> : k3_bodies<true, 64>)
                     : (tile_x == 256 ? k3_bodies<false, 256> : k3_bodies<false, 64>);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, desc, p);
