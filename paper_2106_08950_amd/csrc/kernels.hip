@@ -5,9 +5,9 @@
 //             (Eqs. (5), (16)), rebuild the diffuse solid field of the bodies listed for
 //             the node's tile (Eq. (14)), correct the velocity (Eq. (17)), collide with the
 //             Eq. (15) force term (Eq. (13)) and write the 9 populations back at the node.
-//             Per body, the force and torque contributions of the tile's nodes are summed
-//             in FP64 across the wave and the block, then added with one FP64 atomic per
-//             component (Eqs. (18)-(19)).
+//             Per listed body, each wave sums its nodes' force and torque contributions
+//             in FP64 (a transpose through the wave's own LDS rows) and adds the totals
+//             with one atomic instruction (Eqs. (18)-(19)).
 // k_bodies    one wave per body, FP64: repulsion (Eqs. (28)-(29)), Newton-Euler update
 //             (Eqs. (22)-(24)) and binning of the moved body into the tile lists of the
 //             next step.
@@ -15,8 +15,10 @@
 //
 // The stencil is bandwidth bound (about 3 FLOP per byte of population traffic), so the
 // kernel is built for HBM streaming: structure-of-arrays planes, one node per lane, 64
-// consecutive nodes of a row per wave, and the work split so each XCD sweeps a
-// contiguous band of tiles (neighbouring tiles share L2 lines at their edges).
+// consecutive nodes of a row per wave.  FP32 whole-row tiles (256 x 1) run one tile per
+// block in natural order, so neighbouring row segments stream on the eight XCDs at
+// once; other shapes sweep contiguous chunks of each XCD's eighth of the tiles
+// (neighbouring tiles share L2 lines at their edges).
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"

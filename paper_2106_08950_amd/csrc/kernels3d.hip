@@ -4,9 +4,10 @@
 // paper with Eqs. (13)-(19), (22)-(24), (28)-(29)); see dilbm3d.h for the readings.
 //
 //   k3_collide  one launch per step over all tiles (whole rows of 256 nodes, or 64 x 4 x 1
-//               nodes for short rows; 256 threads, one node per lane): pull streaming of the 19 populations, moments, the solid
-//               field of the listed spheres and walls, Eq. (17), the Eq. (13) collision,
-//               write-back, and the per-sphere FP64 force and torque sums.
+//               nodes for short rows; 256 threads, one node per lane): pull streaming of
+//               the 19 populations, moments, the solid field of the listed spheres and
+//               walls, Eq. (17), the Eq. (13) collision, write-back, and the per-sphere
+//               FP64 force and torque sums.
 //   k3_bodies   one block per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
 //               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists
 //               (each entry carries which of the tile's four waves the support reaches).
