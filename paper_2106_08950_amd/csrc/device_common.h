@@ -53,6 +53,15 @@ __device__ __forceinline__ float phi_of(float l, float phi_k) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-l * phi_k));
 }
 
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014): the pseudo-random frame
+// velocity of a step is drawn from it, keyed by the solve's own step count.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
 __device__ __forceinline__ double min_image(double d, double n) {
   if (d >= 0.5 * n) return d - n;
   if (d < -0.5 * n) return d + n;

@@ -357,11 +357,12 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
     s.tile_x = tile_x_for(*p);
     body_layout3(s, 0);
     fill_desc3(s);
-    // the fluid at rest: every deviation zero in both buffers; empty lists
-    HIPCHK3(launch_zero_bytes(s.pops.ptr, (int64_t)s.pops.bytes, s.stream));
+    // empty lists; then the fluid at rest (every deviation zero, in the frame of step 0)
+    // in both buffers
     HIPCHK3(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, s.stream));
     HIPCHK3(launch_zero_bytes(s.d_err, sizeof(int32_t), s.stream));
     upload_desc3(s);
+    HIPCHK3(launch3_rest_pops((int64_t)kQ3 * p->nx * p->ny * p->nz, s.stream, s.d_desc, 0));
     size_grid3(s);
   });
   if (st != DILBM_OK) {
@@ -442,7 +443,8 @@ dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev) {
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
     HIPCHK3(hipMemcpyAsync(tmp.p, f_dev, sizeof(double) * count, hipMemcpyHostToDevice,
                            s->stream));
-    HIPCHK3(launch3_set_pops(count, s->stream, s->d_desc, s->parity, (const double *)tmp.p));
+    HIPCHK3(launch3_set_pops(count, s->stream, s->d_desc, s->parity, s->steps,
+                             (const double *)tmp.p));
     HIPCHK3(hipStreamSynchronize(s->stream));
   });
 }
@@ -454,7 +456,7 @@ dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev) {
     const int64_t count = (int64_t)kQ3 * s->prm.nx * s->prm.ny * s->prm.nz;
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
-    HIPCHK3(launch3_get_pops(count, s->stream, s->d_desc, s->parity, (double *)tmp.p));
+    HIPCHK3(launch3_get_pops(count, s->stream, s->d_desc, s->parity, s->steps, (double *)tmp.p));
     HIPCHK3(hipMemcpyAsync(f_dev, tmp.p, sizeof(double) * count, hipMemcpyDeviceToHost,
                            s->stream));
     HIPCHK3(hipStreamSynchronize(s->stream));
@@ -474,12 +476,12 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
         HIPCHK3(hipEventCreate(&ev.first));
         HIPCHK3(hipEventCreate(&ev.second));
         HIPCHK3(hipEventRecord(ev.first, s->stream));
-        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p));
+        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p, s->steps));
         HIPCHK3(hipEventRecord(ev.second, s->stream));
         s->events.push_back(ev);
         if (s->events.size() >= 4096) collect_timing3(*s);
       } else {
-        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p));
+        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p, s->steps));
       }
       HIPCHK3(launch3_bodies(false, s->nb, s->tile_x, s->stream, s->d_desc, p));
       s->parity ^= 1;
@@ -499,8 +501,8 @@ dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, doub
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * 4 * n));
     double *t = (double *)tmp.p;
-    HIPCHK3(launch3_fields(s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, t, t + n,
-                           t + 2 * n, t + 3 * n));
+    HIPCHK3(launch3_fields(s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, s->steps,
+                           t, t + n, t + 2 * n, t + 3 * n));
     double *outs[4] = {rho, ux, uy, uz};
     for (int k = 0; k < 4; ++k)
       if (outs[k])

@@ -154,12 +154,6 @@ __device__ __forceinline__ float div36(float x) {
 // at rest stays exactly at rest.  V_t is the SplitMix64 finaliser (Steele, Lea and
 // Flood, OOPSLA 2014) of t, the solve's own step count: the same sequence whether a
 // solve runs alone or batched.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
-  z += 0x9e3779b97f4a7c15ull;
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  return z ^ (z >> 31);
-}
 
 template <int L>
 __device__ __forceinline__ float2 ref_velocity(int64_t t) {

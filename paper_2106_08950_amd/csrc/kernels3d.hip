@@ -60,6 +60,27 @@ __device__ __forceinline__ SphereSnap load_snap3(const DILBM_CONST SphereSnap *q
   return s;
 }
 
+// Reference frame of the stored populations, as in the two-dimensional kernels: after
+// step t what is stored is g_i - 3 K_i c_i.V_t with V_t pseudo-random, so the rounding of
+// a steady per-step increment onto the FP32 grid does not make the same error every step
+// (without it a uniformly driven 64 x 40 x 32 case drifted to 1.8e-5 of the velocity in
+// 1000 steps).  Each component of V_t has 20 significant bits on the grid 2^-36
+// (|V_t| < 2^-17): every frame constant 3 K_i c_i.V_t (K_i = 12, 2, 1), its changes and
+// 36 V_t are exact in FP32, so a fluid at rest stays exactly at rest.
+__device__ __forceinline__ float3 ref_velocity3(int64_t t) {
+  const uint64_t z = splitmix64((uint64_t)t);
+  constexpr float q = 1.0f / 68719476736.0f;  // 2^-36
+  return make_float3((float)((int)(z & 0xFFFFFu) - (1 << 19)) * q,
+                     (float)((int)((z >> 20) & 0xFFFFFu) - (1 << 19)) * q,
+                     (float)((int)((z >> 40) & 0xFFFFFu) - (1 << 19)) * q);
+}
+
+// 3 K_i c_i.V: the frame offset of direction i
+__device__ __forceinline__ double frame_offset3(int i, float3 V) {
+  return 3.0 * (double)K3[i] *
+         ((double)C3X[i] * V.x + (double)C3Y[i] * V.y + (double)C3Z[i] * V.z);
+}
+
 __device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
 
 enum Mode3 { kStep3 = 0, kFields3 = 1 };
@@ -68,7 +89,7 @@ enum Mode3 { kStep3 = 0, kFields3 = 1 };
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
 template <int MODE, int TX>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
-                                      float (*red)[6][64],
+                                      const int64_t t, float (*red)[6][64],
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
                                       double *__restrict__ out_uy,
                                       double *__restrict__ out_uz) {
@@ -132,7 +153,27 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     }
   }
 
-  // ---- moments, Eqs. (5) and (16), in g units (D = 36 drho, J = 36 j) ------------------
+  // ---- storage frame: step t's populations are stored relative to V_t; the step moves
+  // them to the frame of step t + 1 first (exact constants, one rounding per population),
+  // so that the rounding of each output sees an offset that changes from step to step.
+  // The step count passes through an empty asm: the frame constants are then computed
+  // here, next to their use, not hoisted out of the tile loop into vector registers held
+  // across the whole tile.
+  int64_t tc = t;
+  asm volatile("" : "+s"(tc));
+  float3 Vf = ref_velocity3(tc);
+  if (MODE == kStep3) {
+    const float3 Vt = Vf;
+    Vf = ref_velocity3(tc + 1);
+    const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
+#pragma unroll
+    for (int i = 1; i < kQ3; ++i)
+      g[i] -= (3.0f * K3[i]) * ((float)C3X[i] * dvx + (float)C3Y[i] * dvy + (float)C3Z[i] * dvz);
+  }
+  const float V36x = 36.0f * Vf.x, V36y = 36.0f * Vf.y, V36z = 36.0f * Vf.z;  // exact
+
+  // ---- moments, Eqs. (5) and (16), in g units (D = 36 drho, J = 36 j - 36 V; the frame
+  // carries no mass) ------------------------------------------------------------------
   float D = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
 #pragma unroll
   for (int i = 0; i < kQ3; ++i) {
@@ -146,8 +187,10 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const float drho = D * kInv36;
   float Rinv = __builtin_amdgcn_rcpf(R);
   Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
-  // 36 rho u* = 36 (j + G/2)
-  const float Jgx = Jx + 18.0f * d.Gx, Jgy = Jy + 18.0f * d.Gy, Jgz = Jz + 18.0f * d.Gz;
+  // 36 rho u* = 36 (j + G/2), back in the fixed frame
+  // 36 rho u* = 36 (j + G/2), back in the fixed frame
+  const float Jgx = Jx + (V36x + 18.0f * d.Gx), Jgy = Jy + (V36y + 18.0f * d.Gy);
+  const float Jgz = Jz + (V36z + 18.0f * d.Gz);
   const float usx = Jgx * Rinv, usy = Jgy * Rinv, usz = Jgz * Rinv;
 
   // ---- diffuse solid field, Eq. (14), and its sums over spheres and walls ---------------
@@ -348,11 +391,12 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
 
   // ---- collision, Eq. (13), in g units ------------------------------------------------
   // g_i* = g_i + omega (geq_i - g_i) + khalf K_i S_i with
-  //   geq_i = K_i [drho + 3 c.(rho u) + rho (4.5 (c.u)^2 - 1.5 u.u)],
+  //   geq_i = K_i [drho + 3 c.(rho u - V) + rho (4.5 (c.u)^2 - 1.5 u.u)]   (frame V),
   //   S_i   = 3 (c - u).G + 9 (c.u)(c.G)            (uniform body force)
   //         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q           (spheres and walls, Eq. (15) summed)
   // taken per pair of opposite directions, which share the even part.
-  const float mx = div36_3(Mx), my = div36_3(My), mz = div36_3(Mz);  // rho u
+  // rho u - V, from 36 rho u - 36 V directly (exact frame constant)
+  const float mx = div36_3(Mx - V36x), my = div36_3(My - V36y), mz = div36_3(Mz - V36z);
   const float uu = ux * ux + uy * uy + uz * uz;
   const float Gx = d.Gx, Gy = d.Gy, Gz = d.Gz;
   const float uG = ux * Gx + uy * Gy + uz * Gz;
@@ -405,14 +449,14 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
 
 template <int TX>
 __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
-    const Desc3 *__restrict__ desc, int p) {
+    const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   const Desc3 &d = *desc;
   if (TX == 256) {
     // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
     // XCDs at once
     for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-      tile3<kStep3, TX>(d, t, p, red, nullptr, nullptr, nullptr, nullptr);
+      tile3<kStep3, TX>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
     return;
   }
   const WorkSplit ws = xcd_split(d.ntiles);
@@ -421,19 +465,19 @@ __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX>(d, t, p, red, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
 template <int TX>
 __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
-                                                 double *__restrict__ rho,
+                                                 int64_t step, double *__restrict__ rho,
                                                  double *__restrict__ ux,
                                                  double *__restrict__ uy,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX>(d, t, p, nullptr, rho, ux, uy, uz);
+    tile3<kFields3, TX>(d, t, p, step, nullptr, rho, ux, uy, uz);
 }
 
 // One block per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
@@ -632,9 +676,11 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
 
 // Populations in and out: fin / fout are [19][nz][ny][nx] FP64 deviations f_i - w_i rho0
 // of the current state; node x keeps f_i at x - c_i (pull layout), as g = 36 (f - w rho0).
-__global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, const double *__restrict__ fin) {
+__global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
+                            const double *__restrict__ fin) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const float3 V = ref_velocity3(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
@@ -644,13 +690,16 @@ __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, const double 
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] = (float)(36.0 * fin[e]);
+    d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] =
+        (float)(36.0 * fin[e] - frame_offset3(i, V));
   }
 }
 
-__global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, double *__restrict__ fout) {
+__global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
+                            double *__restrict__ fout) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const float3 V = ref_velocity3(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
@@ -660,7 +709,22 @@ __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, double *__res
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    fout[e] = (double)d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] / 36.0;
+    fout[e] = ((double)d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] +
+               frame_offset3(i, V)) /
+              36.0;
+  }
+}
+
+// The fluid at rest (every deviation zero) in the frame of step `step`, in both buffers.
+__global__ void k3_rest_pops(const Desc3 *__restrict__ desc, int64_t step) {
+  const Desc3 &d = *desc;
+  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const float3 V = ref_velocity3(step);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float v = (float)(-frame_offset3((int)(e / plane), V));  // exact
+    d.pop[0][e] = v;
+    d.pop[1][e] = v;
   }
 }
 
@@ -668,11 +732,12 @@ int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min
 
 }  // namespace
 
-hipError_t launch3_collide(int tile_x, int grid, hipStream_t stream, const Desc3 *desc, int p) {
+hipError_t launch3_collide(int tile_x, int grid, hipStream_t stream, const Desc3 *desc, int p,
+                           int64_t step) {
   if (tile_x == 256)
-    hipLaunchKernelGGL(k3_collide<256>, dim3(grid), dim3(256), 0, stream, desc, p);
+    hipLaunchKernelGGL(k3_collide<256>, dim3(grid), dim3(256), 0, stream, desc, p, step);
   else
-    hipLaunchKernelGGL(k3_collide<64>, dim3(grid), dim3(256), 0, stream, desc, p);
+    hipLaunchKernelGGL(k3_collide<64>, dim3(grid), dim3(256), 0, stream, desc, p, step);
   return hipGetLastError();
 }
 
@@ -685,12 +750,14 @@ int collide3_blocks_per_cu(int tile_x) {
 }
 
 hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const Desc3 *desc,
-                          int p, double *rho, double *ux, double *uy, double *uz) {
+                          int p, int64_t step, double *rho, double *ux, double *uy, double *uz) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
   if (tile_x == 256)
-    hipLaunchKernelGGL(k3_fields<256>, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
+    hipLaunchKernelGGL(k3_fields<256>, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux,
+                       uy, uz);
   else
-    hipLaunchKernelGGL(k3_fields<64>, dim3(grid), dim3(256), 0, stream, desc, p, rho, ux, uy, uz);
+    hipLaunchKernelGGL(k3_fields<64>, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux,
+                       uy, uz);
   return hipGetLastError();
 }
 
@@ -705,16 +772,23 @@ hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t st
 }
 
 hipError_t launch3_set_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            const double *fin) {
+                            int64_t step, const double *fin) {
   hipLaunchKernelGGL(k3_set_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
-                     fin);
+                     step, fin);
   return hipGetLastError();
 }
 
 hipError_t launch3_get_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            double *fout) {
+                            int64_t step, double *fout) {
   hipLaunchKernelGGL(k3_get_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
-                     fout);
+                     step, fout);
+  return hipGetLastError();
+}
+
+hipError_t launch3_rest_pops(int64_t count, hipStream_t stream, const Desc3 *desc,
+                             int64_t step) {
+  hipLaunchKernelGGL(k3_rest_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc,
+                     step);
   return hipGetLastError();
 }
 
