@@ -20,6 +20,9 @@
 //   bsnap[2]      per body, what the collide kernel reads of it (BodySnap, 32 B): written
 //                 with every body update, so that a tile reads one listed body in one
 //                 dependent load
+//   bxy[2]        per body, (x, y) rounded to FP32, written with the snapshot: the pair
+//                 search reads 8 bytes per partner and takes the FP64 state only for
+//                 partners within reach
 //   acc[2]        FP64 force accumulators [(nb + 1) * 3]: Fx, Fy, T per body, then the
 //                 wall force in the last slot
 //   err           sticky error bits
@@ -110,6 +113,7 @@ struct SolveDesc {
   double inv_eps_p, inv_eps_p1, inv_eps_w, inv_eps_w1, xi;  // Eqs. (28)-(29)
   double wall_h_d;
   double support;              // cutoff * eps: phi support beyond the radius
+  double rmax;                 // largest body radius of the solve (pair search reach)
   // device buffers
   void *pop[2];
   int32_t *tile_head[2];
@@ -117,6 +121,7 @@ struct SolveDesc {
   double *bstate[2];
   const double *bconst;
   BodySnap *bsnap[2];
+  float *bxy[2];               // per body (x, y) in FP32, interleaved: coarse pair search
   double *acc[2];
   int32_t *err;
 };

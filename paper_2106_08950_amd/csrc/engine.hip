@@ -208,7 +208,7 @@ void validate_bodies(int32_t n, const double *pos, const double *vel, const doub
 
 struct BodyLayout {
   int cap = 1;
-  uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, acc = 0, total = 0;
+  uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, bxy = 0, acc = 0, total = 0;
 };
 
 BodyLayout body_layout(const dilbm_params &p, int nb) {
@@ -226,6 +226,8 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   o += align_up(5 * (uint64_t)std::max(nb, 1) * 8);
   L.bsnap = o;
   o += align_up(2 * (uint64_t)std::max(nb, 1) * sizeof(BodySnap));
+  L.bxy = o;
+  o += align_up(2 * 2 * (uint64_t)std::max(nb, 1) * 4);
   L.acc = o;
   o += align_up(2 * 3 * (uint64_t)(nb + 1) * 8);
   L.total = o;
@@ -344,6 +346,8 @@ void fill_desc(Solve &s) {
   d.bconst = (const double *)(bb + s.L.bconst);
   d.bsnap[0] = (BodySnap *)(bb + s.L.bsnap);
   d.bsnap[1] = d.bsnap[0] + nbs;
+  d.bxy[0] = (float *)(bb + s.L.bxy);
+  d.bxy[1] = d.bxy[0] + 2 * nbs;
   d.acc[0] = (double *)(bb + s.L.acc);
   d.acc[1] = d.acc[0] + 3 * (uint64_t)(s.nb + 1);
 }
@@ -872,6 +876,9 @@ void upload_bodies(Solve &s, hipStream_t st, const double *pos, const double *ve
                    const uint8_t *fixed) {
   const int nb = s.nb;
   const int p = s.parity();
+  double rmax = 0.0;
+  for (int b = 0; b < nb; ++b) rmax = std::max(rmax, radius[b]);
+  s.desc.rmax = rmax;
   // host arrays in the device SoA order
   std::vector<double> state(5 * (size_t)std::max(nb, 1), 0.0);
   std::vector<double> cst(5 * (size_t)std::max(nb, 1), 0.0);

@@ -867,29 +867,45 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       const double *acc = d.acc[p];
       const double hfx = acc[3 * b], hfy = acc[3 * b + 1], T = acc[3 * b + 2];
       // Eq. (28): repulsion from every other body of the solve (minimum image); pairs
-      // farther apart than r_i + r_j + xi are rejected on the squared distance
-      // (the other bodies are read kU rounds of 64 at a time: all loads of a batch are in
-      // flight together, so the loop pays one memory latency per batch, not per round)
+      // farther apart than r_i + r_j + xi are rejected on the squared distance.  The
+      // other bodies are first screened on their FP32 positions (8 bytes each, kU rounds
+      // of 64 in flight together) against the reach r_i + max r_j + xi plus a margin far
+      // above the FP32 rounding of a position; only partners inside it are read and
+      // tested in FP64, in the same order as a full FP64 sweep, so the sums are the same.
       double fx = 0.0, fy = 0.0;
       const double xi = d.xi;
+      const float *__restrict__ bxy = d.bxy[p];
+      const float X32 = (float)X, Y32 = (float)Y;
+      const float fnx = (float)d.nx, fny = (float)d.ny;
+      const float reach = (float)(R + d.rmax + xi) + 0.0625f;
       constexpr int kU = 16;
       for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
-        double xs[kU], ys[kU], rs[kU];
+        float2 q32[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int j = min(j0 + 64 * u + lane, nb - 1);  // clamped: a valid index
-          xs[u] = st[j];
-          ys[u] = st[nb + j];
-          rs[u] = d.bconst[j];
+          q32[u] = *(const float2 *)(bxy + 2 * (int64_t)j);
         }
+        uint32_t near = 0;  // rounds whose partner is within reach
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+          float dx = X32 - q32[u].x, dy = Y32 - q32[u].y;
+          if (dx >= 0.5f * fnx) dx -= fnx;
+          if (dx < -0.5f * fnx) dx += fnx;
+          if (dy >= 0.5f * fny) dy -= fny;
+          if (dy < -0.5f * fny) dy += fny;
+          if (dx * dx + dy * dy <= reach * reach) near |= 1u << u;
+        }
+        while (near) {
+          const int u = __builtin_ctz(near);
+          near &= near - 1;
           const int j = j0 + 64 * u + lane;
-          const double dx = min_image(X - xs[u], dnx);
-          const double dy = min_image(Y - ys[u], dny);
+          if (j >= nb || j == b) continue;
+          const double dx = min_image(X - st[j], dnx);
+          const double dy = min_image(Y - st[nb + j], dny);
           const double d2 = dx * dx + dy * dy;
-          const double rr = R + rs[u];
-          if (j >= nb || j == b || d2 > (rr + xi) * (rr + xi)) continue;
+          const double rr = R + d.bconst[j];
+          if (d2 > (rr + xi) * (rr + xi)) continue;
           const double dist = sqrt(d2);
           const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
                                        : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
@@ -951,7 +967,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       }
     }
     // what the collide kernel of the step reads of this body
-    if (lane == 0) d.bsnap[q][b] = BodySnap{X, Y, (float)U, (float)V, (float)W, (float)R};
+    if (lane == 0) {
+      d.bsnap[q][b] = BodySnap{X, Y, (float)U, (float)V, (float)W, (float)R};
+      *(float2 *)(d.bxy[q] + 2 * (int64_t)b) = make_float2((float)X, (float)Y);
+    }
     // a blown-up body is flagged instead of binned (its tile indices would be garbage)
     if (!isfinite(X) || !isfinite(Y) || !isfinite(R)) {
       if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);

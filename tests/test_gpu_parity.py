@@ -190,3 +190,27 @@ def _check_digest(golden, wl):
 
     meta = json.loads(str(golden["meta"]))
     assert meta["digest"] == workload_digest(wl), "input generator changed; regenerate goldens"
+
+
+@pytest.mark.parametrize("nx", [96, 8192])
+def test_pair_forces_across_the_seam_and_at_large_coordinates(nx):
+    """Eq. (28) pairs found by the FP32 screen of the pair search: one pair in the soft
+    zone across the periodic x seam, one overlapping pair, and (at nx = 8192) positions
+    whose FP32 rounding is coarse.  Velocities after a few steps must match the oracle,
+    which tests every pair exactly in FP64."""
+    ny = 48
+    pos = [[nx - 0.3, 20.0], [11.9, 22.0], [nx / 2 + 0.3, 30.0], [nx / 2 + 12.0, 29.0]]
+    vel = [[0.002, 0.0], [-0.002, 0.001], [0.0, -0.001], [0.001, 0.0]]
+    wl = inputs.Workload(name="pairs", nx=nx, ny=ny, tau=0.8, nsteps=5, G=(1e-6, 0.0),
+                         **inputs._bodies(pos, [6.0] * 4, [1.4] * 4, vel=vel))
+    log_case(f"pair forces across the seam, nx={nx}")
+    g = gpu_solver(wl)
+    o = oracle_solver(wl)
+    g.step(5)
+    o.step(5)
+    xg, ug, _ = g.get_particles()
+    xo, uo, _ = o.get_particles()
+    assert np.abs(xg - xo).max() < 1e-8
+    # the pair forces dominate the velocity change: they must be there on the GPU too
+    assert np.abs(ug - uo).max() <= 1e-4 * np.abs(uo - np.asarray(vel)).max()
+    g.close()
