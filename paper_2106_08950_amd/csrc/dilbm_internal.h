@@ -46,12 +46,17 @@ constexpr int kMaxListCap = 1024;
 constexpr int kListIndexBits = 27;
 constexpr int32_t kListIndexMask = (1 << kListIndexBits) - 1;
 
-// Register budget of the collide kernel: it is compiled for at least this many waves per
-// SIMD (512 / N VGPRs per lane).  The step streams populations, so waves in flight are
-// bytes in flight.  Measured: 7 (72 VGPRs) against 6: FP16 step 4% faster, FP32 the same;
-// 8 (64 VGPRs) makes FP32 1% slower and spills in the FP16 instances.
-#ifndef DILBM_COLLIDE_WAVES
-#define DILBM_COLLIDE_WAVES 7
+// Register budget of the collide kernel, per population storage: it is compiled for at
+// least this many waves per SIMD (512 / N VGPRs per lane).  The step streams populations,
+// so waves in flight are bytes in flight, but a tighter budget costs scheduling freedom.
+// Measured on the 4096^2 suspension: FP32 (256 x 1 tiles) 6 waves (80 VGPRs) against 7:
+// 0.5% faster with discs, 2% without; FP16 7 waves (72 VGPRs) against 6: 3-4% faster;
+// 8 waves (64 VGPRs) makes both slower and spills in the FP16 instances.
+#ifndef DILBM_COLLIDE_WAVES_F32
+#define DILBM_COLLIDE_WAVES_F32 6
+#endif
+#ifndef DILBM_COLLIDE_WAVES_F16
+#define DILBM_COLLIDE_WAVES_F16 7
 #endif
 // Persistent collide grid: each block walks one contiguous chunk of about this many tiles,
 // per population storage type (0 = one block per tile); the grid never drops below one

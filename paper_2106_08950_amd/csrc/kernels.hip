@@ -41,6 +41,7 @@ constexpr float KQ[kQ] = {16.0f, 4.0f, 4.0f, 4.0f, 4.0f, 1.0f, 1.0f, 1.0f, 1.0f}
 
 
 struct StoreF32 {
+  static constexpr int kWaves = DILBM_COLLIDE_WAVES_F32;  // register budget, waves per SIMD
   using T = float;
   static constexpr bool kFrame = true;  // stored in the moving frame of ref_velocity
   static constexpr int kRefLog2 = -17;  // |V_t| < 2^-17
@@ -75,6 +76,7 @@ struct StoreF32 {
 typedef _Float16 F16x2 __attribute__((ext_vector_type(2)));
 
 struct StoreF16 {
+  static constexpr int kWaves = DILBM_COLLIDE_WAVES_F16;  // register budget, waves per SIMD
   using T = _Float16;
   static constexpr bool kFrame = false;
   static constexpr int kRefLog2 = 0;
@@ -784,7 +786,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 }
 
 template <class ST, int TX, int TY, int AM, bool OPEN>
-__global__ __launch_bounds__(kBlockThreads, DILBM_COLLIDE_WAVES) void k_collide(
+__global__ __launch_bounds__(kBlockThreads, ST::kWaves) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
   __shared__ float red[kBlockThreads / 64][3][64];  // per wave: its lanes' force and torque
