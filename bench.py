@@ -35,6 +35,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2106_08950_amd", "csrc", "kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp32_hbm_counters.txt")
 KERNEL3_SRC = os.path.join(ROOT, "paper_2106_08950_amd", "csrc", "kernels3d.hip")
 COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm_counters.txt")
+COUNTERS16 = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp16_hbm_counters.txt")
 
 
 def log(msg):
@@ -304,6 +305,7 @@ def main():
                        "roofline": {"bound": "hbm", "achieved": round(a16, 1),
                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                     "frac": round(a16 / HBM_PEAK_GBS, 4), "bytes_per_node": 36,
+                                    "traffic": measured_traffic(COUNTERS16),
                                     "avg_launch_ms": round(avg16, 5)}}
     if "open_ends" in legs:
         log("open ends")
