@@ -104,9 +104,11 @@ def test_many_steps_match_oracle(seed, nx, ny, nb, walls):
     assert d.max() < 1e-4
 
 
-def test_rest_stays_at_rest_bitwise():
+@pytest.mark.parametrize("storage", [0, 1], ids=["fp32", "fp16"])
+def test_rest_stays_at_rest_bitwise(storage):
     # shifted storage: f - w rho0 == 0 stays exactly 0 (no forcing, bodies at rest,
-    # neutrally buoyant free body under gravity)
+    # neutrally buoyant free body under gravity); in FP16 the stochastic rounding stores
+    # representable values, zero included, exactly
     wl = inputs.cylinder_channel()
     wl = inputs.Workload(**{**wl.__dict__, "G": (0.0, 0.0), "g": (0.0, -1e-3)})
     wl.pos = np.array([[100.0, 40.0], [40.0, 30.0]])
@@ -115,8 +117,8 @@ def test_rest_stays_at_rest_bitwise():
     wl.vel = np.zeros((2, 2))
     wl.omega = np.zeros(2)
     wl.fixed = np.array([1, 0], np.uint8)
-    log_case("rest")
-    g = gpu_solver(wl)
+    log_case(f"rest, storage {storage}")
+    g = gpu_solver(wl, storage=storage)
     g.step(200)
     assert np.all(g.get_populations() == 0.0)
     x, u, om = g.get_particles()
