@@ -137,6 +137,9 @@ dilbm_status dilbm_footprint(const dilbm_params *p, int32_t n_bodies, uint64_t *
 dilbm_status dilbm_create(const dilbm_params *p, dilbm_solver **out);
 
 /* Replace the whole body set at the current step boundary; populations are untouched.
+ * The state per body is what Eqs. (22)-(24) evolve: centre X_s, velocity u_s, spin
+ * omega_s, with mass rho_s pi R^2 and inertia m R^2 / 2 (Section 3.2 gives the particle
+ * by its diameter and density ratio); the solid field of Eq. (14) is rebuilt from it.
  * pos/vel are [n][2], omega/radius/density [n]; vel, omega and fixed may be NULL (zero).
  * radius and density must be > 0.  fixed[b] != 0 makes body b move with its given
  * velocity and spin (its hydrodynamic force is still computed).  Positions are wrapped
@@ -149,7 +152,14 @@ dilbm_status dilbm_set_particles(dilbm_solver *s, int32_t n, const double *pos,
 dilbm_status dilbm_set_populations(dilbm_solver *s, const double *f_dev);
 dilbm_status dilbm_get_populations(dilbm_solver *s, double *f_dev);
 
-/* Advance nsteps >= 0 steps; returns when they are done. */
+/* Advance nsteps >= 0 steps of the procedure of Section 2.3: per step, the solid field
+ * of Eq. (14) from the body state, the collision of Eq. (13) with Eqs. (15)-(17) and the
+ * streaming, the force and torque of Eqs. (18)-(19), and the body update of
+ * Eqs. (22)-(24) with the repulsion of Eqs. (28)-(29).  Synchronous: returns when the
+ * steps are done.  The device's error flags are read back after every chunk of steps
+ * (32 by default) while the next chunk runs, so a blow-up or a list overflow ends the
+ * call at most two chunks after the step where it happened (DILBM_EUNSTABLE /
+ * DILBM_ECAPACITY, handle poisoned; the step count then includes those chunks). */
 dilbm_status dilbm_step(dilbm_solver *s, int64_t nsteps);
 
 /* rho and the corrected velocity u of Eq. (17) of the current state, each [ny][nx];

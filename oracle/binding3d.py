@@ -41,9 +41,11 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        # DILBM_ORACLE3_LIB: a copy built elsewhere (planted-mistake tests)
+        path = os.environ.get("DILBM_ORACLE3_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             compile_c(_SRC, _LIB, force=False)
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(path)
         lib.ora3_lattice.argtypes = [_ip, _ip, _ip, _dp, _dp]
         lib.ora3_feq.argtypes = [C.c_double, _dp, _dp]
         lib.ora3_force_term.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]

@@ -402,6 +402,8 @@ class Engine {
     (void)hipHostFree(h_tile_solve_);
     (void)hipHostFree(h_body_solve_);
     (void)hipHostFree(h_err_);
+    (void)hipHostFree(h_flag_);
+    if (flag_ev_) (void)hipEventDestroy(flag_ev_);
     for (int i = 0; i < 2; ++i) (void)hipEventDestroy(one_ev_[i]);
     (void)hipEventDestroy(table_ev_);
     (void)hipStreamDestroy(aux_);
@@ -474,6 +476,9 @@ class Engine {
     // the batch
     h->tile_base = 0;
     h->body_base = 0;
+    // the error word of the solve's slot: the table may have moved since the solve's
+    // descriptor was filled (a pool solve that has finished keeps its slot until release)
+    if (s.slot >= 0) h->err = d_err_ + s.slot;
     HIPCHK(hipMemcpyAsync(d_one_desc_ + which, h, sizeof(SolveDesc), hipMemcpyHostToDevice, st));
     HIPCHK(hipEventRecord(one_ev_[which], st));
     return d_one_desc_ + which;
@@ -541,6 +546,7 @@ class Engine {
       s->desc.active_steps = (int32_t)a;
       s->desc.parity0 = s->parity();
       h[s->slot] = s->desc;
+      h[s->slot].err = d_err_ + s->slot;
       kmax = std::max<int>(kmax, (int)a);
     }
     HIPCHK(hipMemcpyAsync(d_descs_, h, sizeof(SolveDesc) * slot_used_.size(),
@@ -570,6 +576,19 @@ class Engine {
     HIPCHK(hipStreamSynchronize(stream_));
   }
   int32_t err_of(const Solve &s) const { return h_err_[s.slot]; }
+  // One solve's error word, copied after the work enqueued so far into pinned memory
+  // (asynchronous); flag_wait() waits for the last such copy and returns the word.
+  void flag_copy_async(const Solve &s) {
+    if (!flag_ev_) HIPCHK(hipEventCreateWithFlags(&flag_ev_, hipEventDisableTiming));
+    if (!h_flag_) HIPCHK(hipHostMalloc(&h_flag_, sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(h_flag_, d_err_ + s.slot, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          stream_));
+    HIPCHK(hipEventRecord(flag_ev_, stream_));
+  }
+  int32_t flag_wait() {
+    HIPCHK(hipEventSynchronize(flag_ev_));
+    return *h_flag_;
+  }
   int32_t read_error_of(Solve &s, hipStream_t st) {
     int32_t v = 0;
     HIPCHK(hipMemcpyAsync(&h_err_[s.slot], d_err_ + s.slot, sizeof(int32_t),
@@ -841,6 +860,8 @@ class Engine {
   BatchHeader *d_hdr_ = nullptr;
   int32_t *d_err_ = nullptr;
   int32_t *h_err_ = nullptr;
+  int32_t *h_flag_ = nullptr;
+  hipEvent_t flag_ev_ = nullptr;
   int err_cap_ = 0;
   int64_t total_tiles_ = 0;
   int total_bodies_ = 0;
@@ -1041,8 +1062,7 @@ void check_usable(dilbm_solver *s) {
   if (s->s.poison != DILBM_OK) fail(DILBM_ESTATE, "handle poisoned: " + s->s.err);
 }
 
-void poll_errors(Engine &eng, Solve &s) {
-  const int32_t e = eng.read_error_of(s, eng.stream());
+void raise_errors(Solve &s, int32_t e) {
   if (e & kErrInternal) {
     s.poison = DILBM_EDEVICE;
     s.err = "internal error: a kernel met an out-of-range body index";
@@ -1059,6 +1079,8 @@ void poll_errors(Engine &eng, Solve &s) {
     fail(DILBM_EUNSTABLE, s.err);
   }
 }
+
+void poll_errors(Engine &eng, Solve &s) { raise_errors(s, eng.read_error_of(s, eng.stream())); }
 
 void process_deferred(dilbm_pool *p) {
   auto &v = p->deferred;
@@ -1241,10 +1263,16 @@ dilbm_status dilbm_step(dilbm_solver *h, int64_t nsteps) {
     Engine &eng = *h->eng;
     const int K = eng.graph_steps();
     int64_t left = nsteps;
+    bool pending = false;
     while (left > 0) {
       const int k = (int)std::min<int64_t>(left, K);
       eng.run_chunk(k, k == K);
       left -= k;
+      // the flags as of the previous chunk's end: waiting for them leaves this chunk
+      // queued, so the device does not idle; a failure stops the call one chunk later
+      if (pending) raise_errors(h->s, eng.flag_wait());
+      eng.flag_copy_async(h->s);
+      pending = true;
     }
     eng.collect_timing();
     HIPCHK(hipStreamSynchronize(eng.stream()));

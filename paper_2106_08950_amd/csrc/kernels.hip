@@ -261,8 +261,6 @@ __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], c
        n.Qxx - 2.0f * n.Qxy + n.Qyy);
 }
 
-// Copy one listed body into LDS.  An index outside [0, nb) (never written by the binning)
-// is flagged and staged as a body with no support, so it touches no memory and no node.
 // Change of storage frame V_t -> V_{t+1} of one node's populations: g_i -= 3 K_i c_i.dV
 // (axis directions 12 dV, diagonals 3 (dVx +- dVy); exact constants).
 struct FrameShift {

@@ -78,6 +78,9 @@ def test_one_step_matches_oracle(seed, nx, ny, nb, walls, tile):
     xg, ug, wg = g.get_particles()
     assert np.abs(xg - xo).max() < 1e-9
     assert np.abs(ug - uo).max() <= 1e-4 * max(np.abs(uo).max(), 1e-30) + 1e-15
+    # spin (Eq. (23), I = m R^2 / 2): the one-step increment T / I, compared as increments
+    dwo, dwg = wo - wl.omega, wg - wl.omega
+    assert np.abs(dwg - dwo).max() <= 1e-4 * max(np.abs(dwo).max(), 1e-30) + 1e-15, (dwg, dwo)
     ro, uxo, uyo = o.get_fields()
     rg, uxg, uyg = g.get_fields()
     assert np.abs(rg - ro).max() < 1e-6
@@ -102,6 +105,7 @@ def test_many_steps_match_oracle(seed, nx, ny, nb, walls):
     d = np.abs(xg - xo)
     d = np.minimum(d, [nx, ny] - d)
     assert d.max() < 1e-4
+    assert np.abs(wg - wo).max() <= 1e-4 * max(np.abs(wo).max(), 1e-30), (wg, wo)
 
 
 @pytest.mark.parametrize("storage", [0, 1], ids=["fp32", "fp16"])
