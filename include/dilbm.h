@@ -193,6 +193,11 @@ dilbm_status dilbm_get_body_count(dilbm_solver *s, int32_t *n);
  * call returns the summed milliseconds and the number of launches since enabling. */
 dilbm_status dilbm_set_kernel_timing(dilbm_solver *s, int32_t enable);
 dilbm_status dilbm_get_kernel_timing(dilbm_solver *s, double *collide_ms, int64_t *launches);
+/* The duration of each timed collide-stream launch since timing was enabled, in launch
+ * order: copies min(cap, count) values (milliseconds) into ms[] and sets *count to the
+ * number recorded.  ms may be NULL when cap is 0. */
+dilbm_status dilbm_get_kernel_launch_times(dilbm_solver *s, double *ms, int64_t cap,
+                                           int64_t *count);
 
 void dilbm_destroy(dilbm_solver *s);  /* NULL-safe */
 
@@ -246,8 +251,12 @@ dilbm_status dilbm_pool_get_particle_forces(dilbm_pool *pool, int64_t ticket, do
 dilbm_status dilbm_pool_release(dilbm_pool *pool, int64_t ticket);
 
 /* Pool tuning: steps per captured graph (1..256) and tile shape for solves admitted
- * later; dilbm_pool_autotune times the candidate shapes and graph lengths on the current
- * members (the timed steps are real steps of those members) and keeps the fastest. */
+ * later.  dilbm_pool_autotune times every tile shape with 16-step graphs, then 128-step
+ * graphs with the best shape, on the current members, and keeps the fastest per node
+ * update.  Each candidate's first graph launch captures the graph and is not timed; then
+ * whole graph launches covering at least steps_per_trial steps are timed with events.
+ * Every trial step is a real step of the members (about 5 x 32 + 256 steps at
+ * steps_per_trial <= 16). */
 dilbm_status dilbm_pool_set_launch(dilbm_pool *pool, int32_t graph_steps, int32_t tile);
 dilbm_status dilbm_pool_autotune(dilbm_pool *pool, int32_t steps_per_trial,
                                  int32_t *best_graph_steps, int32_t *best_tile);

@@ -114,6 +114,10 @@ dilbm_status dilbm3d_get_wall_force(dilbm3d_solver *s, double *force);
 dilbm_status dilbm3d_set_kernel_timing(dilbm3d_solver *s, int32_t enable);
 dilbm_status dilbm3d_get_kernel_timing(dilbm3d_solver *s, double *collide_ms,
                                        int64_t *launches);
+/* Each timed collide launch since timing was enabled, in launch order: min(cap, count)
+ * durations in milliseconds into ms[], *count = the number recorded. */
+dilbm_status dilbm3d_get_kernel_launch_times(dilbm3d_solver *s, double *ms, int64_t cap,
+                                             int64_t *count);
 
 /* Release the handle and its device memory; NULL is a no-op. */
 void dilbm3d_destroy(dilbm3d_solver *s);

@@ -23,5 +23,6 @@ from .binding import (  # noqa: F401
     pw_force,
     body_update,
     num_threads,
+    set_num_threads,
 )
 from . import binding3d  # noqa: F401,E402

@@ -103,6 +103,8 @@ def _L():
         lib.ora_get_wall_force.argtypes = [C.c_void_p, _dp]
         lib.ora_get_wall_force.restype = C.c_int32
         lib.ora_num_threads.restype = C.c_int32
+        lib.ora_set_num_threads.argtypes = [C.c_int32]
+        lib.ora_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -122,6 +124,11 @@ def _f64(a, shape=None):
 
 def num_threads() -> int:
     return int(_L().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's node loops (its results do not depend on the count)."""
+    _L().ora_set_num_threads(int(n))
 
 
 def lattice():

@@ -439,6 +439,15 @@ int32_t ora_num_threads(void) {
 #endif
 }
 
+/* Threads of the node loops from now on (n >= 1); results do not depend on it. */
+void ora_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static int valid_params(const ora_params *p) {
   if (!p) return 0;
   if (p->nx < 1 || p->ny < 1) return 0;

@@ -93,6 +93,7 @@ int32_t ora_get_particle_forces(const ora_solver *s, double *force, double *torq
 int32_t ora_get_particles(const ora_solver *s, double *pos, double *vel, double *omega);
 int32_t ora_get_wall_force(const ora_solver *s, double *force);
 int32_t ora_num_threads(void);
+void ora_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }

@@ -555,8 +555,8 @@ class Engine {
     if (kmax == 0) return 0;
     if (timing_) {
       launch_steps(kmax, true);
-    } else if (allow_graph && kmax == K && K > 1) {
-      hipGraphExec_t g = graph_for(K);
+    } else if (allow_graph && kmax > 1) {
+      hipGraphExec_t g = graph_for(kmax);
       HIPCHK(hipGraphLaunch(g, stream_));
     } else {
       launch_steps(kmax, false);
@@ -600,10 +600,12 @@ class Engine {
 
   // ---- timing -------------------------------------------------------------------------
   void set_timing(bool on) {
+    collect_timing();
     timing_ = on;
     timing_used_ = 0;
     timed_ms_ = 0.0;
     timed_launches_ = 0;
+    launch_ms_.clear();
   }
   void collect_timing() {
     if (!timing_used_) return;
@@ -612,11 +614,13 @@ class Engine {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, timing_ev_[i].first, timing_ev_[i].second));
       timed_ms_ += ms;
+      launch_ms_.push_back(ms);
     }
     timed_launches_ += timing_used_;
     timing_used_ = 0;
   }
   double timed_ms() const { return timed_ms_; }
+  const std::vector<float> &launch_ms() const { return launch_ms_; }
   int64_t timed_launches() const { return timed_launches_; }
 
   int64_t total_tiles() const { return total_tiles_; }
@@ -808,6 +812,9 @@ class Engine {
     const int key = K * 2 + (total_bodies_ > 0 ? 1 : 0);
     auto it = graphs_.find(key);
     if (it != graphs_.end()) return it->second;
+    // one graph per chunk length in use (the full length and a remainder or two); a
+    // caller that keeps changing lengths re-captures instead of piling up graphs
+    if (graphs_.size() >= 8) clear_graphs();
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeRelaxed));
     try {
@@ -887,6 +894,7 @@ class Engine {
   int timing_used_ = 0;
   double timed_ms_ = 0.0;
   int64_t timed_launches_ = 0;
+  std::vector<float> launch_ms_;  // every timed collide launch, in launch order
 };
 
 // ---------------------------------------------------------------------------------------
@@ -982,11 +990,31 @@ void get_forces_of(Solve &s, hipStream_t st, double *force, double *torque, doub
   }
 }
 
-void get_fields_of(Engine &eng, Solve &s, hipStream_t st, double **scratch, uint64_t *scratch_n,
-                   Region rg, double *rho, double *ux, double *uy) {
+void check_region(const Solve &s, Region rg) {
   if (rg.w < 1 || rg.h < 1 || rg.x < 0 || rg.y < 0 || rg.x + rg.w > s.prm.nx ||
       rg.y + rg.h > s.prm.ny)
     fail(DILBM_EINVAL, "region outside the lattice");
+}
+
+// rho, u of the region through the device staging buffer b (3 w h doubles) into the host
+// arrays (synchronous on st)
+void fields_through(Engine &eng, Solve &s, hipStream_t st, double *b, Region rg, double *rho,
+                    double *ux, double *uy) {
+  const uint64_t n = (uint64_t)rg.w * rg.h;
+  SolveDesc *dd = eng.one_desc(s, st, 1);
+  const int64_t ntiles = (int64_t)((rg.x + rg.w - 1) / s.desc.tx - rg.x / s.desc.tx + 1) *
+                         ((rg.y + rg.h - 1) / s.desc.ty - rg.y / s.desc.ty + 1);
+  HIPCHK(launch_fields(s.shape, s.prm.storage, ntiles, st, dd, s.parity(), rg, b, b + n,
+                       b + 2 * n));
+  if (rho) HIPCHK(hipMemcpyAsync(rho, b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (ux) HIPCHK(hipMemcpyAsync(ux, b + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (uy) HIPCHK(hipMemcpyAsync(uy, b + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void get_fields_of(Engine &eng, Solve &s, hipStream_t st, double **scratch, uint64_t *scratch_n,
+                   Region rg, double *rho, double *ux, double *uy) {
+  check_region(s, rg);
   const uint64_t n = (uint64_t)rg.w * rg.h;
   if (*scratch_n < n) {
     HIPCHK(hipStreamSynchronize(st));
@@ -996,16 +1024,7 @@ void get_fields_of(Engine &eng, Solve &s, hipStream_t st, double **scratch, uint
     HIPCHK(hipMalloc(scratch, sizeof(double) * 3 * n));
     *scratch_n = n;
   }
-  SolveDesc *dd = eng.one_desc(s, st, 1);
-  double *b = *scratch;
-  const int64_t ntiles = (int64_t)((rg.x + rg.w - 1) / s.desc.tx - rg.x / s.desc.tx + 1) *
-                         ((rg.y + rg.h - 1) / s.desc.ty - rg.y / s.desc.ty + 1);
-  HIPCHK(launch_fields(s.shape, s.prm.storage, ntiles, st, dd, s.parity(), rg, b, b + n,
-                       b + 2 * n));
-  if (rho) HIPCHK(hipMemcpyAsync(rho, b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-  if (ux) HIPCHK(hipMemcpyAsync(ux, b + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-  if (uy) HIPCHK(hipMemcpyAsync(uy, b + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  fields_through(eng, s, st, *scratch, rg, rho, ux, uy);
 }
 
 }  // namespace dilbm
@@ -1266,7 +1285,7 @@ dilbm_status dilbm_step(dilbm_solver *h, int64_t nsteps) {
     bool pending = false;
     while (left > 0) {
       const int k = (int)std::min<int64_t>(left, K);
-      eng.run_chunk(k, k == K);
+      eng.run_chunk(k, true);
       left -= k;
       // the flags as of the previous chunk's end: waiting for them leaves this chunk
       // queued, so the device does not idle; a failure stops the call one chunk later
@@ -1346,6 +1365,18 @@ dilbm_status dilbm_get_kernel_timing(dilbm_solver *h, double *collide_ms, int64_
     h->eng->collect_timing();
     if (collide_ms) *collide_ms = h->eng->timed_ms();
     if (launches) *launches = h->eng->timed_launches();
+  });
+}
+
+dilbm_status dilbm_get_kernel_launch_times(dilbm_solver *h, double *ms, int64_t cap,
+                                           int64_t *count) {
+  if (!h || cap < 0 || (cap > 0 && !ms)) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    h->eng->collect_timing();
+    const std::vector<float> &v = h->eng->launch_ms();
+    const int64_t n = std::min<int64_t>(cap, (int64_t)v.size());
+    for (int64_t i = 0; i < n; ++i) ms[i] = v[i];
+    if (count) *count = (int64_t)v.size();
   });
 }
 
@@ -1474,7 +1505,7 @@ dilbm_status dilbm_pool_run(dilbm_pool *pool, int32_t steps) {
     const int K = eng.graph_steps();
     while (left > 0 && !eng.members().empty()) {
       const int k = std::min(left, K);
-      eng.run_chunk(k, k == K);
+      eng.run_chunk(k, true);
       left -= k;
       // members whose last step is enqueued leave the member set; their completion is
       // marked by an event after this chunk
@@ -1622,38 +1653,46 @@ dilbm_status dilbm_pool_autotune(dilbm_pool *pool, int32_t steps_per_trial,
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
-    const int ks[] = {8, 32, 128};
+    // Time one candidate: the first graph launch of K steps captures the graph (untimed),
+    // then whole K-step graph launches covering at least steps_per_trial steps are timed.
+    // Every trial step is a real step of the members.  Returns ms per node update, or a
+    // negative value when the members ran out of steps.
+    auto trial = [&](int tile, int K) -> double {
+      if (eng.members().empty()) return -1.0;
+      eng.set_shape(tile);
+      eng.set_graph_steps(K);
+      eng.run_chunk(K, true);
+      const int launches = (steps_per_trial + K - 1) / K;
+      double nodes = 0;
+      for (Solve *s : eng.members())
+        nodes += (double)s->prm.nx * s->prm.ny *
+                 (double)std::min<int64_t>((int64_t)launches * K, s->remaining());
+      if (nodes == 0) return -1.0;
+      HIPCHK(hipEventRecord(a, eng.stream()));
+      for (int l = 0; l < launches && !eng.members().empty(); ++l) eng.run_chunk(K, true);
+      HIPCHK(hipEventRecord(b, eng.stream()));
+      HIPCHK(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, b));
+      return ms / nodes;
+    };
+    // tile shapes at a short graph, then the graph length at the best shape
+    const int k_short = 16, k_long = 128;
     double best = 1e300;
     int bk = eng.graph_steps(), bt = eng.shape();
     for (int tile = 0; tile < kNumTileShapes; ++tile) {
-      for (int K : ks) {
-        if (eng.members().empty()) break;
-        eng.set_shape(tile);
-        eng.set_graph_steps(K);
-        eng.run_chunk(K, true);  // warm: captures the graph
-        // node updates the timed steps will do; a trial with none left cannot be judged
-        double nodes = 0;
-        for (Solve *s : eng.members())
-          nodes += (double)s->prm.nx * s->prm.ny *
-                   (double)std::min<int64_t>(steps_per_trial, s->remaining());
-        if (nodes == 0) continue;
-        HIPCHK(hipEventRecord(a, eng.stream()));
-        int left = steps_per_trial;
-        while (left > 0 && !eng.members().empty()) {
-          const int k = std::min(left, K);
-          eng.run_chunk(k, k == K);
-          left -= k;
-        }
-        HIPCHK(hipEventRecord(b, eng.stream()));
-        HIPCHK(hipEventSynchronize(b));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, a, b));
-        const double per = ms / nodes;
-        if (per < best) {
-          best = per;
-          bk = K;
-          bt = tile;
-        }
+      const double t = trial(tile, k_short);
+      if (t >= 0 && t < best) {
+        best = t;
+        bk = k_short;
+        bt = tile;
+      }
+    }
+    if (best < 1e300) {
+      const double t = trial(bt, k_long);
+      if (t >= 0 && t < best) {
+        best = t;
+        bk = k_long;
       }
     }
     (void)hipEventDestroy(a);

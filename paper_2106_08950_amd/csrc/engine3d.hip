@@ -139,6 +139,7 @@ struct dilbm3d_solver {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   double timed_ms = 0.0;
   int64_t timed_launches = 0;
+  std::vector<float> launch_ms;  // every timed collide launch, in launch order
 };
 
 namespace dilbm {
@@ -294,6 +295,7 @@ void collect_timing3(dilbm3d_solver &s) {
     HIPCHK3(hipEventElapsedTime(&ms, ev.first, ev.second));
     s.timed_ms += ms;
     ++s.timed_launches;
+    s.launch_ms.push_back(ms);
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
@@ -571,6 +573,18 @@ dilbm_status dilbm3d_set_kernel_timing(dilbm3d_solver *s, int32_t enable) {
     s->timing = enable != 0;
     s->timed_ms = 0.0;
     s->timed_launches = 0;
+    s->launch_ms.clear();
+  });
+}
+
+dilbm_status dilbm3d_get_kernel_launch_times(dilbm3d_solver *s, double *ms, int64_t cap,
+                                             int64_t *count) {
+  if (!s || cap < 0 || (cap > 0 && !ms)) return DILBM_EINVAL;
+  return guard3(&s->last_error, [&] {
+    collect_timing3(*s);
+    const int64_t n = std::min<int64_t>(cap, (int64_t)s->launch_ms.size());
+    for (int64_t i = 0; i < n; ++i) ms[i] = s->launch_ms[i];
+    if (count) *count = (int64_t)s->launch_ms.size();
   });
 }
 

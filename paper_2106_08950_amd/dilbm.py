@@ -34,7 +34,8 @@ EXPORTED = [
     "dilbm_get_particles",
     "dilbm_get_wall_force", "dilbm_get_step_count", "dilbm_get_body_count",
     "dilbm_set_kernel_timing",
-    "dilbm_get_kernel_timing", "dilbm_destroy", "dilbm_last_error",
+    "dilbm_get_kernel_timing", "dilbm_get_kernel_launch_times", "dilbm_destroy",
+    "dilbm_last_error",
     "dilbm_pool_create", "dilbm_pool_submit", "dilbm_pool_run", "dilbm_pool_sync",
     "dilbm_pool_query", "dilbm_pool_get_fields", "dilbm_pool_get_particles",
     "dilbm_pool_get_particle_forces", "dilbm_pool_release", "dilbm_pool_set_launch",
@@ -111,6 +112,7 @@ def load():
         "dilbm_get_body_count": (I32, [V, C.POINTER(I32)]),
         "dilbm_set_kernel_timing": (I32, [V, I32]),
         "dilbm_get_kernel_timing": (I32, [V, C.POINTER(D), C.POINTER(I64)]),
+        "dilbm_get_kernel_launch_times": (I32, [V, _dp, I64, C.POINTER(I64)]),
         "dilbm_destroy": (None, [V]),
         "dilbm_last_error": (C.c_char_p, [V]),
         "dilbm_pool_create": (I32, [I32, V, V, U64, C.POINTER(V)]),
@@ -352,6 +354,17 @@ class Solver:
         self._check(self._lib.dilbm_get_kernel_timing(self._h, C.byref(ms), C.byref(n)),
                     "dilbm_get_kernel_timing")
         return float(ms.value), int(n.value)
+
+    def kernel_launch_times(self):
+        """Every timed collide launch since timing was enabled (milliseconds)."""
+        n = C.c_int64()
+        self._check(self._lib.dilbm_get_kernel_launch_times(self._h, None, 0, C.byref(n)),
+                    "dilbm_get_kernel_launch_times")
+        out = np.zeros(max(int(n.value), 1))
+        self._check(self._lib.dilbm_get_kernel_launch_times(self._h, _ptr(out), int(n.value),
+                                                            C.byref(n)),
+                    "dilbm_get_kernel_launch_times")
+        return out[: int(n.value)]
 
 
 class Pool:

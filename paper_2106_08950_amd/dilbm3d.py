@@ -22,7 +22,7 @@ EXPORTED = [
     "dilbm3d_set_populations", "dilbm3d_get_populations", "dilbm3d_step",
     "dilbm3d_get_fields", "dilbm3d_get_particle_forces", "dilbm3d_get_particles",
     "dilbm3d_get_wall_force", "dilbm3d_set_kernel_timing", "dilbm3d_get_kernel_timing",
-    "dilbm3d_destroy", "dilbm3d_last_error",
+    "dilbm3d_get_kernel_launch_times", "dilbm3d_destroy", "dilbm3d_last_error",
 ]
 
 
@@ -68,6 +68,7 @@ def load():
         "dilbm3d_get_wall_force": (I32, [V, _dp]),
         "dilbm3d_set_kernel_timing": (I32, [V, I32]),
         "dilbm3d_get_kernel_timing": (I32, [V, C.POINTER(D), C.POINTER(I64)]),
+        "dilbm3d_get_kernel_launch_times": (I32, [V, _dp, I64, C.POINTER(I64)]),
         "dilbm3d_destroy": (None, [V]),
         "dilbm3d_last_error": (C.c_char_p, [V]),
     }
@@ -246,3 +247,14 @@ class Solver3D:
         self._check(load().dilbm3d_get_kernel_timing(self._h, C.byref(ms), C.byref(n)),
                     "dilbm3d_get_kernel_timing")
         return ms.value, n.value
+
+    def kernel_launch_times(self):
+        """Every timed collide launch since timing was enabled (milliseconds)."""
+        n = C.c_int64()
+        self._check(load().dilbm3d_get_kernel_launch_times(self._h, None, 0, C.byref(n)),
+                    "dilbm3d_get_kernel_launch_times")
+        out = np.zeros(max(int(n.value), 1))
+        self._check(load().dilbm3d_get_kernel_launch_times(self._h, _ptr(out), int(n.value),
+                                                           C.byref(n)),
+                    "dilbm3d_get_kernel_launch_times")
+        return out[: int(n.value)]

@@ -87,6 +87,66 @@ def test_one_step_matches_oracle(seed, nx, ny, nb, walls, tile):
     assert velocity_rel_l2(uxg, uyg, uxo, uyo) < 1e-5
 
 
+@pytest.mark.parametrize("seed,nx,ny,nb,walls", [(21, 16, 16, 3, 3), (22, 77, 45, 6, 1),
+                                                 (23, 200, 37, 12, 2)])
+@pytest.mark.parametrize("tile", [0, 2])
+def test_one_step_paper_literal_force_scale(seed, nx, ny, nb, walls, tile):
+    """Eqs. (18)-(19) with the printed scale: force and torque are -sum phi sum_i c_i F_i,
+    (1 - 1/2tau) times the momentum-exchange value; the populations do not change."""
+    wl, f0 = _random_case(seed, nx, ny, nb, walls)
+    wl = inputs.Workload(**{**wl.__dict__, "force_mode": 1})
+    log_case(f"one step, literal force scale, seed={seed} {nx}x{ny} walls={walls} tile={tile}")
+    o = oracle_solver(wl)
+    o.set_populations(f0)
+    o.step(1)
+    g = gpu_solver(wl, tile=tile)
+    g.set_populations(f0)
+    g.step(1)
+    fo = o.get_populations()
+    fg = g.get_populations()
+    assert np.abs(fg - fo).max() / np.abs(fo).max() <= STEP_TOL
+    Fo, To = o.get_particle_forces()
+    Fg, Tg = g.get_particle_forces()
+    assert np.abs(Fg - Fo).max() <= 1e-4 * max(np.abs(Fo).max(), 1e-30), (Fg, Fo)
+    assert np.abs(Tg - To).max() <= 1e-4 * max(np.abs(To).max(), 1e-30)
+    if walls:
+        Wo, Wg = o.get_wall_force(), g.get_wall_force()
+        assert np.abs(Wg - Wo).max() <= 1e-4 * np.abs(Wo).max()
+    # against the momentum-exchange run from the same state: exactly the factor apart
+    o0 = oracle_solver(inputs.Workload(**{**wl.__dict__, "force_mode": 0}))
+    o0.set_populations(f0)
+    o0.step(1)
+    F0, _ = o0.get_particle_forces()
+    k = 1.0 - 1.0 / (2.0 * wl.tau)
+    assert np.allclose(Fo, k * F0, rtol=1e-12, atol=1e-18 * max(np.abs(F0).max(), 1.0))
+    xo, uo, wo = o.get_particles()
+    xg, ug, wg = g.get_particles()
+    assert np.abs(xg - xo).max() < 1e-9
+    assert np.abs((wg - wl.omega) - (wo - wl.omega)).max() <= (
+        1e-4 * max(np.abs(wo - wl.omega).max(), 1e-30) + 1e-15)
+
+
+@pytest.mark.parametrize("seed,walls", [(31, 0), (32, 3)])
+def test_many_steps_paper_literal_force_scale(seed, walls):
+    wl, f0 = _random_case(seed, 80, 64, 6, walls, overlap=False, amp=2e-4)
+    wl = inputs.Workload(**{**wl.__dict__, "force_mode": 1})
+    log_case(f"300 steps, literal force scale, seed={seed} walls={walls}")
+    o = oracle_solver(wl)
+    o.set_populations(f0)
+    g = gpu_solver(wl)
+    g.set_populations(f0)
+    o.step(300)
+    g.step(300)
+    _, uxo, uyo = o.get_fields()
+    _, uxg, uyg = g.get_fields()
+    assert velocity_rel_l2(uxg, uyg, uxo, uyo) < 1e-5
+    xo, uo, wo = o.get_particles()
+    xg, ug, wg = g.get_particles()
+    d = np.abs(xg - xo)
+    d = np.minimum(d, [wl.nx, wl.ny] - d)
+    assert d.max() < 1e-4
+
+
 @pytest.mark.parametrize("seed,nx,ny,nb,walls", [(11, 64, 48, 5, 0), (12, 90, 70, 6, 3)])
 def test_many_steps_match_oracle(seed, nx, ny, nb, walls):
     wl, f0 = _random_case(seed, nx, ny, nb, walls, overlap=False, amp=2e-4)
