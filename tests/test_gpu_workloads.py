@@ -107,14 +107,26 @@ def test_dense_suspension_1000_steps(storage):
     x, u, om = g.get_particles()
     rho, ux, uy = g.get_fields()
     pos_err = _wrap_err(x, gold["pos"], [wl.nx, wl.ny]).max()
-    u_err = velocity_rel_l2(ux[::32, ::32], uy[::32, ::32], gold["ux_s32"], gold["uy_s32"])
+    # the velocity on 16 full rows, 16 full columns and two 128 x 128 windows around discs
+    # (every node of each), and on every 32nd node in both directions
+    rows, cols, wins = gold["rows"], gold["cols"], gold["wins"]
+    w = int(gold["u_wins"].shape[-1])
+    g_parts = [np.stack([ux[rows], uy[rows]]).ravel(), np.stack([ux[:, cols], uy[:, cols]]).ravel()]
+    o_parts = [gold["u_rows"].ravel(), gold["u_cols"].ravel()]
+    for k, (x0, y0) in enumerate(wins):
+        g_parts.append(np.stack([ux[y0:y0 + w, x0:x0 + w], uy[y0:y0 + w, x0:x0 + w]]).ravel())
+        o_parts.append(gold["u_wins"][k].ravel())
+    gs, os_ = np.concatenate(g_parts), np.concatenate(o_parts).astype(np.float64)
+    u_err = float(np.linalg.norm(gs - os_) / np.linalg.norm(os_))
+    u_err_s32 = velocity_rel_l2(ux[::32, ::32], uy[::32, ::32], gold["ux_s32"], gold["uy_s32"])
     vel_err = np.abs(u - gold["vel"]).max() / np.abs(gold["vel"]).max()
-    print(f"suspension storage={storage}: position error {pos_err:.3e}, u rel L2 {u_err:.3e}, "
-          f"body velocity rel error {vel_err:.3e}")
+    print(f"suspension storage={storage}: position error {pos_err:.3e}, u rel L2 (rows, "
+          f"columns, windows) {u_err:.3e}, every 32nd node {u_err_s32:.3e}, body velocity rel "
+          f"error {vel_err:.3e}")
     if storage == dilbm.STORE_FP32:
-        assert pos_err <= 1e-4 and u_err <= 1e-5
+        assert pos_err <= 1e-4 and u_err <= 1e-5 and u_err_s32 <= 1e-5
     else:
-        assert pos_err <= 1e-2 and u_err <= 2e-3
+        assert pos_err <= 1e-2 and u_err <= 2e-3 and u_err_s32 <= 2e-3
 
 
 def test_dense_suspension_one_step_full_size():
@@ -144,35 +156,34 @@ def test_dense_suspension_one_step_full_size():
     assert _wrap_err(xg, xo, [wl.nx, wl.ny]).max() < 1e-9
 
 
-def test_maximum_lattice_size_by_windows():
-    """nx * ny just below 2^31 (65536 x 32767, 155 GB of FP32 populations): a disc across
-    both periodic seams and one at large coordinates, 4 steps from rest under a body
-    force.  Nodes farther than the support plus 4 steps are untouched by the discs and
-    have u = (n + 1/2) G exactly; the neighbourhood of each disc equals a small periodic
-    oracle solve holding the same disc at the same place relative to its window."""
-    nx, ny, steps, W = 65536, 32767, 4, 96
-    G = (1e-5, 2e-6)
-    discs = np.array([[nx - 2.7, ny - 3.4], [40000.3, 20000.6]])
-    R = 6.0
-    wl = inputs.Workload(name="max", nx=nx, ny=ny, tau=0.8, nsteps=steps, G=G,
-                         **inputs._bodies(discs, [R, R], [1.3, 1.3]))
-    log_case("maximum lattice 65536x32767 FP32 (155 GB)")
-    g = gpu_solver(wl)
-    g.step(steps)
+def _check_by_windows(g, nx, ny, steps, G, discs, R, rho_s, W=96, tol=1e-5, far=8):
+    """A solve started from rest under a body force G, advanced `steps` steps: nodes
+    farther than the support plus `steps` from every disc are untouched by them and have
+    u = (n + 1/2) G; the neighbourhood of each disc equals a small periodic oracle solve
+    holding the same disc at the same place relative to its window (stitched across the
+    periodic seams)."""
     xg, ug, wg = g.get_particles()
     Fg, Tg = g.get_particle_forces()
-    # far field
     rng = np.random.default_rng(1)
-    for _ in range(8):
-        x0 = int(rng.integers(0, nx - 8))
-        y0 = int(rng.integers(100, 15000))
+    for _ in range(far):
+        while True:
+            x0 = int(rng.integers(0, nx - 8))
+            y0 = int(rng.integers(0, ny - 8))
+            d = np.abs(np.asarray(discs) - [x0 + 4, y0 + 4])
+            d = np.minimum(d, [nx, ny] - d)
+            if np.all(np.hypot(d[:, 0], d[:, 1]) > R + 8 + steps + 16):
+                break
         rho, ux, uy = g.get_fields_region(x0, y0, 8, 8)
-        assert np.allclose(ux, (steps + 0.5) * G[0], rtol=1e-5, atol=0)
-        assert np.allclose(uy, (steps + 0.5) * G[1], rtol=1e-5, atol=0)
-    # windows around each disc (the first one stitched across the seams)
+        if tol <= 1e-5:  # FP32: every node
+            assert np.allclose(ux, (steps + 0.5) * G[0], rtol=1e-5, atol=0)
+            assert np.allclose(uy, (steps + 0.5) * G[1], rtol=1e-5, atol=0)
+        else:  # FP16: relative L2 over the 8 x 8 window
+            e = velocity_rel_l2(ux, uy, np.full_like(ux, (steps + 0.5) * G[0]),
+                                np.full_like(uy, (steps + 0.5) * G[1]))
+            assert e <= tol, e
     h = W // 2
-    for b in range(2):
-        cx, cy = int(np.floor(discs[b, 0])), int(np.floor(discs[b, 1]))
+    for b in range(len(discs)):
+        cx, cy = int(np.floor(discs[b][0])), int(np.floor(discs[b][1]))
         ox, oy = cx - h, cy - h   # window origin (may be negative or past the end: wraps)
         ux_w = np.empty((W, W))
         uy_w = np.empty((W, W))
@@ -190,16 +201,59 @@ def test_maximum_lattice_size_by_windows():
                 uy_w[j, i:i + run] = c[0]
                 i += run
         small = inputs.Workload(name="win", nx=W, ny=W, tau=0.8, nsteps=steps, G=G,
-                                **inputs._bodies([[discs[b, 0] - ox, discs[b, 1] - oy]], [R],
-                                                 [1.3]))
+                                **inputs._bodies([[discs[b][0] - ox, discs[b][1] - oy]], [R],
+                                                 [rho_s]))
         o = oracle_solver(small)
         o.step(steps)
         ro, uxo, uyo = o.get_fields()
-        assert velocity_rel_l2(ux_w, uy_w, uxo, uyo) < 1e-5
+        err = velocity_rel_l2(ux_w, uy_w, uxo, uyo)
+        assert err < tol, (b, err)
         xo, uo, wo = o.get_particles()
         assert np.abs((xg[b] - [ox, oy]) % [nx, ny] - xo[0]).max() < 1e-9
         Fo, To = o.get_particle_forces()
-        assert np.abs(Fg[b] - Fo[0]).max() <= 1e-4 * np.abs(Fo[0]).max()
+        assert np.abs(Fg[b] - Fo[0]).max() <= max(tol, 1e-4) * np.abs(Fo[0]).max()
+
+
+@pytest.mark.parametrize("storage,nx,ny,tile", [
+    (dilbm.STORE_FP32, 8192, 8192, -1),   # 2.4 GB per population buffer: 32-bit plane offsets
+    (dilbm.STORE_FP32, 8192, 8192, 0),    # the same with 64 x 4 tiles (chunked order)
+    (dilbm.STORE_FP16, 16384, 8192, -1),  # FP16, 2.4 GB per buffer
+])
+def test_plane_offset_addressing_by_windows(storage, nx, ny, tile):
+    """Lattices whose population buffer passes 2 GB but whose planes stay under it take the
+    collide instances with a scalar plane base and 32-bit offsets.  Discs across both
+    periodic seams and at large coordinates; 4 steps from rest under a body force, checked
+    far from the discs and by windows around each."""
+    steps = 4
+    G = (1e-5, 2e-6)
+    discs = [[nx - 2.7, ny - 3.4], [nx - 5000.3, ny - 1000.6], [3.2, 4100.7]]
+    R, rho_s = 6.0, 1.3
+    wl = inputs.Workload(name="g32", nx=nx, ny=ny, tau=0.8, nsteps=steps, G=G,
+                         **inputs._bodies(discs, [R] * 3, [rho_s] * 3))
+    log_case(f"plane-offset addressing {nx}x{ny} storage={storage} tile={tile}")
+    g = gpu_solver(wl, storage=storage, tile=tile)
+    g.step(steps)
+    _check_by_windows(g, nx, ny, steps, G, discs, R, rho_s,
+                      tol=1e-5 if storage == dilbm.STORE_FP32 else 2e-3)
+    g.close()
+
+
+def test_maximum_lattice_size_by_windows():
+    """nx * ny just below 2^31 (65536 x 32767, 155 GB of FP32 populations): a disc across
+    both periodic seams and one at large coordinates, 4 steps from rest under a body
+    force.  Nodes farther than the support plus 4 steps are untouched by the discs and
+    have u = (n + 1/2) G exactly; the neighbourhood of each disc equals a small periodic
+    oracle solve holding the same disc at the same place relative to its window."""
+    nx, ny, steps = 65536, 32767, 4
+    G = (1e-5, 2e-6)
+    discs = [[nx - 2.7, ny - 3.4], [40000.3, 20000.6]]
+    R, rho_s = 6.0, 1.3
+    wl = inputs.Workload(name="max", nx=nx, ny=ny, tau=0.8, nsteps=steps, G=G,
+                         **inputs._bodies(discs, [R, R], [rho_s, rho_s]))
+    log_case("maximum lattice 65536x32767 FP32 (155 GB)")
+    g = gpu_solver(wl)
+    g.step(steps)
+    _check_by_windows(g, nx, ny, steps, G, discs, R, rho_s)
     g.close()
 
 
