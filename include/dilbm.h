@@ -171,6 +171,17 @@ dilbm_status dilbm_get_fields(dilbm_solver *s, double *rho, double *ux, double *
 dilbm_status dilbm_get_fields_region(dilbm_solver *s, int32_t x0, int32_t y0, int32_t w,
                                      int32_t h, double *rho, double *ux, double *uy);
 
+/* The same as dilbm_get_fields_region for callers that cannot allocate memory (code
+ * under HIP graph capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc): it allocates nothing.  The values go through a fixed device staging
+ * array of 3 x 2^20 FP64 (24 MiB, held on each GPU the library runs on until the process
+ * ends) instead of a buffer of the handle's.  w * h must be at most 2^20 (1048576) nodes,
+ * else DILBM_EINVAL and nothing is read.  All calls on one GPU share the array: calls
+ * that overlap on one GPU (other threads, other handles) race and must be serialised by
+ * the caller. */
+dilbm_status dilbm_get_fields_region_noalloc(dilbm_solver *s, int32_t x0, int32_t y0, int32_t w,
+                                             int32_t h, double *rho, double *ux, double *uy);
+
 /* Force [n][2] and torque [n] on each body by the fluid in the last completed step
  * (zeros before the first step), Eqs. (18)-(19) with the sign printed there. */
 dilbm_status dilbm_get_particle_forces(dilbm_solver *s, double *force, double *torque);

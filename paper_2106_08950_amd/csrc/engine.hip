@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1027,6 +1028,33 @@ void get_fields_of(Engine &eng, Solve &s, hipStream_t st, double **scratch, uint
   fields_through(eng, s, st, *scratch, rg, rho, ux, uy);
 }
 
+// ---------------------------------------------------------------------------------------
+// Staging for dilbm_get_fields_region_noalloc: a fixed device array, so that the call
+// allocates nothing.  Each GPU holds its own copy until the process ends; every call on a
+// GPU shares it (calls that overlap on one GPU race).  Host code never uses the array's
+// name as an address: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+
+constexpr int64_t kNoAllocMaxNodes = (int64_t)1 << 20;  // 3 x 8 MiB of FP64
+static __device__ __align__(256) double scratch[3 * kNoAllocMaxNodes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+double *scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(DILBM_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(DILBM_EDEVICE, "no device address for the staging array");
+    g_scratch_ptr[device] = (double *)p;
+  }
+  return g_scratch_ptr[device];
+}
+
 }  // namespace dilbm
 
 // =======================================================================================
@@ -1315,6 +1343,20 @@ dilbm_status dilbm_get_fields_region(dilbm_solver *h, int32_t x0, int32_t y0, in
     HIPCHK(hipSetDevice(h->eng->device()));
     get_fields_of(*h->eng, h->s, h->eng->stream(), &h->scratch, &h->scratch_n,
                   Region{x0, y0, w, hgt}, rho, ux, uy);
+  });
+}
+
+dilbm_status dilbm_get_fields_region_noalloc(dilbm_solver *h, int32_t x0, int32_t y0, int32_t w,
+                                             int32_t hgt, double *rho, double *ux, double *uy) {
+  if (!h) return DILBM_EINVAL;
+  return guard(&h->last_error, [&] {
+    const Region rg{x0, y0, w, hgt};
+    check_region(h->s, rg);
+    if ((int64_t)w * hgt > kNoAllocMaxNodes)
+      fail(DILBM_EINVAL, "region larger than the fixed staging array (2^20 nodes)");
+    double *b = scratch_on(h->eng->device());
+    HIPCHK(hipSetDevice(h->eng->device()));
+    fields_through(*h->eng, h->s, h->eng->stream(), b, rg, rho, ux, uy);
   });
 }
 

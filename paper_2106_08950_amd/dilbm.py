@@ -30,7 +30,8 @@ ABI_VERSION = 2
 EXPORTED = [
     "dilbm_params_init", "dilbm_num_tile_shapes", "dilbm_tile_shape", "dilbm_footprint",
     "dilbm_create", "dilbm_set_particles", "dilbm_set_populations", "dilbm_get_populations",
-    "dilbm_step", "dilbm_get_fields", "dilbm_get_fields_region", "dilbm_get_particle_forces",
+    "dilbm_step", "dilbm_get_fields", "dilbm_get_fields_region",
+    "dilbm_get_fields_region_noalloc", "dilbm_get_particle_forces",
     "dilbm_get_particles",
     "dilbm_get_wall_force", "dilbm_get_step_count", "dilbm_get_body_count",
     "dilbm_set_kernel_timing",
@@ -105,6 +106,7 @@ def load():
         "dilbm_step": (I32, [V, I64]),
         "dilbm_get_fields": (I32, [V, _dp, _dp, _dp]),
         "dilbm_get_fields_region": (I32, [V, I32, I32, I32, I32, _dp, _dp, _dp]),
+        "dilbm_get_fields_region_noalloc": (I32, [V, I32, I32, I32, I32, _dp, _dp, _dp]),
         "dilbm_get_particle_forces": (I32, [V, _dp, _dp]),
         "dilbm_get_particles": (I32, [V, _dp, _dp, _dp]),
         "dilbm_get_wall_force": (I32, [V, _dp]),
@@ -317,6 +319,17 @@ class Solver:
         self._check(self._lib.dilbm_get_fields_region(self._h, int(x0), int(y0), int(w), int(h),
                                                       _ptr(rho), _ptr(ux), _ptr(uy)),
                     "dilbm_get_fields_region")
+        return rho, ux, uy
+
+    def get_fields_region_noalloc(self, x0, y0, w, h):
+        """dilbm_get_fields_region_noalloc: the same values through the library's fixed
+        staging array (no device allocation)."""
+        rho = np.empty((h, w))
+        ux = np.empty((h, w))
+        uy = np.empty((h, w))
+        self._check(self._lib.dilbm_get_fields_region_noalloc(
+            self._h, int(x0), int(y0), int(w), int(h), _ptr(rho), _ptr(ux), _ptr(uy)),
+            "dilbm_get_fields_region_noalloc")
         return rho, ux, uy
 
     def get_particle_forces(self):
