@@ -100,7 +100,9 @@ typedef struct dilbm_params {
   int32_t fp16_scale_log2;     /* FP16 storage keeps 36 (f - w rho0) * 2^k; k in [0, 24] */
   int32_t list_capacity;       /* bodies per tile list; 0 = min(n_bodies, 128) */
   int32_t tile;                /* tile shape id (dilbm_tile_shape); -1 = default: 256 x 1
-                                  for FP32 storage with nx >= 1024, else 64 x 4 */
+                                  for FP32 storage with nx >= 1024, else 64 x 4.  Shape 5
+                                  (512 x 1, two nodes per lane) needs FP16 storage and an
+                                  even nx */
   int32_t x_boundary;          /* DILBM_XBC_*; INLET_OUTLET needs nx >= 3, no DILBM_WALL_X */
   int32_t inlet_kind;          /* DILBM_INLET_*: VELOCITY prescribes inlet_velocity and
                                   takes rho from the neighbour; PRESSURE prescribes
@@ -125,7 +127,8 @@ typedef struct dilbm_solver dilbm_solver;
  * nx and ny are set to 0 and must be filled in. */
 void dilbm_params_init(dilbm_params *p);
 
-/* Number of tile shapes and the node extent (tx, ty) of shape `id`. */
+/* Number of tile shapes and the node extent (tx, ty) of shape `id`: shapes 0-4 hold 256
+ * nodes (one per lane of a 256-thread block), shape 5 holds 512 (two per lane). */
 int32_t dilbm_num_tile_shapes(void);
 dilbm_status dilbm_tile_shape(int32_t id, int32_t *tx, int32_t *ty);
 

@@ -35,10 +35,13 @@
 namespace dilbm {
 
 constexpr int kQ = 9;
-constexpr int kNumTileShapes = 5;
-constexpr int kTileTX[kNumTileShapes] = {64, 128, 256, 32, 16};
-constexpr int kTileTY[kNumTileShapes] = {4, 2, 1, 8, 16};
-constexpr int kBlockThreads = 256;       // every tile shape has 256 nodes
+// Tile shapes (nodes): 0-4 hold 256 nodes, one per lane; 5 is a 512-node row segment with
+// two neighbouring nodes per lane, for FP16 populations on lattices of even width.
+constexpr int kNumTileShapes = 6;
+constexpr int kTileTX[kNumTileShapes] = {64, 128, 256, 32, 16, 512};
+constexpr int kTileTY[kNumTileShapes] = {4, 2, 1, 8, 16, 1};
+constexpr int kPairShape = 5;
+constexpr int kBlockThreads = 256;       // threads of every collide block
 constexpr int kMaxListCap = 1024;
 // A tile-list entry: the body index in the low 27 bits and, in bits 27-30, which of the
 // tile's four waves hold a node within the body's support (set by the binning; a wave
@@ -57,6 +60,10 @@ constexpr int32_t kListIndexMask = (1 << kListIndexBits) - 1;
 #endif
 #ifndef DILBM_COLLIDE_WAVES_F16
 #define DILBM_COLLIDE_WAVES_F16 7
+#endif
+// the same for the FP16 instance with two nodes per lane (512-node tiles)
+#ifndef DILBM_COLLIDE_WAVES_X2
+#define DILBM_COLLIDE_WAVES_X2 5
 #endif
 // Persistent collide grid: each block walks one contiguous chunk of about this many tiles,
 // per population storage type (0 = one block per tile); the grid never drops below one

@@ -140,6 +140,12 @@ int max_tiles_for(int nx, int ny) {
   return m;
 }
 
+// Tile shape 5 holds two neighbouring nodes per lane: FP16 populations on an even nx.
+bool shape_fits(int shape, const dilbm_params &p) {
+  if (shape != kPairShape) return true;
+  return p.storage == DILBM_STORE_FP16 && (p.nx % 2) == 0;
+}
+
 void validate(const dilbm_params *p) {
   if (!p) fail(DILBM_EINVAL, "params is NULL");
   if (p->abi_version != DILBM_ABI_VERSION) fail(DILBM_EABI, "abi_version mismatch");
@@ -169,6 +175,9 @@ void validate(const dilbm_params *p) {
   if (p->list_capacity < 0 || p->list_capacity > kMaxListCap)
     fail(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
   if (p->tile < -1 || p->tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
+  if (p->tile >= 0 && !shape_fits(p->tile, *p))
+    fail(DILBM_EINVAL, "tile shape 5 (512 x 1, two nodes per lane) needs FP16 storage and an "
+                       "even nx");
   if (p->x_boundary != DILBM_XBC_PERIODIC && p->x_boundary != DILBM_XBC_INLET_OUTLET)
     fail(DILBM_EINVAL, "unknown x_boundary");
   if (p->x_boundary == DILBM_XBC_INLET_OUTLET) {
@@ -236,7 +245,9 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
 }
 
 // Default tile shape of a plain solve: whole-row 256 x 1 tiles (natural collide order)
-// for FP32 populations on rows of 1024 nodes or more, else 64 x 4.
+// for FP32 populations on rows of 1024 nodes or more, else 64 x 4.  (FP16 in 512 x 1
+// tiles with two nodes per lane measured slower than 64 x 4 on the 4096^2 suspension:
+// 168 against about 150 us per collide launch.)
 int default_shape(const dilbm_params &p) {
   return (p.storage == DILBM_STORE_FP32 && p.nx >= 1024) ? 2 : 0;
 }
@@ -764,7 +775,9 @@ class Engine {
   // against 5.4 for the best chunked order in a copy probe with the same access pattern,
   // 6% faster for the FP32 step.  Other shapes, and FP16 (whose natural-order step is 25%
   // slower), sweep XCD-contiguous chunks.
-  bool natural_order() const { return storage_ == DILBM_STORE_FP32 && kTileTX[shape_] == 256; }
+  bool natural_order() const {
+    return (storage_ == DILBM_STORE_FP32 && kTileTX[shape_] == 256) || shape_ == kPairShape;
+  }
 
   int collide_grid_for(int64_t T) {
     if (natural_order()) return (int)std::max<int64_t>(1, std::min<int64_t>(T, (int64_t)1 << 30));
@@ -1487,6 +1500,11 @@ dilbm_status dilbm_pool_submit(dilbm_pool *pool, const dilbm_params *prm, int32_
     HIPCHK(hipSetDevice(eng.device()));
     if (!eng.members().empty() && prm->storage != eng.storage())
       fail(DILBM_EINVAL, "all members of a pool share one storage type");
+    const int want = pool->solves.empty() && eng.members().empty() && pool->pending_shape >= 0
+                         ? pool->pending_shape
+                         : eng.shape();
+    if (!shape_fits(want, *prm))
+      fail(DILBM_EINVAL, "the pool's tile shape 5 needs FP16 storage and an even nx");
     process_deferred(pool);
     const BodyLayout L = body_layout(*prm, n);
     const uint64_t need = pop_bytes(*prm) + L.total;
@@ -1677,6 +1695,9 @@ dilbm_status dilbm_pool_set_launch(dilbm_pool *pool, int32_t graph_steps, int32_
   return guard(&pool->last_error, [&] {
     if (graph_steps < 1 || graph_steps > 256) fail(DILBM_EINVAL, "graph_steps in [1, 256]");
     if (tile < -1 || tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
+    if (tile >= 0)
+      for (Solve *m : pool->eng->members())
+        if (!shape_fits(tile, m->prm)) fail(DILBM_EINVAL, "tile shape does not fit a member");
     HIPCHK(hipSetDevice(pool->eng->device()));
     pool->eng->set_graph_steps(graph_steps);
     if (tile >= 0) {
@@ -1723,6 +1744,9 @@ dilbm_status dilbm_pool_autotune(dilbm_pool *pool, int32_t steps_per_trial,
     double best = 1e300;
     int bk = eng.graph_steps(), bt = eng.shape();
     for (int tile = 0; tile < kNumTileShapes; ++tile) {
+      bool fits = true;
+      for (Solve *m : eng.members()) fits = fits && shape_fits(tile, m->prm);
+      if (!fits) continue;
       const double t = trial(tile, k_short);
       if (t >= 0 && t < best) {
         best = t;

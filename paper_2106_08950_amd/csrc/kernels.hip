@@ -81,16 +81,18 @@ struct StoreF16 {
   static constexpr bool kFrame = false;
   static constexpr int kRefLog2 = 0;
   static constexpr bool kStochastic = true;
-  // v * scale rounded stochastically to FP16, with byte k of h as the random bits.  The
-  // gfx950 conversion v_cvt_sr_f16_f32 adds the top 13 bits of its random operand to the
-  // 13 FP32 mantissa bits that FP16 drops, then truncates (normal range).  The operand is
-  // byte k on top and one set bit below it (a single v_perm_b32 builds it), so the
-  // rounding point sits at (r + 1/2) / 256 of an ulp, r uniform on 0..255: the stored
-  // value rounds up with its distance from the lower neighbour, to 1/256 ulp.
+  // v * scale rounded stochastically to FP16.  The gfx950 conversion v_cvt_sr_f16_f32 adds
+  // the top 13 bits of its random operand to the 13 FP32 mantissa bits that FP16 drops,
+  // then truncates (normal range), so with 13 uniform random bits the stored value rounds
+  // up with exactly its distance from the lower neighbour: unbiased for every FP32 input.
+  // (Eight random bits leave a bias of up to 1/512 ulp that depends on where the value
+  // sits between its neighbours; in a slowly varying flow it repeats from step to step,
+  // and it moved the settling disc of the FP16 tests by 9e-3 lattice units in 20 000
+  // steps, against 1.6e-3 with 13 bits.)  h supplies 32 random bits; odd k take the word
+  // rotated by 13, so one word serves two populations with disjoint bits.
   static __device__ __forceinline__ uint16_t round_bits(float v, float scale, uint32_t h,
                                                         int k) {
-    const uint32_t rnd =
-        __builtin_amdgcn_perm(h, 0x00800000u, ((4u + (uint32_t)k) << 24) | 0x00020C0Cu);
+    const uint32_t rnd = (k & 1) ? __builtin_amdgcn_alignbit(h, h, 13) : h;
     const float x = v * scale;
     // the conversion writes the low half of its destination; seeding that register with
     // x itself costs no move (its high half is never stored)
@@ -359,14 +361,15 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
                                              double *__restrict__ out_rho,
                                              double *__restrict__ out_ux,
                                              double *__restrict__ out_uy,
-                                             const Region region) {
+                                             const Region region, const int xoff) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int nx = d.nx, ny = d.ny;
   const int tyi = lt / d.tiles_x;
   const int txi = lt - tyi * d.tiles_x;
   const int x0 = txi * TX, y0 = tyi * TY;
-  const int x = x0 + (tid % TX);
+  // xoff: the second half of a 512-node tile, read by the fields pass in two halves
+  const int x = x0 + xoff + (tid % TX);
   // a wave covers part of one row when the tile is at least 64 wide: its row is uniform
   const int y = TX >= 64 ? __builtin_amdgcn_readfirstlane(y0 + tid / TX) : y0 + tid / TX;
   const bool valid = (x < nx) && (y < ny);
@@ -541,7 +544,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
         return false;
       }
-      if (!((raw >> (kListIndexBits + wave)) & 1)) return false;
+      // the wave masks describe the step kernel's waves; the fields pass takes every
+      // listed body
+      if (MODE == kModeStep && !((raw >> (kListIndexBits + wave)) & 1)) return false;
       if (j == 0)
         sj = s0;
       else
@@ -729,14 +734,15 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const float sc = d.store_scale;
   uint16_t hb[kQ];  // FP16: the stochastically rounded halves
   if constexpr (ST::kStochastic) {
-    // 8 random bits per population from one hash of (node, step) and two xorshifts
+    // 13 random bits per population: five 32-bit words, one hash of (node, step) and four
+    // xorshifts, each serving two populations
     const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
-    const uint32_t h0 = lowbias32(((uint32_t)yc * (uint32_t)nx + (uint32_t)xc) ^ tk);
-    const uint32_t h1 = xorshift32(h0);
-    const uint32_t h2 = xorshift32(h1);
+    uint32_t hh[5];
+    hh[0] = lowbias32(((uint32_t)yc * (uint32_t)nx + (uint32_t)xc) ^ tk);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i)
-      hb[i] = ST::round_bits(out[i], sc, i < 4 ? h0 : (i < 8 ? h1 : h2), i & 3);
+    for (int r = 1; r < 5; ++r) hh[r] = xorshift32(hh[r - 1]);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) hb[i] = ST::round_bits(out[i], sc, hh[i >> 1], i & 1);
   }
   if (valid) {
     if (AM == kAddrBuf && TX >= 64) {
@@ -783,8 +789,389 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   }
 }
 
+// ---- FP16 populations, two nodes per lane --------------------------------------------
+// Whole-row tiles of 512 nodes: lane l of a block holds the neighbouring nodes
+// x0 + 2l and x0 + 2l + 1.  Every plane's row segment is then 1 KB, as for FP32 in
+// 256-node tiles, each lane moves its two populations of a plane in one 4-byte access,
+// and a wave keeps twice the bytes in flight of a one-node lane.  Pairs pulled across x
+// start at an odd element: those 4-byte loads are 2-byte aligned (gfx9 takes unaligned
+// dword loads in the unaligned access mode that the ROCm runtime sets); at the periodic
+// row ends the two halves are loaded separately.  Needs an even nx.  Per node the
+// arithmetic is that of process_tile.
+
+// Two neighbouring FP16 populations as floats times inv (the lower address first).
+__device__ __forceinline__ void unpack2(uint32_t v, float inv, float &a, float &b) {
+  a = (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu)) * inv;
+  b = (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)) * inv;
+}
+
+// Elements e0 and e1 of a row of FP16 populations as one 32-bit word (e0 in the low half):
+// one load when they are neighbours, else two.  Buffer form: `row` is the scalar byte
+// offset of the row inside the buffer; pointer form: `base` is the row's first element.
+__device__ __forceinline__ uint32_t ld_pair_buf(__amdgpu_buffer_rsrc_t r, uint32_t row, int e0,
+                                                int e1) {
+  if (e1 == e0 + 1) return __builtin_amdgcn_raw_buffer_load_b32(r, 2u * (uint32_t)e0, row, 0);
+  const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(r, 2u * (uint32_t)e0, row, 0);
+  const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(r, 2u * (uint32_t)e1, row, 0);
+  return lo | (hi << 16);
+}
+__device__ __forceinline__ uint32_t ld_pair_ptr(const uint16_t *base, int e0, int e1) {
+  if (e1 == e0 + 1) {
+    uint32_t v;
+    __builtin_memcpy(&v, base + e0, 4);
+    return v;
+  }
+  return (uint32_t)base[e0] | ((uint32_t)base[e1] << 16);
+}
+
+template <int AM, bool OPEN>
+__device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt, const int p,
+                                                const int64_t t, float (*red)[3][64]) {
+  using ST = StoreF16;
+  constexpr int TX = 512;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int nx = d.nx, ny = d.ny;
+  const int tyi = lt / d.tiles_x;
+  const int txi = lt - tyi * d.tiles_x;
+  const int x0 = txi * TX;
+  const int y = __builtin_amdgcn_readfirstlane(tyi);  // one row per tile: wave-uniform
+  const int xa = x0 + 2 * tid;                        // the lane's first node
+  const bool valid = xa < nx;                         // nx is even: both nodes or neither
+  const int xc = min(xa, nx - 2);                     // clamped: loads stay in bounds
+  const int ym = (y == 0) ? ny - 1 : y - 1;
+  const int yp = (y + 1 == ny) ? 0 : y + 1;
+  const float inv = d.store_inv;
+  const uint16_t *__restrict__ src = (const uint16_t *)d.pop[p];
+  uint16_t *__restrict__ dst = (uint16_t *)d.pop[p ^ 1];
+  const int64_t plane = (int64_t)nx * ny;
+  // elements pulled across x: c_x = +1 from (xc - 1, xc), c_x = -1 from (xc + 1, xc + 2)
+  const int em0 = xc == 0 ? nx - 1 : xc - 1, em1 = xc;
+  const int ep0 = xc + 1, ep1 = xc + 2 == nx ? 0 : xc + 2;
+
+  // ---- pull streaming (pairs) --------------------------------------------------------
+  uint32_t w[kQ];
+  if (AM == kAddrBuf) {
+    const uint32_t pb = (uint32_t)plane * 2u;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)(kQ * pb), kBufferFlags);
+    const uint32_t s0 = (uint32_t)(y * nx) * 2u, sm = (uint32_t)(ym * nx) * 2u,
+                   sp = (uint32_t)(yp * nx) * 2u;
+    w[0] = ld_pair_buf(rs, 0 * pb + s0, xc, xc + 1);
+    w[1] = ld_pair_buf(rs, 1 * pb + s0, em0, em1);
+    w[2] = ld_pair_buf(rs, 2 * pb + sm, xc, xc + 1);
+    w[3] = ld_pair_buf(rs, 3 * pb + s0, ep0, ep1);
+    w[4] = ld_pair_buf(rs, 4 * pb + sp, xc, xc + 1);
+    w[5] = ld_pair_buf(rs, 5 * pb + sm, em0, em1);
+    w[6] = ld_pair_buf(rs, 6 * pb + sm, ep0, ep1);
+    w[7] = ld_pair_buf(rs, 7 * pb + sp, ep0, ep1);
+    w[8] = ld_pair_buf(rs, 8 * pb + sp, em0, em1);
+  } else {
+    const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+    w[0] = ld_pair_ptr(src + 0 * plane + r0, xc, xc + 1);
+    w[1] = ld_pair_ptr(src + 1 * plane + r0, em0, em1);
+    w[2] = ld_pair_ptr(src + 2 * plane + rm, xc, xc + 1);
+    w[3] = ld_pair_ptr(src + 3 * plane + r0, ep0, ep1);
+    w[4] = ld_pair_ptr(src + 4 * plane + rp, xc, xc + 1);
+    w[5] = ld_pair_ptr(src + 5 * plane + rm, em0, em1);
+    w[6] = ld_pair_ptr(src + 6 * plane + rm, ep0, ep1);
+    w[7] = ld_pair_ptr(src + 7 * plane + rp, ep0, ep1);
+    w[8] = ld_pair_ptr(src + 8 * plane + rp, em0, em1);
+  }
+
+  // the tile's head and its first body's snapshot, in flight with the populations
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * (int64_t)lt);
+  const int32_t raw0 = (int32_t)(hv >> 32);
+  const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
+  const int nbs = d.nbodies;
+  const DILBM_CONST int32_t *list =
+      (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
+  const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
+  BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
+  if (nbs > 0) s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
+  if (tid == 0) d.tile_head[p ^ 1][2 * (int64_t)lt] = 0;  // lists of the next step start empty
+  if (lt == 0) {
+    double *a = d.acc[p ^ 1];
+    for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+  }
+
+  float f[2][kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) unpack2(w[i], inv, f[0][i], f[1][i]);
+
+  // ---- moments, Eqs. (5) and (16), per node (no storage frame with FP16) -------------
+  float rho[2], drho[2], Rinv[2], Jgx[2], Jgy[2], usx[2], usy[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float *g = f[k];
+    const float D = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float Jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const float Jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const float R = d.rho36 + D;
+    rho[k] = R * kInv36;
+    drho[k] = D * kInv36;
+    float ri = __builtin_amdgcn_rcpf(R);
+    Rinv[k] = fmaf(fmaf(-R, ri, 1.0f), ri, ri);
+    Jgx[k] = Jx + 18.0f * d.Gx;
+    Jgy[k] = Jy + 18.0f * d.Gy;
+    usx[k] = Jgx[k] * Rinv[k];
+    usy[k] = Jgy[k] * Rinv[k];
+  }
+
+  // ---- diffuse solid field, Eq. (14), per node ----------------------------------------
+  float Phi[2] = {0.f, 0.f}, Ax[2] = {0.f, 0.f}, Ay[2] = {0.f, 0.f};
+  float Mxx[2] = {0.f, 0.f}, Mxy[2] = {0.f, 0.f}, Myy[2] = {0.f, 0.f};
+  const float lcut = d.lcut;
+  const float phik = d.phi_k;
+  const float h = d.wall_h;
+  const bool wy = (d.wall_mask & 1u) && (y < d.wall_y_lo || y + 1 > d.wall_y_hi);
+  const bool wx = (d.wall_mask & 2u) && (x0 < d.wall_x_lo || x0 + TX > d.wall_x_hi);
+  const bool any_solid = (nb > 0) || wy || wx;
+  bool bnd[2] = {false, false};
+  if (OPEN && d.xbc && valid) {
+    bnd[0] = xa == 0;
+    bnd[1] = xa + 1 == nx - 1;
+  }
+
+  if (any_solid) {
+    float lwy = -1e30f, lwx[2] = {-1e30f, -1e30f};
+    if (wy) {
+      float dy = (float)y + 0.5f;
+      if (dy >= 0.5f * (float)ny) dy -= (float)ny;
+      lwy = h - fabsf(dy);
+    }
+    if (wx) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        float dx = (float)(xc + k) + 0.5f;
+        if (dx >= 0.5f * (float)nx) dx -= (float)nx;
+        lwx[k] = h - fabsf(dx);
+      }
+    }
+    const double ynode = (double)y + 0.5;
+    const double dnx = (double)nx, dny = (double)ny;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    auto body = [&](const int j, int &e, BodySnap &sj) -> bool {
+      const int32_t raw = j == 0 ? raw0 : list[j];
+      e = raw & kListIndexMask;
+      if (e >= nbs) {
+        if (lane == 0) atomicOr(d.err, (int32_t)kErrInternal);
+        return false;
+      }
+      if (!((raw >> (kListIndexBits + wave)) & 1)) return false;
+      if (j == 0)
+        sj = s0;
+      else
+        sj = load_snap(snap + e);
+      return true;
+    };
+    const float kap = d.kappa;
+    double *__restrict__ acc = d.acc[p];
+    bool own[2];
+    float S[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      own[k] = valid && !bnd[k];
+      S[k] = 0.f;
+      if (own[k] && wy && lwy >= lcut) S[k] += phi_of(lwy, phik);
+      if (own[k] && wx && lwx[k] >= lcut) S[k] += phi_of(lwx[k], phik);
+    }
+    auto reduce3 = [&](const int e, const float fx, const float fy, const float tq) {
+      float(*r)[64] = red[tid >> 6];
+      r[0][lane] = fx;
+      r[1][lane] = fy;
+      r[2][lane] = tq;
+      __builtin_amdgcn_wave_barrier();
+      double part = 0.0;
+      if (lane < 24) {
+        const float *q = &r[lane >> 3][(lane & 7) * 8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) part += (double)q[k];
+      }
+      __builtin_amdgcn_wave_barrier();
+      part += dpp_f64<0xB1>(part);   // quad_perm [1, 0, 3, 2]
+      part += dpp_f64<0x4E>(part);   // quad_perm [2, 3, 0, 1]
+      part += dpp_f64<0x141>(part);  // row_half_mirror: the eight lanes of a group
+      if (lane < 24 && (lane & 7) == 0) unsafeAtomicAdd(&acc[3 * e + (lane >> 3)], part);
+    };
+    // one pass with unit weights (see process_tile); a lane's two nodes add their force
+    // and torque before the wave's sums
+    for (int j = 0; j < nb; ++j) {
+      int e;
+      BodySnap sj;
+      if (!body(j, e, sj)) continue;
+      const float ry = (float)min_image(ynode - sj.y, dny);
+      float fx = 0.f, fy = 0.f, tq = 0.f;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float rx = (float)min_image((double)(xc + k) + 0.5 - sj.x, dnx);
+        const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+        if (own[k] && l >= lcut) {
+          const float wgt = phi_of(l, phik);
+          S[k] += wgt;
+          const float ux_s = sj.u - sj.w * ry;
+          const float uy_s = sj.v + sj.w * rx;
+          Phi[k] += wgt;
+          Ax[k] += wgt * ux_s;
+          Ay[k] += wgt * uy_s;
+          Mxx[k] += wgt * ux_s * ux_s;
+          Mxy[k] += wgt * ux_s * uy_s;
+          Myy[k] += wgt * uy_s * uy_s;
+          const float gx = -kap * wgt * rho[k] * (ux_s - usx[k]);
+          const float gy = -kap * wgt * rho[k] * (uy_s - usy[k]);
+          fx += gx;
+          fy += gy;
+          tq += rx * gy - ry * gx;
+        }
+      }
+      if (__ballot(fx != 0.f || fy != 0.f) != 0) reduce3(e, fx, fy, tq);
+    }
+    float scale[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      scale[k] = S[k] > 1.0f ? 1.0f / S[k] : 1.0f;
+      Phi[k] *= scale[k];
+      Ax[k] *= scale[k];
+      Ay[k] *= scale[k];
+      Mxx[k] *= scale[k];
+      Mxy[k] *= scale[k];
+      Myy[k] *= scale[k];
+    }
+    if (__ballot((own[0] && S[0] > 1.0f) || (own[1] && S[1] > 1.0f)) != 0) {
+      for (int j = 0; j < nb; ++j) {
+        int e;
+        BodySnap sj;
+        if (!body(j, e, sj)) continue;
+        const float ry = (float)min_image(ynode - sj.y, dny);
+        float fx = 0.f, fy = 0.f, tq = 0.f;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const float c = scale[k] - 1.0f;  // 0 where S <= 1
+          const float rx = (float)min_image((double)(xc + k) + 0.5 - sj.x, dnx);
+          const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry);
+          if (own[k] && c != 0.0f && l >= lcut) {
+            const float wgt = phi_of(l, phik);
+            const float ux_s = sj.u - sj.w * ry;
+            const float uy_s = sj.v + sj.w * rx;
+            const float gx = c * (-kap * wgt * rho[k] * (ux_s - usx[k]));
+            const float gy = c * (-kap * wgt * rho[k] * (uy_s - usy[k]));
+            fx += gx;
+            fy += gy;
+            tq += rx * gy - ry * gx;
+          }
+        }
+        if (__ballot(fx != 0.f || fy != 0.f) != 0) reduce3(e, fx, fy, tq);
+      }
+    }
+    if (wy || wx) {
+      float fx = 0.f, fy = 0.f;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (own[k] && wy && lwy >= lcut) {
+          const float wgt = scale[k] * phi_of(lwy, phik);
+          Phi[k] += wgt;
+          fx += kap * wgt * rho[k] * usx[k];
+          fy += kap * wgt * rho[k] * usy[k];
+        }
+        if (own[k] && wx && lwx[k] >= lcut) {
+          const float wgt = scale[k] * phi_of(lwx[k], phik);
+          Phi[k] += wgt;
+          fx += kap * wgt * rho[k] * usx[k];
+          fy += kap * wgt * rho[k] * usy[k];
+        }
+      }
+      if (__ballot(fx != 0.f || fy != 0.f) != 0) {
+        const double sx = wave_sum((double)fx);
+        const double sy = wave_sum((double)fy);
+        if (lane == 0) {
+          unsafeAtomicAdd(&acc[3 * nbs], sx);
+          unsafeAtomicAdd(&acc[3 * nbs + 1], sy);
+        }
+      }
+    }
+  }
+
+  // ---- Eq. (17), collision Eq. (13), open ends, checks, per node ----------------------
+  const bool any_bnd = OPEN && d.xbc && __ballot(bnd[0] || bnd[1]) != 0;
+  const FrameShift fs{0.0f, 0.0f, 0.0f, 0.0f};
+  float out[2][kQ];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float Px = rho[k] * (Ax[k] - Phi[k] * usx[k]);
+    const float Py = rho[k] * (Ay[k] - Phi[k] * usy[k]);
+    const float Mx = fmaf(18.0f, Px, Jgx[k]);
+    const float My = fmaf(18.0f, Py, Jgy[k]);
+    NodeState n;
+    n.drho = drho[k];
+    n.rho = rho[k];
+    n.ux = Mx * Rinv[k];
+    n.uy = My * Rinv[k];
+    n.momx = div36(Mx);
+    n.momy = div36(My);
+    n.Px = Px;
+    n.Py = Py;
+    n.Qxx = rho[k] * (Mxx[k] - Phi[k] * usx[k] * usx[k]);
+    n.Qxy = rho[k] * (Mxy[k] - Phi[k] * usx[k] * usy[k]);
+    n.Qyy = rho[k] * (Myy[k] - Phi[k] * usy[k] * usy[k]);
+    if (any_solid)
+      collide_node<true>(f[k], out[k], n, d.Gx, d.Gy, d.omega, d.khalf);
+    else
+      collide_node<false>(f[k], out[k], n, d.Gx, d.Gy, d.omega, d.khalf);
+    float rho_r = rho[k], uxr = n.ux, uyr = n.uy;
+    if constexpr (OPEN) {
+      if (any_bnd && bnd[k])
+        nee_node<ST>(d, (const _Float16 *)src, plane, xc + k, y, fs, 0.0f, 0.0f, out[k], rho_r,
+                     uxr, uyr);
+    }
+    const float usq = uxr * uxr + uyr * uyr;
+    bad = bad || !(rho_r > 0.0f && usq <= 0.25f);
+  }
+  if (__ballot(valid && bad) != 0 && lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
+
+  // ---- stochastic FP16 write-back, both nodes' halves in one 4-byte store per plane ---
+  const float sc = d.store_scale;
+  const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
+  uint32_t hw[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) hw[i] = 0u;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    // the same random words per node as process_tile
+    uint32_t hh[5];
+    hh[0] = lowbias32(((uint32_t)y * (uint32_t)nx + (uint32_t)(xc + k)) ^ tk);
+#pragma unroll
+    for (int r = 1; r < 5; ++r) hh[r] = xorshift32(hh[r - 1]);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      hw[i] |= (uint32_t)ST::round_bits(out[k][i], sc, hh[i >> 1], i & 1) << (16 * k);
+  }
+  if (valid) {
+    if (AM == kAddrBuf) {
+      const uint32_t pb = (uint32_t)plane * 2u;
+      const __amdgpu_buffer_rsrc_t rd =
+          __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
+      const uint32_t s0 = (uint32_t)(y * nx) * 2u;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(hw[i], rd, 2u * (uint32_t)xc, i * pb + s0, 0);
+    } else {
+      const int64_t o = (int64_t)y * nx + xc;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) *(uint32_t *)(dst + i * plane + o) = hw[i];
+    }
+  }
+}
+
+// register budget (waves per SIMD) of a collide instance: two nodes per lane hold twice
+// the per-node state
+template <class ST, int TX, int TY>
+constexpr int collide_waves() {
+  return TX * TY > kBlockThreads ? DILBM_COLLIDE_WAVES_X2 : ST::kWaves;
+}
+
 template <class ST, int TX, int TY, int AM, bool OPEN>
-__global__ __launch_bounds__(kBlockThreads, ST::kWaves) void k_collide(
+__global__ __launch_bounds__(kBlockThreads, (collide_waves<ST, TX, TY>())) void k_collide(
     const SolveDesc *__restrict__ descs, const int32_t *__restrict__ tile_solve,
     const BatchHeader *__restrict__ hdr, int k) {
   __shared__ float red[kBlockThreads / 64][3][64];  // per wave: its lanes' force and torque
@@ -795,8 +1182,11 @@ __global__ __launch_bounds__(kBlockThreads, ST::kWaves) void k_collide(
     if (k >= d.active_steps) return;
     const int p = (d.parity0 + k) & 1;
     const int lt = (int)(t - d.tile_base);
-    process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, red, nullptr,
-                                                  nullptr, nullptr, Region{0, 0, 0, 0});
+    if constexpr (TX * TY == 2 * kBlockThreads)
+      process_tile_x2<AM, OPEN>(d, lt, p, d.step0 + k, red);
+    else
+      process_tile<ST, TX, TY, kModeStep, AM, OPEN>(d, lt, p, d.step0 + k, red, nullptr,
+                                                    nullptr, nullptr, Region{0, 0, 0, 0}, 0);
   };
   if (hdr->natural) {
     // tile b to block b: consecutive tiles (neighbouring row segments) run on the eight
@@ -826,8 +1216,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_fields(const SolveDesc *__res
   const int64_t n = (int64_t)ntx * (ty1 - ty0 + 1);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
     const int lt = (int)((ty0 + e / ntx) * d.tiles_x + tx0 + e % ntx);
-    process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, nullptr, rho, ux,
-                                                           uy, region);
+    // a 512-node tile (one row, two nodes per lane in the step kernel) in two halves
+    for (int xoff = 0; xoff < TX * TY; xoff += kBlockThreads)
+      process_tile<ST, TX, TY, kModeFields, kAddrWide, true>(d, lt, p, d.step0, nullptr, rho,
+                                                             ux, uy, region, xoff);
   }
 }
 
@@ -994,15 +1386,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       // axis by the distance to the rectangle's middle less half its extent (the periodic
       // distance is 1-Lipschitz), so no reached wave is left out
       uint32_t mask = 0;
+      const int npw = d.tx * d.ty / 4;  // nodes per wave: 64, or 128 with two per lane
       for (int w = 0; w < 4; ++w) {
         int xa, xb, ya, yb;
-        if (d.tx >= 64) {
-          ya = yb = ty * d.ty + (64 * w) / d.tx;
-          xa = tx * d.tx + (64 * w) % d.tx;
-          xb = xa + 63;
+        if (d.tx >= npw) {
+          ya = yb = ty * d.ty + (npw * w) / d.tx;
+          xa = tx * d.tx + (npw * w) % d.tx;
+          xb = xa + npw - 1;
         } else {
-          ya = ty * d.ty + w * (64 / d.tx);
-          yb = ya + 64 / d.tx - 1;
+          ya = ty * d.ty + w * (npw / d.tx);
+          yb = ya + npw / d.tx - 1;
           xa = tx * d.tx;
           xb = xa + d.tx - 1;
         }
@@ -1137,6 +1530,11 @@ static CollideKernel collide_kernel(int shape, int storage, int addr, bool open)
     }
   switch (shape) {
     DILBM_SHAPES(DILBM_CASE)
+    case 5:  // 512 x 1, two nodes per lane: FP16 populations only
+      if (storage == 1) {
+        DILBM_PICK(StoreF16, 512, 1)
+      }
+      return nullptr;
     default:
       return nullptr;
   }
@@ -1178,6 +1576,11 @@ hipError_t launch_fields(int shape, int storage, int64_t ntiles, hipStream_t str
     break;
   switch (shape) {
     DILBM_SHAPES(DILBM_CASE)
+    case 5:
+      if (storage != 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_fields<StoreF16, 512, 1>), dim3(grid), dim3(kBlockThreads), 0,
+                         stream, desc, p, region, rho, ux, uy);
+      break;
     default:
       return hipErrorInvalidValue;
   }

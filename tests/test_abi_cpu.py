@@ -85,8 +85,18 @@ def test_footprint_counts_populations_and_bodies():
 
 def test_tile_shapes_cover_256_nodes():
     shapes = dilbm.tile_shapes()
-    assert len(shapes) >= 3
-    assert all(tx * ty == 256 for tx, ty in shapes)
+    assert len(shapes) == 6
+    assert all(tx * ty == 256 for tx, ty in shapes[:5])
+    assert shapes[5] == (512, 1)  # two nodes per lane
+
+
+def test_pair_tile_shape_needs_fp16_and_even_width():
+    bad = [dict(nx=1024, ny=8, tile=5), dict(nx=1023, ny=8, tile=5, storage=dilbm.STORE_FP16)]
+    for kw in bad:
+        with pytest.raises(dilbm.DilbmError) as e:
+            dilbm.footprint(dilbm.Params(**kw), 0)
+        assert e.value.status == dilbm.EINVAL
+    assert dilbm.footprint(dilbm.Params(nx=1024, ny=8, tile=5, storage=dilbm.STORE_FP16), 0) > 0
 
 
 def test_one_hip_runtime_per_process():
