@@ -79,6 +79,15 @@ constexpr int32_t kListIndexMask = (1 << kListIndexBits) - 1;
 
 enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
 
+// Neighbour lists of the Eq. (28) pair search.  Each body keeps the partners that were
+// within r_i + r_j + xi + kNbrSkin of it when the lists were last built; while no body of
+// the solve has moved more than kNbrSkin / 2 since then, every pair within reach is on
+// them.  A body that has moved that far raises the solve's rebuild flag, and at the next
+// step every body rebuilds its list by the full sweep.  A list that would pass
+// kNbrCap entries is marked -1: that body sweeps every step until the next rebuild.
+constexpr int kNbrCap = 64;
+constexpr double kNbrSkin = 2.0;
+
 // One body as the collide kernel sees it at a step: position (FP64, so that node - centre
 // differences keep FP64 accuracy before they are rounded), rigid velocity, spin and radius.
 struct BodySnap {
@@ -136,6 +145,14 @@ struct SolveDesc {
   float *bxy[2];               // per body (x, y) in FP32, interleaved: coarse pair search
   double *acc[2];
   int32_t *err;
+  // neighbour lists of the pair search: count per body (-1: sweep every step), kNbrCap
+  // partner indices per body, the position each body had when its list was built, and the
+  // rebuild flags (by step parity: a step reads flag[p], raises flag[p ^ 1]; the collide
+  // kernel of the next step clears flag[p])
+  int32_t *nbr_cnt;
+  int32_t *nbr_list;
+  double *nbr_ref;
+  int32_t *nl_flag;
 };
 
 // A rectangle of nodes [x, x + w) x [y, y + h) inside one solve.

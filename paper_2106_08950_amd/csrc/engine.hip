@@ -218,7 +218,8 @@ void validate_bodies(int32_t n, const double *pos, const double *vel, const doub
 
 struct BodyLayout {
   int cap = 1;
-  uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, bxy = 0, acc = 0, total = 0;
+  uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, bxy = 0, acc = 0;
+  uint64_t nbr_cnt = 0, nbr_list = 0, nbr_ref = 0, nl_flag = 0, total = 0;
 };
 
 BodyLayout body_layout(const dilbm_params &p, int nb) {
@@ -240,6 +241,14 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   o += align_up(2 * 2 * (uint64_t)std::max(nb, 1) * 4);
   L.acc = o;
   o += align_up(2 * 3 * (uint64_t)(nb + 1) * 8);
+  L.nbr_cnt = o;
+  o += align_up(4 * (uint64_t)std::max(nb, 1));
+  L.nbr_list = o;
+  o += align_up(4 * (uint64_t)kNbrCap * std::max(nb, 1));
+  L.nbr_ref = o;
+  o += align_up(2 * 8 * (uint64_t)std::max(nb, 1));
+  L.nl_flag = o;
+  o += align_up(2 * 4);
   L.total = o;
   return L;
 }
@@ -362,6 +371,10 @@ void fill_desc(Solve &s) {
   d.bxy[1] = d.bxy[0] + 2 * nbs;
   d.acc[0] = (double *)(bb + s.L.acc);
   d.acc[1] = d.acc[0] + 3 * (uint64_t)(s.nb + 1);
+  d.nbr_cnt = (int32_t *)(bb + s.L.nbr_cnt);
+  d.nbr_list = (int32_t *)(bb + s.L.nbr_list);
+  d.nbr_ref = (double *)(bb + s.L.nbr_ref);
+  d.nl_flag = (int32_t *)(bb + s.L.nl_flag);
 }
 
 // ---------------------------------------------------------------------------------------

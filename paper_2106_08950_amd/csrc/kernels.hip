@@ -474,6 +474,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
       for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+      if (tid == 0) d.nl_flag[p ^ 1] = 0;  // read by the last body step, raised by the next
     }
   }
 
@@ -893,6 +894,7 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
   if (lt == 0) {
     double *a = d.acc[p ^ 1];
     for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+    if (tid == 0) d.nl_flag[p ^ 1] = 0;  // read by the last body step, raised by the next
   }
 
   float f[2][kQ];
@@ -1254,55 +1256,95 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     const double m = d.bconst[2 * nb + b], I = d.bconst[3 * nb + b];
     const bool fixed = d.bconst[4 * nb + b] != 0.0;
     int q = p;
+    if (BIN_ONLY && b == 0 && lane == 0) d.nl_flag[p] = 1;  // new bodies: build the lists
     if (!BIN_ONLY) {
       // hydrodynamic force and torque of the step (read now: in flight with the pair loads)
       const double *acc = d.acc[p];
       const double hfx = acc[3 * b], hfy = acc[3 * b + 1], T = acc[3 * b + 2];
       // Eq. (28): repulsion from every other body of the solve (minimum image); pairs
-      // farther apart than r_i + r_j + xi are rejected on the squared distance.  The
-      // other bodies are first screened on their FP32 positions (8 bytes each, kU rounds
-      // of 64 in flight together) against the reach r_i + max r_j + xi plus a margin far
-      // above the FP32 rounding of a position; only partners inside it are read and
-      // tested in FP64, in the same order as a full FP64 sweep, so the sums are the same.
+      // farther apart than r_i + r_j + xi are rejected on the squared distance.  Partners
+      // come from the body's neighbour list (see kNbrCap); when the lists are rebuilt, or
+      // this body's overflowed, every other body is swept: first screened on its FP32
+      // position (8 bytes each, kU rounds of 64 in flight together) against
+      // r_i + max r_j + xi + skin plus a margin far above the FP32 rounding of a position,
+      // then tested in FP64, and kept on the list when within r_i + r_j + xi + skin.
       double fx = 0.0, fy = 0.0;
       const double xi = d.xi;
-      const float *__restrict__ bxy = d.bxy[p];
-      const float X32 = (float)X, Y32 = (float)Y;
-      const float fnx = (float)d.nx, fny = (float)d.ny;
-      const float reach = (float)(R + d.rmax + xi) + 0.0625f;
-      constexpr int kU = 16;
-      for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
-        float2 q32[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int j = min(j0 + 64 * u + lane, nb - 1);  // clamped: a valid index
-          q32[u] = *(const float2 *)(bxy + 2 * (int64_t)j);
+      auto pair = [&](const int j, double &dx, double &dy) -> double {  // d^2, or -1
+        dx = min_image(X - st[j], dnx);
+        dy = min_image(Y - st[nb + j], dny);
+        return dx * dx + dy * dy;
+      };
+      auto add_force = [&](const int j, const double dx, const double dy, const double d2) {
+        const double rr = R + d.bconst[j];
+        if (d2 > (rr + xi) * (rr + xi)) return;
+        const double dist = sqrt(d2);
+        const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
+                                     : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
+        fx += kk * dx;
+        fy += kk * dy;
+      };
+      int32_t *__restrict__ my_list = d.nbr_list + (int64_t)b * kNbrCap;
+      const int cnt0 = d.nbr_cnt[b];
+      const bool sweep = d.nl_flag[p] != 0 || cnt0 < 0;
+      if (!sweep) {
+        // the list: one partner per lane
+        if (lane < cnt0) {
+          const int j = my_list[lane];
+          double dx, dy;
+          const double d2 = pair(j, dx, dy);
+          add_force(j, dx, dy, d2);
         }
-        uint32_t near = 0;  // rounds whose partner is within reach
+      } else {
+        const bool rebuild = d.nl_flag[p] != 0;
+        const float *__restrict__ bxy = d.bxy[p];
+        const float X32 = (float)X, Y32 = (float)Y;
+        const float fnx = (float)d.nx, fny = (float)d.ny;
+        const float reach = (float)(R + d.rmax + xi + kNbrSkin) + 0.0625f;
+        int cnt = 0;  // list entries kept (wave-uniform)
+        constexpr int kU = 16;
+        for (int j0 = 0; j0 < nb; j0 += 64 * kU) {
+          float2 q32[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          float dx = X32 - q32[u].x, dy = Y32 - q32[u].y;
-          if (dx >= 0.5f * fnx) dx -= fnx;
-          if (dx < -0.5f * fnx) dx += fnx;
-          if (dy >= 0.5f * fny) dy -= fny;
-          if (dy < -0.5f * fny) dy += fny;
-          if (dx * dx + dy * dy <= reach * reach) near |= 1u << u;
+          for (int u = 0; u < kU; ++u) {
+            const int j = min(j0 + 64 * u + lane, nb - 1);  // clamped: a valid index
+            q32[u] = *(const float2 *)(bxy + 2 * (int64_t)j);
+          }
+          uint32_t near = 0;  // rounds whose partner is within reach
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            float dx = X32 - q32[u].x, dy = Y32 - q32[u].y;
+            if (dx >= 0.5f * fnx) dx -= fnx;
+            if (dx < -0.5f * fnx) dx += fnx;
+            if (dy >= 0.5f * fny) dy -= fny;
+            if (dy < -0.5f * fny) dy += fny;
+            if (dx * dx + dy * dy <= reach * reach) near |= 1u << u;
+          }
+          // rounds in order for every lane, so the list is appended wave by wave
+          for (int u = 0; u < kU && j0 + 64 * u < nb; ++u) {
+            const int j = j0 + 64 * u + lane;
+            bool keep = false;
+            if (((near >> u) & 1u) && j < nb && j != b) {
+              double dx, dy;
+              const double d2 = pair(j, dx, dy);
+              const double rs = R + d.bconst[j] + xi + kNbrSkin;
+              keep = d2 <= rs * rs;
+              add_force(j, dx, dy, d2);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (rebuild && bal != 0) {
+              const int slot = cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                         (uint32_t)(bal >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+              if (keep && slot < kNbrCap) my_list[slot] = j;
+              cnt += __builtin_popcountll(bal);
+            }
+          }
         }
-        while (near) {
-          const int u = __builtin_ctz(near);
-          near &= near - 1;
-          const int j = j0 + 64 * u + lane;
-          if (j >= nb || j == b) continue;
-          const double dx = min_image(X - st[j], dnx);
-          const double dy = min_image(Y - st[nb + j], dny);
-          const double d2 = dx * dx + dy * dy;
-          const double rr = R + d.bconst[j];
-          if (d2 > (rr + xi) * (rr + xi)) continue;
-          const double dist = sqrt(d2);
-          const double kk = dist <= rr ? (rr - dist) * d.inv_eps_p1
-                                       : (rr + xi - dist) * (rr + xi - dist) * d.inv_eps_p;
-          fx += kk * dx;
-          fy += kk * dy;
+        if (rebuild && lane == 0) {
+          d.nbr_cnt[b] = cnt <= kNbrCap ? cnt : -1;
+          d.nbr_ref[2 * b] = X;
+          d.nbr_ref[2 * b + 1] = Y;
         }
       }
       fx = wave_sum(fx);  // every lane now holds the totals
@@ -1348,6 +1390,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       Y = Y - dny * floor(Y / dny);
       if (X >= dnx) X -= dnx;
       if (Y >= dny) Y -= dny;
+      // moved more than half the skin since the lists were built: rebuild them next step
+      {
+        const double mx = min_image(X - d.nbr_ref[2 * b], dnx);
+        const double my = min_image(Y - d.nbr_ref[2 * b + 1], dny);
+        if (lane == 0 && !(mx * mx + my * my <= 0.25 * kNbrSkin * kNbrSkin)) d.nl_flag[p ^ 1] = 1;
+      }
       q = p ^ 1;
       if (lane == 0) {
         double *sn = d.bstate[q];
