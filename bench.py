@@ -1,7 +1,7 @@
 """Benchmark of the DI-LBM time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs fp32,fp16,open_ends,suspension3d,batched,served]
+                    [--legs fp32,fp16,open_ends,suspension3d,suspension3d_q27,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -12,14 +12,17 @@ HBM before the timed region starts.
 
 How each single-solve leg is measured:
 1. set-up (create, bodies) on the host;
-2. a settle phase: device copies of the population volume back to back on the solve's
-   stream for about 0.4 s.  After an idle spell the first ~50 steps (about 10 ms of
-   streaming) run up to 15% slower while the chip's clocks settle; the copies take that
-   transient and give the copy bandwidth, the roofline's second denominator;
-3. W warm-up steps, then five timed runs of exactly K steps each (production path: HIP
+2. the copy bandwidth, the roofline's second denominator: device copies of the population
+   volume back to back on the solve's stream;
+3. a settle phase: untimed steps of the same solve for about 0.3 s.  After an idle spell
+   the first ~60 steps (10-15 ms of streaming) run up to 10% slower while the chip's
+   clocks settle (kernel traces show it; back-to-back copies before the steps shorten
+   the transient but do not remove it), so a short timed region right after set-up would
+   measure the transient rather than the step;
+4. W warm-up steps, then five timed runs of exactly K steps each (production path: HIP
    graph chunks), each bracketed by device synchronisations; `value` and `ms_per_step`
    come from the median run, and all five are reported;
-4. a separate pass of max(K, 200) steps with HIP events around every collide launch on
+5. a separate pass of max(K, 200) steps with HIP events around every collide launch on
    the solve's stream (direct launches): the roofline's per-launch average, with the
    minimum and the median.
 
@@ -29,6 +32,7 @@ Further legs, reported in the same JSON line:
   fixed discs), FP32;
 * suspension3d: the three-dimensional path, 256^3 D3Q19 nodes with 400 free spheres
   (seed 8), FP32 (152 B per node update);
+* suspension3d_q27: the same on the D3Q27 lattice (216 B per node update);
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -58,6 +62,8 @@ KERNEL3_FILES = [os.path.join(CSRC, f) for f in
 COUNTERS = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp32_hbm_counters.txt")
 COUNTERS16 = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp16_hbm_counters.txt")
 COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm_counters.txt")
+COUNTERS3_27 = os.path.join(ROOT, "profiles",
+                            "k3_collide_suspension3d_256_d3q27_fp32_hbm_counters.txt")
 TIMED_RUNS = 5
 
 
@@ -107,10 +113,10 @@ def copy_calibration():
     print("copied 3 x 1 GiB (read 1 GiB + write 1 GiB per copy)", flush=True)
 
 
-def settle(stream, nbytes, seconds=0.4):
+def copy_bandwidth(stream, nbytes, seconds=0.2):
     """Back-to-back device copies of nbytes on `stream` for about `seconds`, with no host
-    wait between them, ending right before the caller's steps are enqueued.  Returns the
-    copy bandwidth (GB/s, nbytes read + nbytes written per copy) over the second half."""
+    wait between them.  Returns the copy bandwidth (GB/s, nbytes read + nbytes written
+    per copy) over the second half."""
     import torch
 
     n = max(nbytes // 4, 1)
@@ -137,6 +143,18 @@ def settle(stream, nbytes, seconds=0.4):
         gbs = 2 * n * 4 * (reps - reps // 2) / (a.elapsed_time(b) * 1e-3) / 1e9
         del x, y
     return gbs
+
+
+def settle_steps(step, seconds=0.3):
+    """Untimed steps of the solve for about `seconds` (see the module docstring)."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(16)
+    torch.cuda.synchronize()
+    per = max((time.perf_counter() - t0) / 16, 1e-6)
+    step(max(16, int(seconds / per)))
 
 
 def timed_runs(step, steps):
@@ -187,7 +205,8 @@ def single_solve(wl, storage, steps, warmup, tile, stream, bytes_per_node, traff
                                      stream=stream.cuda_stream)
     s = dilbm.Solver(prm)
     s.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
-    copy_gbs = settle(stream, 9 * wl.nodes * (4 if storage == dilbm.STORE_FP32 else 2))
+    copy_gbs = copy_bandwidth(stream, 9 * wl.nodes * (4 if storage == dilbm.STORE_FP32 else 2))
+    settle_steps(s.step)
     s.step(warmup)
     runs = timed_runs(s.step, steps)
     ms = launch_pass(s, max(steps, 200))
@@ -199,24 +218,28 @@ def single_solve(wl, storage, steps, warmup, tile, stream, bytes_per_node, traff
             "roofline": roofline(bytes_per_node, wl.nodes, ms, traffic, "k_collide", copy_gbs)}
 
 
-def suspension3d_leg(steps, warmup, stream):
-    """The three-dimensional path: 256^3 periodic D3Q19 nodes with 400 free spheres, FP32
-    (19 x 4 bytes read + 19 x 4 written = 152 B per node update)."""
+def suspension3d_leg(steps, warmup, stream, q=19):
+    """The three-dimensional path: 256^3 periodic nodes with 400 free spheres, FP32, on
+    D3Q19 (19 x 4 bytes read + 19 x 4 written = 152 B per node update) or D3Q27 (216 B)."""
     from paper_2106_08950_amd import dilbm3d, inputs3d
 
     w3 = inputs3d.suspension3d()
-    s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w3, device=0, stream=stream.cuda_stream))
+    s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w3, device=0, stream=stream.cuda_stream,
+                                                      lattice=q))
     s.set_particles(w3.pos, w3.radius, w3.density, w3.vel, w3.omega, w3.fixed)
-    copy_gbs = settle(stream, 19 * 4 * w3.nodes)
+    copy_gbs = copy_bandwidth(stream, q * 4 * w3.nodes)
+    settle_steps(s.step)
     s.step(warmup)
     runs = timed_runs(s.step, steps)
     ms = launch_pass(s, max(steps, 100))
     s.close()
     dt = statistics.median(runs)
-    return {"workload": w3.name, "value": round(w3.nodes * steps / dt / 1e6, 1),
+    counters = COUNTERS3 if q == 19 else COUNTERS3_27
+    return {"workload": w3.name, "lattice": f"D3Q{q}",
+            "value": round(w3.nodes * steps / dt / 1e6, 1),
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
             "runs_ms_per_step": [round(r * 1e3 / steps, 4) for r in runs],
-            "roofline": roofline(152, w3.nodes, ms, measured_traffic(COUNTERS3, KERNEL3_FILES),
+            "roofline": roofline(8 * q, w3.nodes, ms, measured_traffic(counters, KERNEL3_FILES),
                                  "k3_collide", copy_gbs)}
 
 
@@ -374,7 +397,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,batched,served")
+    ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,suspension3d_q27,"
+                                      "batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--served-count", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -433,6 +457,10 @@ def main():
     if "suspension3d" in legs:
         log("suspension3d")
         out["suspension3d"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup, stream)
+    if "suspension3d_q27" in legs:
+        log("suspension3d D3Q27")
+        out["suspension3d_q27"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup,
+                                                   stream, q=27)
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

@@ -1,6 +1,6 @@
 /*
- * dilbm3d.h -- C ABI of the three-dimensional DI-LBM step in libdilbm.so (D3Q19 lattice,
- * spherical particles), on MI355X (gfx950).
+ * dilbm3d.h -- C ABI of the three-dimensional DI-LBM step in libdilbm.so (D3Q19 or D3Q27
+ * lattice, spherical particles), on MI355X (gfx950).
  *
  * The paper (Liu, Huang, Chai & Shi) states DI-LBM in two dimensions and motivates it by
  * the cost of solid volume fractions in three.  These calls take the same step as
@@ -8,7 +8,7 @@
  *   1. the diffuse solid field phi of Eq. (14) with l = R - |x - X| for a sphere;
  *   2. the collision of Eq. (13) with the corrected velocity of Eq. (17), phi times the
  *      force term of Eq. (15) and the uncorrected velocity of Eq. (16);
- *   3. pull streaming over the D3Q19 velocities and the moments of Eq. (5);
+ *   3. pull streaming over the D3Q19 or D3Q27 velocities and the moments of Eq. (5);
  *   4. the hydrodynamic force and torque of Eqs. (18)-(19) per sphere (torque r x F, a
  *      vector; FP64 accumulation) and the motion of Eqs. (22)-(24) with the repulsion
  *      of Eqs. (28)-(29) (FP64).
@@ -18,9 +18,13 @@
  *   - D3Q19 directions: 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7..18 the edge
  *     directions in opposite pairs: (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1),
  *     (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  Weights
- *     1/3, 1/18, 1/36; c_s^2 = 1/3.
- *   - Field arrays are [nz][ny][nx]; population arrays are [19][nz][ny][nx] and hold
- *     f_i - w_i * rho0 as FP64.  Per-sphere vectors are [n][3] (x, y, z).
+ *     1/3, 1/18, 1/36; c_s^2 = 1/3.  D3Q27 (lattice = 27) keeps these 19 and adds the
+ *     corner directions 19..26 in opposite pairs: (1,1,1), (-1,-1,-1), (1,1,-1),
+ *     (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1), (1,-1,-1); weights 8/27, 2/27, 1/54,
+ *     1/216, c_s^2 = 1/3 (both are the standard three-dimensional counterparts of the
+ *     D2Q9 velocities and weights of Eqs. (3)-(4)).
+ *   - Field arrays are [nz][ny][nx]; population arrays are [q][nz][ny][nx] (q = 19 or
+ *     27) and hold f_i - w_i * rho0 as FP64.  Per-sphere vectors are [n][3] (x, y, z).
  *   - Host pointers; the caller owns every array; status codes and handle poisoning
  *     as in dilbm.h (DILBM_EUNSTABLE and DILBM_ECAPACITY poison the handle).
  *   - Populations are stored on the device in FP32 as f_i - w_i rho0 (structure of
@@ -43,7 +47,7 @@
 extern "C" {
 #endif
 
-#define DILBM3D_ABI_VERSION 1u
+#define DILBM3D_ABI_VERSION 2u
 
 enum { DILBM3D_WALL_Y = 1u, DILBM3D_WALL_X = 2u, DILBM3D_WALL_Z = 4u };
 
@@ -51,7 +55,7 @@ typedef struct dilbm3d_solver dilbm3d_solver;
 
 typedef struct dilbm3d_params {
   uint32_t abi_version;        /* DILBM3D_ABI_VERSION, else DILBM_EABI */
-  int32_t nx, ny, nz;          /* >= 1 each; nx * ny * nz * 19 * 4 bytes per buffer < 4 GB */
+  int32_t nx, ny, nz;          /* >= 1 each; nx * ny * nz * q * 4 bytes per buffer < 4 GB */
   double tau;                  /* BGK relaxation time, > 0.5 */
   double rho0;                 /* rest density, > 0 */
   double interface_width;      /* epsilon of Eq. (14), > 0 */
@@ -63,6 +67,7 @@ typedef struct dilbm3d_params {
   int32_t force_mode;          /* DILBM_FORCE_MOMENTUM_EXCHANGE or DILBM_FORCE_PAPER_LITERAL */
   double coll_eps_p, coll_eps_p_overlap, coll_eps_w, coll_eps_w_overlap, coll_xi; /* (28)-(29) */
   int32_t list_capacity;       /* spheres listed per tile; 0 = min(n, 128); <= 1024 */
+  int32_t lattice;             /* 19 (D3Q19; 0 also means 19) or 27 (D3Q27) */
   int32_t device;              /* HIP device ordinal */
   void *stream;                /* hipStream_t to run on, or NULL for a library-owned one */
 } dilbm3d_params;

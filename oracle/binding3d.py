@@ -32,6 +32,7 @@ class _Params(C.Structure):
         ("force_mode", C.c_int32),
         ("eps_p", C.c_double), ("eps_p1", C.c_double), ("eps_w", C.c_double),
         ("eps_w1", C.c_double), ("xi", C.c_double),
+        ("lattice", C.c_int32),
     ]
 
 
@@ -53,6 +54,12 @@ def _L():
         lib.ora3_collide_node.argtypes = [C.c_double, C.c_double, _dp, C.c_int32, _dp, _dp, _dp,
                                           C.c_int32, _dp, _dp, _dp, _dp, _dp]
         lib.ora3_collide_node.restype = C.c_int32
+        lib.ora3q_lattice.argtypes = [C.c_int32, _ip, _ip, _ip, _dp, _dp]
+        lib.ora3q_feq.argtypes = [C.c_int32, C.c_double, _dp, _dp]
+        lib.ora3q_force_term.argtypes = [C.c_int32, C.c_double, C.c_double, _dp, _dp, _dp]
+        lib.ora3q_guo_term.argtypes = [C.c_int32, C.c_double, _dp, _dp, _dp]
+        lib.ora3q_collide_node.argtypes = [C.c_int32] + lib.ora3_collide_node.argtypes
+        lib.ora3q_collide_node.restype = C.c_int32
         lib.ora3_pp_force.argtypes = [_dp] + [C.c_double] * 5 + [_dp]
         lib.ora3_pw_force.argtypes = [_dp] + [C.c_double] * 4 + [_dp]
         lib.ora3_body_update.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -87,47 +94,48 @@ def _f64(a, shape=None):
     return a.reshape(shape) if shape is not None else a
 
 
-def lattice():
-    cx, cy, cz = (np.zeros(Q, np.int32) for _ in range(3))
-    w = np.zeros(Q)
+def lattice(q=Q):
+    """Velocities and weights of D3Q19 (q = 19) or D3Q27 (q = 27), and c_s^2."""
+    cx, cy, cz = (np.zeros(q, np.int32) for _ in range(3))
+    w = np.zeros(q)
     cs2 = np.zeros(1)
-    _L().ora3_lattice(cx.ctypes.data_as(_ip), cy.ctypes.data_as(_ip), cz.ctypes.data_as(_ip),
-                      _ptr(w), _ptr(cs2))
+    _L().ora3q_lattice(q, cx.ctypes.data_as(_ip), cy.ctypes.data_as(_ip),
+                       cz.ctypes.data_as(_ip), _ptr(w), _ptr(cs2))
     return cx, cy, cz, w, float(cs2[0])
 
 
-def feq(rho, u):
-    out = np.zeros(Q)
-    _L().ora3_feq(rho, _ptr(_f64(u, (3,))), _ptr(out))
+def feq(rho, u, q=Q):
+    out = np.zeros(q)
+    _L().ora3q_feq(q, rho, _ptr(_f64(u, (3,))), _ptr(out))
     return out
 
 
-def force_term(tau, rho, us, ustar):
-    out = np.zeros(Q)
-    _L().ora3_force_term(tau, rho, _ptr(_f64(us, (3,))), _ptr(_f64(ustar, (3,))), _ptr(out))
+def force_term(tau, rho, us, ustar, q=Q):
+    out = np.zeros(q)
+    _L().ora3q_force_term(q, tau, rho, _ptr(_f64(us, (3,))), _ptr(_f64(ustar, (3,))), _ptr(out))
     return out
 
 
-def guo_term(tau, u, G):
-    out = np.zeros(Q)
-    _L().ora3_guo_term(tau, _ptr(_f64(u, (3,))), _ptr(_f64(G, (3,))), _ptr(out))
+def guo_term(tau, u, G, q=Q):
+    out = np.zeros(q)
+    _L().ora3q_guo_term(q, tau, _ptr(_f64(u, (3,))), _ptr(_f64(G, (3,))), _ptr(out))
     return out
 
 
-def collide_node(tau, rho0, f_dev, phis=(), us=(), G=(0.0, 0.0, 0.0), force_mode=0):
+def collide_node(tau, rho0, f_dev, phis=(), us=(), G=(0.0, 0.0, 0.0), force_mode=0, q=Q):
     """One node, no streaming.  Returns (status, fpost_dev, rho, u, ustar, force_b[nb, 3])."""
     nb = len(phis)
     ph = _f64(np.asarray(phis, np.float64).reshape(-1))
     usa = _f64(np.asarray(us, np.float64).reshape(nb, 3)) if nb else None
-    fp = np.zeros(Q)
+    fp = np.zeros(q)
     rho = np.zeros(1)
     u = np.zeros(3)
     ust = np.zeros(3)
     fb = np.zeros(max(nb, 1) * 3)
-    st = _L().ora3_collide_node(tau, rho0, _ptr(_f64(f_dev, (Q,))), nb,
-                                _ptr(ph) if nb else None, _ptr(usa) if nb else None,
-                                _ptr(_f64(G, (3,))), force_mode, _ptr(fp), _ptr(rho), _ptr(u),
-                                _ptr(ust), _ptr(fb))
+    st = _L().ora3q_collide_node(q, tau, rho0, _ptr(_f64(f_dev, (q,))), nb,
+                                 _ptr(ph) if nb else None, _ptr(usa) if nb else None,
+                                 _ptr(_f64(G, (3,))), force_mode, _ptr(fp), _ptr(rho), _ptr(u),
+                                 _ptr(ust), _ptr(fb))
     return int(st), fp, float(rho[0]), u, ust, fb[: 3 * nb].reshape(nb, 3)
 
 
@@ -169,6 +177,7 @@ class Oracle3Params:
     eps_w: float = 0.5e4
     eps_w1: float = 0.5e4
     xi: float = 1.0
+    lattice: int = 19          # 19: D3Q19, 27: D3Q27
 
     def _c(self):
         p = _Params()
@@ -182,6 +191,7 @@ class Oracle3Params:
         p.force_mode = int(self.force_mode)
         p.eps_p, p.eps_p1, p.eps_w, p.eps_w1, p.xi = (self.eps_p, self.eps_p1, self.eps_w,
                                                       self.eps_w1, self.xi)
+        p.lattice = int(self.lattice)
         return p
 
 
@@ -192,7 +202,8 @@ class Oracle3Error(RuntimeError):
 
 
 class Oracle3Solver:
-    """FP64 3-D DI-LBM solver.  Populations: deviations, shape [19, nz, ny, nx]."""
+    """FP64 3-D DI-LBM solver.  Populations: deviations, shape [q, nz, ny, nx], q = 19 or
+    27 (params.lattice)."""
 
     def __init__(self, params: Oracle3Params):
         self.params = params
@@ -243,11 +254,11 @@ class Oracle3Solver:
         self.nb = n
 
     def set_populations(self, f_dev):
-        f_dev = _f64(f_dev, (Q,) + self.shape)
+        f_dev = _f64(f_dev, (self.params.lattice,) + self.shape)
         self._check(_L().ora3_set_populations(self._h, _ptr(f_dev)), "ora3_set_populations")
 
     def get_populations(self):
-        out = np.zeros((Q,) + self.shape)
+        out = np.zeros((self.params.lattice,) + self.shape)
         self._check(_L().ora3_get_populations(self._h, _ptr(out)), "ora3_get_populations")
         return out
 

@@ -1,6 +1,6 @@
 /*
  * dilbm3d_oracle.c -- plain FP64 CPU reference of the three-dimensional DI-LBM time step
- * (D3Q19, spheres).
+ * (D3Q19 or D3Q27, spheres).
  *
  * TEST INFRASTRUCTURE ONLY: the oracle that the GPU library's 3-D path is checked
  * against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg load it.
@@ -35,64 +35,89 @@
 #include <omp.h>
 #endif
 
-#define Q 19
-
-static const int32_t CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-static const int32_t CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-static const int32_t CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+/* The two velocity sets, standard three-dimensional counterparts of Eqs. (3)-(4):
+ * D3Q19 is the rest direction, the six axis directions and the twelve edge directions;
+ * D3Q27 adds the eight corner directions.  Opposite directions are neighbours (i, i + 1)
+ * for odd i, and D3Q27's first 19 directions are those of D3Q19. */
+#define QMAX 27
+static const int32_t CX[QMAX] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                 1, -1, 1, -1, 1, -1, -1, 1};
+static const int32_t CY[QMAX] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                 1, -1, 1, -1, -1, 1, 1, -1};
+static const int32_t CZ[QMAX] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                 1, -1, -1, 1, 1, -1, 1, -1};
 static const double CS2 = 1.0 / 3.0;
 
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_EUNSTABLE = -4 };
 
-static double weight(int i) {
+static int valid_q(int32_t q) { return q == 19 || q == 27; }
+
+/* weights by |c|^2 = 0, 1, 2, 3: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216 */
+static double weight(int32_t q, int i) {
   const int n = abs(CX[i]) + abs(CY[i]) + abs(CZ[i]);
+  if (q == 27) return n == 0 ? 8.0 / 27.0 : (n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
   return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-void ora3_lattice(int32_t *cx, int32_t *cy, int32_t *cz, double *w, double *cs2) {
-  for (int i = 0; i < Q; ++i) {
+void ora3q_lattice(int32_t q, int32_t *cx, int32_t *cy, int32_t *cz, double *w, double *cs2) {
+  for (int i = 0; i < q; ++i) {
     if (cx) cx[i] = CX[i];
     if (cy) cy[i] = CY[i];
     if (cz) cz[i] = CZ[i];
-    if (w) w[i] = weight(i);
+    if (w) w[i] = weight(q, i);
   }
   if (cs2) *cs2 = CS2;
 }
 
 /* Eq. (2): f_i^eq = w_i rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)] */
-void ora3_feq(double rho, const double *u, double *feq) {
+void ora3q_feq(int32_t q, double rho, const double *u, double *feq) {
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < q; ++i) {
     const double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
-    feq[i] = weight(i) * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    feq[i] = weight(q, i) * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
   }
 }
 
 /* Eq. (15): F_i = (1 - 1/(2 tau)) [f_i^eq(rho, u_s) - f_i^eq(rho, u*)] */
-void ora3_force_term(double tau, double rho, const double *us, const double *ustar, double *F) {
-  double a[Q], b[Q];
-  ora3_feq(rho, us, a);
-  ora3_feq(rho, ustar, b);
-  for (int i = 0; i < Q; ++i) F[i] = (1.0 - 1.0 / (2.0 * tau)) * (a[i] - b[i]);
+void ora3q_force_term(int32_t q, double tau, double rho, const double *us, const double *ustar,
+                      double *F) {
+  double a[QMAX], b[QMAX];
+  ora3q_feq(q, rho, us, a);
+  ora3q_feq(q, rho, ustar, b);
+  for (int i = 0; i < q; ++i) F[i] = (1.0 - 1.0 / (2.0 * tau)) * (a[i] - b[i]);
 }
 
 /* Guo-Zheng-Shi forcing of a uniform body force density G */
-void ora3_guo_term(double tau, const double *u, const double *G, double *Gi) {
-  for (int i = 0; i < Q; ++i) {
+void ora3q_guo_term(int32_t q, double tau, const double *u, const double *G, double *Gi) {
+  for (int i = 0; i < q; ++i) {
     const double c[3] = {CX[i], CY[i], CZ[i]};
     const double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
     double s = 0.0;
     for (int a = 0; a < 3; ++a) s += ((c[a] - u[a]) / CS2 + cu * c[a] / (CS2 * CS2)) * G[a];
-    Gi[i] = (1.0 - 1.0 / (2.0 * tau)) * weight(i) * s;
+    Gi[i] = (1.0 - 1.0 / (2.0 * tau)) * weight(q, i) * s;
   }
 }
 
-int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t nb,
-                          const double *phi_b, const double *us, const double *G,
-                          int32_t force_mode, double *fpost_dev, double *rho_out,
-                          double *u_out, double *ustar_out, double *force_b) {
-  double f[Q];
-  for (int i = 0; i < Q; ++i) f[i] = f_dev[i] + weight(i) * rho0;
+/* the D3Q19 forms of the pointwise operators */
+void ora3_lattice(int32_t *cx, int32_t *cy, int32_t *cz, double *w, double *cs2) {
+  ora3q_lattice(19, cx, cy, cz, w, cs2);
+}
+void ora3_feq(double rho, const double *u, double *feq) { ora3q_feq(19, rho, u, feq); }
+void ora3_force_term(double tau, double rho, const double *us, const double *ustar, double *F) {
+  ora3q_force_term(19, tau, rho, us, ustar, F);
+}
+void ora3_guo_term(double tau, const double *u, const double *G, double *Gi) {
+  ora3q_guo_term(19, tau, u, G, Gi);
+}
+
+int32_t ora3q_collide_node(int32_t q, double tau, double rho0, const double *f_dev, int32_t nb,
+                           const double *phi_b, const double *us, const double *G,
+                           int32_t force_mode, double *fpost_dev, double *rho_out,
+                           double *u_out, double *ustar_out, double *force_b) {
+  if (!valid_q(q)) return ORA_EINVAL;
+  const int Q = q;
+  double f[QMAX];
+  for (int i = 0; i < Q; ++i) f[i] = f_dev[i] + weight(q, i) * rho0;
 
   /* Eq. (5) and Eq. (16); u* carries half of the fluid body force */
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -118,13 +143,13 @@ int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t 
   }
 
   /* Eq. (13): f* = f - (f - f^eq(rho, u))/tau + phi F_i + G_i */
-  double feq[Q], Gi[Q], Fb[Q], acc[Q];
-  ora3_feq(rho, u, feq);
-  ora3_guo_term(tau, u, G, Gi);
+  double feq[QMAX], Gi[QMAX], Fb[QMAX], acc[QMAX];
+  ora3q_feq(q, rho, u, feq);
+  ora3q_guo_term(q, tau, u, G, Gi);
   for (int i = 0; i < Q; ++i) acc[i] = 0.0;
   for (int b = 0; b < nb; ++b) {
     const double wb = scale * phi_b[b];
-    ora3_force_term(tau, rho, us + 3 * b, ust, Fb);
+    ora3q_force_term(q, tau, rho, us + 3 * b, ust, Fb);
     for (int i = 0; i < Q; ++i) acc[i] += wb * Fb[i];
     if (force_b) {
       double fb[3];
@@ -147,7 +172,7 @@ int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t 
   int bad = !(rho > 0.0) || !(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 0.25);
   for (int i = 0; i < Q; ++i) {
     const double fp = f[i] - (f[i] - feq[i]) / tau + acc[i] + Gi[i];
-    fpost_dev[i] = fp - weight(i) * rho0;
+    fpost_dev[i] = fp - weight(q, i) * rho0;
     if (!isfinite(fpost_dev[i])) bad = 1;
   }
   if (rho_out) *rho_out = rho;
@@ -156,6 +181,14 @@ int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t 
     if (ustar_out) ustar_out[a] = ust[a];
   }
   return bad ? ORA_EUNSTABLE : ORA_OK;
+}
+
+int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t nb,
+                          const double *phi_b, const double *us, const double *G,
+                          int32_t force_mode, double *fpost_dev, double *rho_out,
+                          double *u_out, double *ustar_out, double *force_b) {
+  return ora3q_collide_node(19, tau, rho0, f_dev, nb, phi_b, us, G, force_mode, fpost_dev,
+                            rho_out, u_out, ustar_out, force_b);
 }
 
 /* Eq. (28) along the centre line d = X_i - X_j (not normalised, as written) */
@@ -204,8 +237,9 @@ void ora3_body_update(double m, double I, const double *F, const double *T, doub
 
 struct ora3_solver {
   ora3_params p;
+  int32_t q;      /* 19 or 27 directions */
   int64_t n;      /* nx*ny*nz */
-  double *f;      /* [19][nz][ny][nx] deviations at t_n */
+  double *f;      /* [q][nz][ny][nx] deviations at t_n */
   double *ftmp;
   int32_t nb;
   double *bx, *bu, *bw; /* [nb][3]: centre, velocity, spin */
@@ -359,6 +393,7 @@ static int valid_params(const ora3_params *p) {
   if (p->wall_mask & ~7u) return 0;
   if (p->wall_mask && !(p->wall_h > 0.0)) return 0;
   if (p->force_mode != 0 && p->force_mode != 1) return 0;
+  if (p->lattice != 0 && !valid_q(p->lattice)) return 0;
   return 1;
 }
 
@@ -369,9 +404,10 @@ int32_t ora3_create(const ora3_params *p, ora3_solver **out) {
   ora3_solver *s = (ora3_solver *)calloc(1, sizeof(ora3_solver));
   if (!s) return ORA_ENOMEM;
   s->p = *p;
+  s->q = p->lattice ? p->lattice : 19;
   s->n = (int64_t)p->nx * p->ny * p->nz;
-  s->f = (double *)calloc((size_t)(Q * s->n), sizeof(double));
-  s->ftmp = (double *)calloc((size_t)(Q * s->n), sizeof(double));
+  s->f = (double *)calloc((size_t)(s->q * s->n), sizeof(double));
+  s->ftmp = (double *)calloc((size_t)(s->q * s->n), sizeof(double));
   s->off = (int64_t *)calloc((size_t)(s->n + 1), sizeof(int64_t));
   if (!s->f || !s->ftmp || !s->off) {
     ora3_destroy(s);
@@ -451,13 +487,13 @@ int32_t ora3_set_particles(ora3_solver *s, int32_t n, const double *pos, const d
 
 int32_t ora3_set_populations(ora3_solver *s, const double *f_dev) {
   if (!s || !f_dev) return ORA_EINVAL;
-  memcpy(s->f, f_dev, (size_t)(Q * s->n) * sizeof(double));
+  memcpy(s->f, f_dev, (size_t)(s->q * s->n) * sizeof(double));
   return ORA_OK;
 }
 
 int32_t ora3_get_populations(const ora3_solver *s, double *f_dev) {
   if (!s || !f_dev) return ORA_EINVAL;
-  memcpy(f_dev, s->f, (size_t)(Q * s->n) * sizeof(double));
+  memcpy(f_dev, s->f, (size_t)(s->q * s->n) * sizeof(double));
   return ORA_OK;
 }
 
@@ -474,14 +510,15 @@ static int node_pass(ora3_solver *s, double *fout, double *rho_o, double *ux_o, 
     for (int32_t j = 0; j < ny; ++j) {
       for (int32_t i = 0; i < nx; ++i) {
         const int64_t node = ((int64_t)k * ny + j) * nx + i;
-        double fd[Q], fp[Q], rho, u[3];
+        const int Q = s->q;
+        double fd[QMAX], fp[QMAX], rho, u[3];
         for (int q = 0; q < Q; ++q) fd[q] = s->f[q * n + node];
         const int64_t e0 = s->off[node];
         const int32_t nb = (int32_t)(s->off[node + 1] - e0);
         const int st =
-            ora3_collide_node(p->tau, p->rho0, fd, nb, nb ? s->e_phi + e0 : NULL,
-                              nb ? s->e_us + 3 * e0 : NULL, p->G, p->force_mode, fp, &rho, u,
-                              NULL, nb ? s->e_F + 3 * e0 : NULL);
+            ora3q_collide_node(Q, p->tau, p->rho0, fd, nb, nb ? s->e_phi + e0 : NULL,
+                               nb ? s->e_us + 3 * e0 : NULL, p->G, p->force_mode, fp, &rho, u,
+                               NULL, nb ? s->e_F + 3 * e0 : NULL);
         if (st != ORA_OK) bad = 1;
         if (rho_o) rho_o[node] = rho;
         if (ux_o) ux_o[node] = u[0];

@@ -1,6 +1,6 @@
 /*
  * dilbm3d_oracle.h -- interface of the FP64 CPU reference of the three-dimensional DI-LBM
- * time step (D3Q19 lattice, spherical particles).
+ * time step (D3Q19 or D3Q27 lattice, spherical particles).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is the oracle that the GPU library's 3-D path
  * is checked against.  Only the test suite, the smoke check and the CPU-baseline leg of
@@ -41,11 +41,22 @@ typedef struct ora3_params {
   double wall_h;           /* half thickness of a wall slab */
   int32_t force_mode;      /* 0: momentum-exchange scale; 1: Eq. (18) taken literally */
   double eps_p, eps_p1, eps_w, eps_w1, xi;   /* Eqs. (28)-(29) */
+  int32_t lattice;         /* 19 (D3Q19, also 0) or 27 (D3Q27) */
 } ora3_params;
 
 typedef struct ora3_solver ora3_solver;
 
-/* lattice and pointwise operators */
+/* lattice and pointwise operators: the ora3q_ forms take the velocity set (19 or 27),
+ * the ora3_ forms are D3Q19 */
+void   ora3q_lattice(int32_t q, int32_t *cx, int32_t *cy, int32_t *cz, double *w, double *cs2);
+void   ora3q_feq(int32_t q, double rho, const double *u, double *feq);
+void   ora3q_force_term(int32_t q, double tau, double rho, const double *us, const double *ustar,
+                        double *F);
+void   ora3q_guo_term(int32_t q, double tau, const double *u, const double *G, double *Gi);
+int32_t ora3q_collide_node(int32_t q, double tau, double rho0, const double *f_dev, int32_t nb,
+                           const double *phi_b, const double *us, const double *G,
+                           int32_t force_mode, double *fpost_dev, double *rho_out,
+                           double *u_out, double *ustar_out, double *force_b);
 void   ora3_lattice(int32_t *cx, int32_t *cy, int32_t *cz, double *w, double *cs2);
 void   ora3_feq(double rho, const double *u, double *feq);
 void   ora3_force_term(double tau, double rho, const double *us, const double *ustar,

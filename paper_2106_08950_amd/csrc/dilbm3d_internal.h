@@ -2,9 +2,10 @@
 // libdilbm (internal to the library).
 //
 // Memory layout of one 3-D solve in HBM:
-//   pop[2]        two population buffers, structure of arrays [19][nz][ny][nx] of FP32
-//                 deviations d_i = f_i - w_i rho0.  Pull scheme: node x at time t_n finds
-//                 f_i in pop[p][i][x - c_i].
+//   pop[2]        two population buffers, structure of arrays [q][nz][ny][nx] (q = 19 or
+//                 27) of FP32 g_i = S (f_i - w_i rho0), S = 36 or 216, stored in the moving
+//                 frame of ref_velocity3.  Pull scheme: node x at time t_n finds f_i in
+//                 pop[p][i][x - c_i].
 //   tile_head[2]  per tile (64 x 4 x 1 or 256 x 1 x 1 nodes) two words: the number of
 //                 spheres whose phi support may touch it and the first list entry;
 //                 tile_list[2]: `list_cap` entries per tile (sphere index and four-wave
@@ -24,7 +25,8 @@
 
 namespace dilbm {
 
-constexpr int kQ3 = 19;
+constexpr int kQ3 = 19;      // D3Q19
+constexpr int kQ3Max = 27;   // D3Q27
 // Tiles are tile_x x (256 / tile_x) x 1 nodes, 256 threads: tile_x = 256 (a whole row of
 // up to 256 nodes per block) when nx >= DILBM3D_WIDE_MIN, else 64 (64 x 4 x 1).
 #ifndef DILBM3D_WIDE_MIN
@@ -35,6 +37,10 @@ constexpr int kMaxListCap3 = 1024;
 // Register budget of the collide kernel: compiled for at least this many waves per SIMD.
 #ifndef DILBM3D_COLLIDE_WAVES
 #define DILBM3D_COLLIDE_WAVES 4
+#endif
+// the same for the D3Q27 instances (27 populations per node)
+#ifndef DILBM3D27_COLLIDE_WAVES
+#define DILBM3D27_COLLIDE_WAVES 3
 #endif
 
 // Chunk of tiles each collide block sweeps (the grid never drops below one resident

@@ -64,13 +64,18 @@ dilbm_status guard3(std::string *err, F &&f) {
   }
 }
 
+// directions of the lattice: 19 (D3Q19, also for 0) or 27 (D3Q27)
+int q_of(const dilbm3d_params &p) { return p.lattice == 27 ? 27 : 19; }
+
 void validate3(const dilbm3d_params *p) {
   if (!p) fail3(DILBM_EINVAL, "params is NULL");
   if (p->abi_version != DILBM3D_ABI_VERSION) fail3(DILBM_EABI, "abi_version mismatch");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) fail3(DILBM_EINVAL, "nx, ny, nz must be >= 1");
+  if (p->lattice != 0 && p->lattice != 19 && p->lattice != 27)
+    fail3(DILBM_EINVAL, "lattice must be 19 (D3Q19) or 27 (D3Q27)");
   const uint64_t nodes = (uint64_t)p->nx * p->ny * p->nz;
-  if (nodes * kQ3 * 4ull >= (1ull << 32) - 256)
-    fail3(DILBM_EINVAL, "19 * 4 bytes * nx * ny * nz must stay under 4 GB");
+  if (nodes * (uint64_t)q_of(*p) * 4ull >= (1ull << 32) - 256)
+    fail3(DILBM_EINVAL, "q * 4 bytes * nx * ny * nz must stay under 4 GB");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) fail3(DILBM_EINVAL, "tau must be > 0.5");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) fail3(DILBM_EINVAL, "rho0 must be > 0");
   if (!(p->interface_width > 0.0) || !std::isfinite(p->interface_width))
@@ -164,7 +169,7 @@ void size_grid3(dilbm3d_solver &s) {
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_of(s.prm, 256), (int64_t)1 << 30));
     return;
   }
-  const int bpc = std::max(1, collide3_blocks_per_cu(s.tile_x));
+  const int bpc = std::max(1, collide3_blocks_per_cu(q_of(s.prm), s.tile_x));
   int cus = 0;
   HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
   const int64_t T = tiles_of(s.prm, s.tile_x), resident = (int64_t)cus * bpc;
@@ -242,7 +247,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.xi = p.coll_xi;
   d.wall_h_d = p.wall_half_thickness;
   d.support = p.phi_cutoff * p.interface_width;
-  const uint64_t half = (uint64_t)kQ3 * p.nx * p.ny * p.nz * 4;
+  const uint64_t half = (uint64_t)q_of(p) * p.nx * p.ny * p.nz * 4;
   d.pop[0] = (float *)s.pops.ptr;
   d.pop[1] = (float *)((char *)s.pops.ptr + half);
   char *bb = (char *)s.body.ptr;
@@ -352,7 +357,7 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
       HIPCHK3(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
       s.own_stream = true;
     }
-    const uint64_t half = (uint64_t)kQ3 * p->nx * p->ny * p->nz * 4;
+    const uint64_t half = (uint64_t)q_of(*p) * p->nx * p->ny * p->nz * 4;
     s.pops = alloc3(2 * half);
     HIPCHK3(hipMalloc(&s.d_desc, sizeof(Desc3)));
     HIPCHK3(hipMalloc(&s.d_err, sizeof(int32_t)));
@@ -364,7 +369,8 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
     HIPCHK3(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, s.stream));
     HIPCHK3(launch_zero_bytes(s.d_err, sizeof(int32_t), s.stream));
     upload_desc3(s);
-    HIPCHK3(launch3_rest_pops((int64_t)kQ3 * p->nx * p->ny * p->nz, s.stream, s.d_desc, 0));
+    HIPCHK3(launch3_rest_pops(q_of(*p), (int64_t)q_of(*p) * p->nx * p->ny * p->nz, s.stream,
+                              s.d_desc, 0));
     size_grid3(s);
   });
   if (st != DILBM_OK) {
@@ -440,12 +446,12 @@ dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev) {
   return guard3(&s->last_error, [&] {
     check_usable3(s);
     HIPCHK3(hipSetDevice(s->device));
-    const int64_t count = (int64_t)kQ3 * s->prm.nx * s->prm.ny * s->prm.nz;
+    const int64_t count = (int64_t)q_of(s->prm) * s->prm.nx * s->prm.ny * s->prm.nz;
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
     HIPCHK3(hipMemcpyAsync(tmp.p, f_dev, sizeof(double) * count, hipMemcpyHostToDevice,
                            s->stream));
-    HIPCHK3(launch3_set_pops(count, s->stream, s->d_desc, s->parity, s->steps,
+    HIPCHK3(launch3_set_pops(q_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps,
                              (const double *)tmp.p));
     HIPCHK3(hipStreamSynchronize(s->stream));
   });
@@ -455,10 +461,10 @@ dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev) {
   if (!s || !f_dev) return DILBM_EINVAL;
   return guard3(&s->last_error, [&] {
     HIPCHK3(hipSetDevice(s->device));
-    const int64_t count = (int64_t)kQ3 * s->prm.nx * s->prm.ny * s->prm.nz;
+    const int64_t count = (int64_t)q_of(s->prm) * s->prm.nx * s->prm.ny * s->prm.nz;
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
-    HIPCHK3(launch3_get_pops(count, s->stream, s->d_desc, s->parity, s->steps, (double *)tmp.p));
+    HIPCHK3(launch3_get_pops(q_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps, (double *)tmp.p));
     HIPCHK3(hipMemcpyAsync(f_dev, tmp.p, sizeof(double) * count, hipMemcpyDeviceToHost,
                            s->stream));
     HIPCHK3(hipStreamSynchronize(s->stream));
@@ -478,12 +484,14 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
         HIPCHK3(hipEventCreate(&ev.first));
         HIPCHK3(hipEventCreate(&ev.second));
         HIPCHK3(hipEventRecord(ev.first, s->stream));
-        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p, s->steps));
+        HIPCHK3(launch3_collide(q_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+                                s->steps));
         HIPCHK3(hipEventRecord(ev.second, s->stream));
         s->events.push_back(ev);
         if (s->events.size() >= 4096) collect_timing3(*s);
       } else {
-        HIPCHK3(launch3_collide(s->h.tile_x, s->grid, s->stream, s->d_desc, p, s->steps));
+        HIPCHK3(launch3_collide(q_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+                                s->steps));
       }
       HIPCHK3(launch3_bodies(false, s->nb, s->tile_x, s->stream, s->d_desc, p));
       s->parity ^= 1;
@@ -503,7 +511,7 @@ dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, doub
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * 4 * n));
     double *t = (double *)tmp.p;
-    HIPCHK3(launch3_fields(s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, s->steps,
+    HIPCHK3(launch3_fields(q_of(s->prm), s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, s->steps,
                            t, t + n, t + 2 * n, t + 3 * n));
     double *outs[4] = {rho, ux, uy, uz};
     for (int k = 0; k < 4; ++k)

@@ -1,4 +1,5 @@
-// kernels3d.hip -- gfx950 kernels of the three-dimensional DI-LBM step (D3Q19, spheres).
+// kernels3d.hip -- gfx950 kernels of the three-dimensional DI-LBM step (D3Q19 or D3Q27,
+// spheres).
 //
 // The step is the one of kernels.hip carried to three dimensions (Section 2.3 of the
 // paper with Eqs. (13)-(19), (22)-(24), (28)-(29)); see dilbm3d.h for the readings.
@@ -13,9 +14,11 @@
 //               (each entry carries which of the tile's four waves the support reaches).
 //   k3_fields   rho and the corrected velocity of Eq. (17) (output only).
 //
-// Populations are kept as g_i = 36 (f_i - w_i rho0) in FP32: the weights 1/3, 1/18, 1/36
-// enter as the exact integers K_i = 12, 2, 1, so every constant on the mass and momentum
-// path is exact in binary and what remains is unbiased round-to-nearest.
+// Populations are kept as g_i = S (f_i - w_i rho0) in FP32, with S making the weights exact
+// integers K_i = S w_i: D3Q19 S = 36 (weights 1/3, 1/18, 1/36 -> K = 12, 2, 1), D3Q27
+// S = 216 (8/27, 2/27, 1/54, 1/216 -> K = 64, 16, 4, 1).  Every constant on the mass and
+// momentum path is then exact in binary and what remains is unbiased round-to-nearest.
+// Kernels are instantiated per lattice L (19 or 27 directions).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,19 +32,39 @@ namespace dilbm {
 
 namespace {
 
-// D3Q19: rest, the six axis directions, the twelve edge directions; opposite directions
-// are neighbours (i, i + 1) for odd i.
-constexpr int C3X[kQ3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int C3Y[kQ3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int C3Z[kQ3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-constexpr float K3[kQ3] = {12.0f, 2.0f, 2.0f, 2.0f, 2.0f, 2.0f, 2.0f, 1.0f, 1.0f, 1.0f,
-                           1.0f,  1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f};
-constexpr float kInv36 = 1.0f / 36.0f;
+// Directions: rest, the six axis directions, the twelve edge directions (D3Q19), then the
+// eight corner directions (D3Q27); opposite directions are neighbours (i, i + 1) for odd i.
+constexpr int C3X[kQ3Max] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                             1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int C3Y[kQ3Max] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                             1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int C3Z[kQ3Max] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                             1, -1, -1, 1, 1, -1, 1, -1};
 
-// x / 36 correctly rounded: the reciprocal product corrected by one FMA residual step
-__device__ __forceinline__ float div36_3(float x) {
-  const float q = x * kInv36;
-  return fmaf(fmaf(-36.0f, q, x), kInv36, q);
+// The population scale S and the integer weights K_i = S w_i of lattice L.
+template <int L>
+struct Lat3;
+template <>
+struct Lat3<19> {
+  static constexpr float S = 36.0f;
+  static constexpr float K[4] = {12.0f, 2.0f, 1.0f, 0.0f};  // by |c|^2
+};
+template <>
+struct Lat3<27> {
+  static constexpr float S = 216.0f;
+  static constexpr float K[4] = {64.0f, 16.0f, 4.0f, 1.0f};
+};
+template <int L>
+__host__ __device__ constexpr float kw3(int i) {
+  return Lat3<L>::K[(C3X[i] != 0) + (C3Y[i] != 0) + (C3Z[i] != 0)];
+}
+
+// x / S correctly rounded: the reciprocal product corrected by one FMA residual step
+template <int L>
+__device__ __forceinline__ float divS(float x) {
+  constexpr float S = Lat3<L>::S, inv = 1.0f / S;
+  const float q = x * inv;
+  return fmaf(fmaf(-S, q, x), inv, q);
 }
 
 __device__ __forceinline__ SphereSnap load_snap3(const DILBM_CONST SphereSnap *q) {
@@ -64,20 +87,31 @@ __device__ __forceinline__ SphereSnap load_snap3(const DILBM_CONST SphereSnap *q
 // step t what is stored is g_i - 3 K_i c_i.V_t with V_t pseudo-random, so the rounding of
 // a steady per-step increment onto the FP32 grid does not make the same error every step
 // (without it a uniformly driven 64 x 40 x 32 case drifted to 1.8e-5 of the velocity in
-// 1000 steps).  Each component of V_t has 20 significant bits on the grid 2^-36
-// (|V_t| < 2^-17): every frame constant 3 K_i c_i.V_t (K_i = 12, 2, 1), its changes and
-// 36 V_t are exact in FP32, so a fluid at rest stays exactly at rest.
+// 1000 steps).  Each component of V_t is a multiple of 2^-36 with B significant bits,
+// |V_t| < 2^(B-37): B = 18 on D3Q19, 15 on D3Q27.  Every frame constant 3 K_i c_i.V_t is
+// then a multiple of 2^-36, and so is every partial sum of them the moments take; those
+// sums are bounded by 3 V_max sum_i K_i |c_i|_1 = 3 V_max S (108 V_max < 2^-12.2 on
+// D3Q19, 648 V_max < 2^-12.6 on D3Q27), so they hold at most 24 significant bits and are
+// exact in FP32, as are the per-step changes of the constants and S V_t: a fluid at rest
+// stays exactly at rest.  (With 20 bits the D3Q27 moment sums round: its S is six times
+// larger.)  Against the FP32 grid of the populations the offsets stay far above one ulp,
+// which is all the decorrelation needs.
+template <int L>
 __device__ __forceinline__ float3 ref_velocity3(int64_t t) {
+  constexpr int B = L == 27 ? 15 : 18;
+  constexpr uint32_t mask = (1u << B) - 1u;
+  constexpr int half = 1 << (B - 1);
   const uint64_t z = splitmix64((uint64_t)t);
   constexpr float q = 1.0f / 68719476736.0f;  // 2^-36
-  return make_float3((float)((int)(z & 0xFFFFFu) - (1 << 19)) * q,
-                     (float)((int)((z >> 20) & 0xFFFFFu) - (1 << 19)) * q,
-                     (float)((int)((z >> 40) & 0xFFFFFu) - (1 << 19)) * q);
+  return make_float3((float)((int)(z & mask) - half) * q,
+                     (float)((int)((z >> 20) & mask) - half) * q,
+                     (float)((int)((z >> 40) & mask) - half) * q);
 }
 
 // 3 K_i c_i.V: the frame offset of direction i
+template <int L>
 __device__ __forceinline__ double frame_offset3(int i, float3 V) {
-  return 3.0 * (double)K3[i] *
+  return 3.0 * (double)kw3<L>(i) *
          ((double)C3X[i] * V.x + (double)C3Y[i] * V.y + (double)C3Z[i] * V.z);
 }
 
@@ -87,7 +121,7 @@ enum Mode3 { kStep3 = 0, kFields3 = 1 };
 
 // One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
-template <int MODE, int TX>
+template <int MODE, int TX, int L>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
                                       const int64_t t, float (*red)[6][64],
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
@@ -113,7 +147,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const uint32_t plane = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
   const uint32_t pb = plane * 4u;
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(kQ3 * pb), kBufferFlags);
+      __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(L * pb), kBufferFlags);
   const uint32_t vx0 = (uint32_t)xc * 4u;
   const uint32_t vxm = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * 4u;  // source x - 1
   const uint32_t vxp = (uint32_t)(xc + 1 == nx ? 0 : xc + 1) * 4u;  // source x + 1
@@ -125,9 +159,9 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       row[dz + 1][dy + 1] = __builtin_amdgcn_readfirstlane(
           ((uint32_t)wrapi(z + dz, nz) * (uint32_t)ny + (uint32_t)wrapi(yc + dy, ny)) *
           (uint32_t)nx * 4u);
-  float g[kQ3];
+  float g[L];
 #pragma unroll
-  for (int i = 0; i < kQ3; ++i) {
+  for (int i = 0; i < L; ++i) {
     const uint32_t v = C3X[i] == 0 ? vx0 : (C3X[i] > 0 ? vxm : vxp);
     const uint32_t s = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
     g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, s, 0));
@@ -161,36 +195,37 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // across the whole tile.
   int64_t tc = t;
   asm volatile("" : "+s"(tc));
-  float3 Vf = ref_velocity3(tc);
+  float3 Vf = ref_velocity3<L>(tc);
   if (MODE == kStep3) {
     const float3 Vt = Vf;
-    Vf = ref_velocity3(tc + 1);
+    Vf = ref_velocity3<L>(tc + 1);
     const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
 #pragma unroll
-    for (int i = 1; i < kQ3; ++i)
-      g[i] -= (3.0f * K3[i]) * ((float)C3X[i] * dvx + (float)C3Y[i] * dvy + (float)C3Z[i] * dvz);
+    for (int i = 1; i < L; ++i)
+      g[i] -= (3.0f * kw3<L>(i)) *
+              ((float)C3X[i] * dvx + (float)C3Y[i] * dvy + (float)C3Z[i] * dvz);
   }
-  const float V36x = 36.0f * Vf.x, V36y = 36.0f * Vf.y, V36z = 36.0f * Vf.z;  // exact
+  constexpr float S = Lat3<L>::S, invS = 1.0f / S, halfS = 0.5f * S;
+  const float V36x = S * Vf.x, V36y = S * Vf.y, V36z = S * Vf.z;  // S V, exact
 
-  // ---- moments, Eqs. (5) and (16), in g units (D = 36 drho, J = 36 j - 36 V; the frame
+  // ---- moments, Eqs. (5) and (16), in g units (D = S drho, J = S j - S V; the frame
   // carries no mass) ------------------------------------------------------------------
   float D = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
 #pragma unroll
-  for (int i = 0; i < kQ3; ++i) {
+  for (int i = 0; i < L; ++i) {
     D += g[i];
     if (C3X[i]) Jx += C3X[i] > 0 ? g[i] : -g[i];
     if (C3Y[i]) Jy += C3Y[i] > 0 ? g[i] : -g[i];
     if (C3Z[i]) Jz += C3Z[i] > 0 ? g[i] : -g[i];
   }
-  const float R = 36.0f * d.rho0 + D;  // 36 rho
-  const float rho = R * kInv36;
-  const float drho = D * kInv36;
+  const float R = S * d.rho0 + D;  // S rho
+  const float rho = R * invS;
+  const float drho = D * invS;
   float Rinv = __builtin_amdgcn_rcpf(R);
   Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
-  // 36 rho u* = 36 (j + G/2), back in the fixed frame
-  // 36 rho u* = 36 (j + G/2), back in the fixed frame
-  const float Jgx = Jx + (V36x + 18.0f * d.Gx), Jgy = Jy + (V36y + 18.0f * d.Gy);
-  const float Jgz = Jz + (V36z + 18.0f * d.Gz);
+  // S rho u* = S (j + G/2), back in the fixed frame
+  const float Jgx = Jx + (V36x + halfS * d.Gx), Jgy = Jy + (V36y + halfS * d.Gy);
+  const float Jgz = Jz + (V36z + halfS * d.Gz);
   const float usx = Jgx * Rinv, usy = Jgy * Rinv, usz = Jgz * Rinv;
 
   // ---- diffuse solid field, Eq. (14), and its sums over spheres and walls ---------------
@@ -372,10 +407,10 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     }
   }
 
-  // ---- corrected velocity, Eq. (17): 36 rho u = 36 rho u* + 18 P, P = rho (A - Phi u*) --
+  // ---- corrected velocity, Eq. (17): S rho u = S rho u* + (S/2) P, P = rho (A - Phi u*) --
   const float Px = rho * (Ax - Phi * usx), Py = rho * (Ay - Phi * usy);
   const float Pz = rho * (Az - Phi * usz);
-  const float Mx = fmaf(18.0f, Px, Jgx), My = fmaf(18.0f, Py, Jgy), Mz = fmaf(18.0f, Pz, Jgz);
+  const float Mx = fmaf(halfS, Px, Jgx), My = fmaf(halfS, Py, Jgy), Mz = fmaf(halfS, Pz, Jgz);
   const float ux = Mx * Rinv, uy = My * Rinv, uz = Mz * Rinv;
 
   if (MODE == kFields3) {
@@ -395,8 +430,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   //   S_i   = 3 (c - u).G + 9 (c.u)(c.G)            (uniform body force)
   //         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q           (spheres and walls, Eq. (15) summed)
   // taken per pair of opposite directions, which share the even part.
-  // rho u - V, from 36 rho u - 36 V directly (exact frame constant)
-  const float mx = div36_3(Mx - V36x), my = div36_3(My - V36y), mz = div36_3(Mz - V36z);
+  // rho u - V, from S rho u - S V directly (exact frame constant)
+  const float mx = divS<L>(Mx - V36x), my = divS<L>(My - V36y), mz = divS<L>(Mz - V36z);
   const float uu = ux * ux + uy * uy + uz * uz;
   const float Gx = d.Gx, Gy = d.Gy, Gz = d.Gz;
   const float uG = ux * Gx + uy * Gy + uz * Gz;
@@ -413,10 +448,10 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const float om = d.omega, kh = d.khalf;
   const float base = drho - 1.5f * rho * uu;            // even part shared by all i
   const float sbase = -3.0f * uG - 1.5f * trQ;          // even part of S shared by all i
-  float out[kQ3];
-  out[0] = g[0] + om * (K3[0] * base - g[0]) + kh * K3[0] * sbase;
+  float out[L];
+  out[0] = g[0] + om * (kw3<L>(0) * base - g[0]) + kh * kw3<L>(0) * sbase;
 #pragma unroll
-  for (int i = 1; i < kQ3; i += 2) {
+  for (int i = 1; i < L; i += 2) {
     const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
     const float cu = cx * ux + cy * uy + cz * uz;
     const float cm = cx * mx + cy * my + cz * mz;
@@ -424,7 +459,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     const float cP = cx * Px + cy * Py + cz * Pz;
     const float cQc = cx * cx * Qxx + cy * cy * Qyy + cz * cz * Qzz +
                       2.0f * (cx * cy * Qxy + cx * cz * Qxz + cy * cz * Qyz);
-    const float K = K3[i];
+    const float K = kw3<L>(i);
     const float ev = K * (base + 4.5f * rho * cu * cu);     // even part of geq
     const float od = K * 3.0f * cm;                           // odd part of geq
     const float sev = K * (sbase + 9.0f * cu * cG + 4.5f * cQc);
@@ -438,25 +473,25 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     atomicOr(d.err, (int32_t)kErrUnstable);
   if (valid) {
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)d.pop[p ^ 1], (short)0, (int)(kQ3 * pb), kBufferFlags);
+        (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
     const uint32_t s0r = row[1][1];
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i)
+    for (int i = 0; i < L; ++i)
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
                                             (uint32_t)i * pb + s0r, 0);
   }
 }
 
-template <int TX>
-__global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
-    const Desc3 *__restrict__ desc, int p, int64_t step) {
+template <int TX, int L>
+__global__ __launch_bounds__(256, (L == 19 ? DILBM3D_COLLIDE_WAVES : DILBM3D27_COLLIDE_WAVES))
+void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   const Desc3 &d = *desc;
   if (TX == 256) {
     // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
     // XCDs at once
     for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-      tile3<kStep3, TX>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
+      tile3<kStep3, TX, L>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
     return;
   }
   const WorkSplit ws = xcd_split(d.ntiles);
@@ -465,11 +500,11 @@ __global__ __launch_bounds__(256, DILBM3D_COLLIDE_WAVES) void k3_collide(
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX, L>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
-template <int TX>
+template <int TX, int L>
 __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
                                                  int64_t step, double *__restrict__ rho,
                                                  double *__restrict__ ux,
@@ -477,7 +512,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX>(d, t, p, step, nullptr, rho, ux, uy, uz);
+    tile3<kFields3, TX, L>(d, t, p, step, nullptr, rho, ux, uy, uz);
 }
 
 // One block per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
@@ -674,14 +709,15 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   }
 }
 
-// Populations in and out: fin / fout are [19][nz][ny][nx] FP64 deviations f_i - w_i rho0
-// of the current state; node x keeps f_i at x - c_i (pull layout), as g = 36 (f - w rho0).
+// Populations in and out: fin / fout are [L][nz][ny][nx] FP64 deviations f_i - w_i rho0
+// of the current state; node x keeps f_i at x - c_i (pull layout), as g = S (f - w rho0).
+template <int L>
 __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             const double *__restrict__ fin) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
-  const float3 V = ref_velocity3(step);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+  const float3 V = ref_velocity3<L>(step);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
     const int64_t n = e - i * plane;
@@ -691,16 +727,17 @@ __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
     d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] =
-        (float)(36.0 * fin[e] - frame_offset3(i, V));
+        (float)((double)Lat3<L>::S * fin[e] - frame_offset3<L>(i, V));
   }
 }
 
+template <int L>
 __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             double *__restrict__ fout) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
-  const float3 V = ref_velocity3(step);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+  const float3 V = ref_velocity3<L>(step);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
     const int64_t n = e - i * plane;
@@ -710,19 +747,20 @@ __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
     fout[e] = ((double)d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] +
-               frame_offset3(i, V)) /
-              36.0;
+               frame_offset3<L>(i, V)) /
+              (double)Lat3<L>::S;
   }
 }
 
 // The fluid at rest (every deviation zero) in the frame of step `step`, in both buffers.
+template <int L>
 __global__ void k3_rest_pops(const Desc3 *__restrict__ desc, int64_t step) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
-  const float3 V = ref_velocity3(step);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ3 * plane;
+  const float3 V = ref_velocity3<L>(step);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const float v = (float)(-frame_offset3((int)(e / plane), V));  // exact
+    const float v = (float)(-frame_offset3<L>((int)(e / plane), V));  // exact
     d.pop[0][e] = v;
     d.pop[1][e] = v;
   }
@@ -732,32 +770,33 @@ int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min
 
 }  // namespace
 
-hipError_t launch3_collide(int tile_x, int grid, hipStream_t stream, const Desc3 *desc, int p,
-                           int64_t step) {
-  if (tile_x == 256)
-    hipLaunchKernelGGL(k3_collide<256>, dim3(grid), dim3(256), 0, stream, desc, p, step);
-  else
-    hipLaunchKernelGGL(k3_collide<64>, dim3(grid), dim3(256), 0, stream, desc, p, step);
+using Collide3 = void (*)(const Desc3 *, int, int64_t);
+static Collide3 collide3_kernel(int q, int tile_x) {
+  if (q == 27) return tile_x == 256 ? &k3_collide<256, 27> : &k3_collide<64, 27>;
+  return tile_x == 256 ? &k3_collide<256, 19> : &k3_collide<64, 19>;
+}
+
+hipError_t launch3_collide(int q, int tile_x, int grid, hipStream_t stream, const Desc3 *desc,
+                           int p, int64_t step) {
+  hipLaunchKernelGGL(collide3_kernel(q, tile_x), dim3(grid), dim3(256), 0, stream, desc, p,
+                     step);
   return hipGetLastError();
 }
 
-int collide3_blocks_per_cu(int tile_x) {
+int collide3_blocks_per_cu(int q, int tile_x) {
   int n = 0;
-  const void *f = tile_x == 256 ? reinterpret_cast<const void *>(k3_collide<256>)
-                                : reinterpret_cast<const void *>(k3_collide<64>);
+  const void *f = reinterpret_cast<const void *>(collide3_kernel(q, tile_x));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) return 0;
   return n;
 }
 
-hipError_t launch3_fields(int tile_x, int64_t ntiles, hipStream_t stream, const Desc3 *desc,
-                          int p, int64_t step, double *rho, double *ux, double *uy, double *uz) {
+hipError_t launch3_fields(int q, int tile_x, int64_t ntiles, hipStream_t stream,
+                          const Desc3 *desc, int p, int64_t step, double *rho, double *ux,
+                          double *uy, double *uz) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
-  if (tile_x == 256)
-    hipLaunchKernelGGL(k3_fields<256>, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux,
-                       uy, uz);
-  else
-    hipLaunchKernelGGL(k3_fields<64>, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux,
-                       uy, uz);
+  auto k = q == 27 ? (tile_x == 256 ? &k3_fields<256, 27> : &k3_fields<64, 27>)
+                   : (tile_x == 256 ? &k3_fields<256, 19> : &k3_fields<64, 19>);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux, uy, uz);
   return hipGetLastError();
 }
 
@@ -771,24 +810,24 @@ hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch3_set_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+hipError_t launch3_set_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
                             int64_t step, const double *fin) {
-  hipLaunchKernelGGL(k3_set_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
-                     step, fin);
+  hipLaunchKernelGGL(q == 27 ? &k3_set_pops<27> : &k3_set_pops<19>,
+                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step, fin);
   return hipGetLastError();
 }
 
-hipError_t launch3_get_pops(int64_t count, hipStream_t stream, const Desc3 *desc, int p,
+hipError_t launch3_get_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
                             int64_t step, double *fout) {
-  hipLaunchKernelGGL(k3_get_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p,
-                     step, fout);
+  hipLaunchKernelGGL(q == 27 ? &k3_get_pops<27> : &k3_get_pops<19>,
+                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step, fout);
   return hipGetLastError();
 }
 
-hipError_t launch3_rest_pops(int64_t count, hipStream_t stream, const Desc3 *desc,
+hipError_t launch3_rest_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc,
                              int64_t step) {
-  hipLaunchKernelGGL(k3_rest_pops, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc,
-                     step);
+  hipLaunchKernelGGL(q == 27 ? &k3_rest_pops<27> : &k3_rest_pops<19>,
+                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, step);
   return hipGetLastError();
 }
 

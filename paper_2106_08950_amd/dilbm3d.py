@@ -14,7 +14,7 @@ import numpy as np
 from . import dilbm
 
 Q = 19
-ABI_VERSION = 1
+ABI_VERSION = 2
 WALL_Y, WALL_X, WALL_Z = 1, 2, 4
 
 EXPORTED = [
@@ -38,7 +38,7 @@ class dilbm3d_params(C.Structure):
         ("coll_eps_p", C.c_double), ("coll_eps_p_overlap", C.c_double),
         ("coll_eps_w", C.c_double), ("coll_eps_w_overlap", C.c_double),
         ("coll_xi", C.c_double),
-        ("list_capacity", C.c_int32),
+        ("list_capacity", C.c_int32), ("lattice", C.c_int32),
         ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -100,6 +100,7 @@ class Params3D:
     coll_eps_w_overlap: float = 0.5e4
     coll_xi: float = 1.0
     list_capacity: int = 0
+    lattice: int = 19          # 19: D3Q19, 27: D3Q27
     device: int = 0
     stream: int = 0
     abi_version: int = ABI_VERSION
@@ -121,6 +122,7 @@ class Params3D:
         p.coll_eps_w, p.coll_eps_w_overlap = float(self.coll_eps_w), float(self.coll_eps_w_overlap)
         p.coll_xi = float(self.coll_xi)
         p.list_capacity = int(self.list_capacity)
+        p.lattice = int(self.lattice)
         p.device = int(self.device)
         p.stream = int(self.stream) or None
         return p
@@ -148,7 +150,8 @@ def _ptr(a):
 
 
 class Solver3D:
-    """One 3-D DI-LBM solve on the GPU.  Populations: [19, nz, ny, nx] deviations."""
+    """One 3-D DI-LBM solve on the GPU.  Populations: [q, nz, ny, nx] deviations, q = 19
+    (D3Q19) or 27 (D3Q27, params.lattice = 27)."""
 
     def __init__(self, params: Params3D):
         self.params = params
@@ -165,6 +168,10 @@ class Solver3D:
     def shape(self):
         p = self.params
         return (p.nz, p.ny, p.nx)
+
+    @property
+    def q(self):
+        return 27 if self.params.lattice == 27 else 19
 
     def _check(self, st, where):
         if st != 0:
@@ -199,11 +206,11 @@ class Solver3D:
         self.nb = n
 
     def set_populations(self, f_dev):
-        f_dev = _f64(f_dev, (Q,) + self.shape)
+        f_dev = _f64(f_dev, (self.q,) + self.shape)
         self._check(load().dilbm3d_set_populations(self._h, _ptr(f_dev)), "dilbm3d_set_populations")
 
     def get_populations(self):
-        out = np.zeros((Q,) + self.shape)
+        out = np.zeros((self.q,) + self.shape)
         self._check(load().dilbm3d_get_populations(self._h, _ptr(out)), "dilbm3d_get_populations")
         return out
 

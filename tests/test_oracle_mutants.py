@@ -23,7 +23,7 @@ SRC3 = os.path.join(ORA, "dilbm3d_oracle.c")
 PINS2 = ["tests/test_oracle_pointwise.py", "tests/test_oracle_solver.py",
          "tests/test_oracle_bodies.py", "tests/test_oracle_boundaries.py"]
 BODIES = ["tests/test_oracle_bodies.py"]
-PINS3 = ["tests/test_oracle3d.py"]
+PINS3 = ["tests/test_oracle3d.py", "tests/test_oracle3d_q27.py"]
 
 # (name, source, text, replacement, pin files that must catch it)
 MUTANTS = [
@@ -94,6 +94,13 @@ MUTANTS = [
      "ust[a] = (j[a] + 0.5 * G[a]) / rho;", "ust[a] = j[a] / rho;", PINS3),
     ("3-D interface width doubled", SRC3, "return 0.5 * (1.0 + tanh(2.0 * l / p->eps));",
      "return 0.5 * (1.0 + tanh(l / p->eps));", PINS3),
+    ("D3Q27 corner weight 1/108", SRC3, "(n == 2 ? 1.0 / 54.0 : 1.0 / 216.0)",
+     "(n == 2 ? 1.0 / 54.0 : 1.0 / 108.0)", PINS3),
+    ("D3Q27 edge and corner weights swapped", SRC3, "(n == 2 ? 1.0 / 54.0 : 1.0 / 216.0)",
+     "(n == 2 ? 1.0 / 216.0 : 1.0 / 54.0)", PINS3),
+    ("D3Q27 corner direction flipped in z", SRC3,
+     "                                 1, -1, -1, 1, 1, -1, 1, -1};",
+     "                                 -1, -1, -1, 1, 1, -1, 1, -1};", PINS3),
 ]
 
 
