@@ -242,7 +242,13 @@ dilbm_status dilbm_pool_submit(dilbm_pool *pool, const dilbm_params *p, int32_t 
                                const uint8_t *fixed, int64_t nsteps, int64_t *ticket);
 
 /* Enqueue up to `steps` steps for every member that has steps left (fewer for members
- * that finish earlier) and return without waiting. */
+ * that finish earlier).  After each K-step chunk the members' sticky error words are
+ * copied to the host asynchronously; the call waits for the previous chunk's copy (the
+ * device keeps the current chunk queued) and stops every member whose solve has become
+ * unstable or overflowed a list: it leaves the pool at most one chunk after the failure,
+ * dilbm_pool_query reports it done, and its results calls return the error.  The call
+ * returns with the last chunk still running; dilbm_pool_sync waits for it and applies
+ * the same check. */
 dilbm_status dilbm_pool_run(dilbm_pool *pool, int32_t steps);
 
 /* Wait for everything enqueued so far. */

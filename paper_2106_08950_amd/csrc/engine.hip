@@ -614,6 +614,9 @@ class Engine {
     HIPCHK(hipEventSynchronize(flag_ev_));
     return *h_flag_;
   }
+  // The error table as it stands on the device: its address and the slots in use.
+  const int32_t *err_table() const { return d_err_; }
+  int err_slots() const { return (int)slot_used_.size(); }
   int32_t read_error_of(Solve &s, hipStream_t st) {
     int32_t v = 0;
     HIPCHK(hipMemcpyAsync(&h_err_[s.slot], d_err_ + s.slot, sizeof(int32_t),
@@ -1107,6 +1110,13 @@ struct dilbm_pool {
   std::string last_error;
   double *scratch = nullptr;
   uint64_t scratch_n = 0;
+  // error words of the members after the last enqueued chunk, copied asynchronously into
+  // pinned memory; `poll_who` names the (ticket, slot) pairs the copy covers
+  int32_t *h_poll = nullptr;
+  int poll_cap = 0;
+  hipEvent_t poll_ev = nullptr;
+  bool poll_pending = false;
+  std::vector<std::pair<int64_t, int>> poll_who;
 };
 
 namespace {
@@ -1568,6 +1578,68 @@ dilbm_status dilbm_pool_submit(dilbm_pool *pool, const dilbm_params *prm, int32_
   });
 }
 
+// A member leaves the pool: its completion is marked by an event after the work enqueued
+// so far.
+static void finish_member(Engine &eng, Solve *s) {
+  HIPCHK(hipEventRecord(s->done_ev, eng.stream()));
+  s->finished = true;
+  eng.leave(s);
+}
+
+// The sticky error bits of a pool solve, as its status and message.
+static void poison_from_flags(Solve *s, int32_t e) {
+  if (s->poison != DILBM_OK) return;
+  if (e & kErrInternal) {
+    s->poison = DILBM_EDEVICE;
+    s->err = "internal error: a kernel met an out-of-range body index";
+  } else if (e & kErrCapacity) {
+    s->poison = DILBM_ECAPACITY;
+    s->err = "a tile body list overflowed";
+  } else if (e & kErrUnstable) {
+    s->poison = DILBM_EUNSTABLE;
+    s->err = "unstable";
+  }
+}
+
+// Wait for the members' error words copied after the previous chunk and stop every
+// member whose solve has failed (it runs at most the one chunk enqueued since).
+static void poll_wait(dilbm_pool *pool) {
+  if (!pool->poll_pending) return;
+  Engine &eng = *pool->eng;
+  HIPCHK(hipEventSynchronize(pool->poll_ev));
+  pool->poll_pending = false;
+  for (const auto &w : pool->poll_who) {
+    auto it = pool->solves.find(w.first);
+    if (it == pool->solves.end()) continue;  // released since
+    Solve *s = it->second.get();
+    const int32_t e = pool->h_poll[w.second];
+    if (e == 0 || s->slot != w.second) continue;
+    poison_from_flags(s, e);
+    if (!s->finished) finish_member(eng, s);
+  }
+}
+
+// Copy the members' error words after the work enqueued so far (asynchronous).
+static void poll_copy_async(dilbm_pool *pool) {
+  Engine &eng = *pool->eng;
+  const int n = eng.err_slots();
+  if (n == 0 || eng.members().empty()) return;
+  if (!pool->poll_ev) HIPCHK(hipEventCreateWithFlags(&pool->poll_ev, hipEventDisableTiming));
+  if (n > pool->poll_cap) {
+    (void)hipHostFree(pool->h_poll);
+    pool->h_poll = nullptr;
+    pool->poll_cap = 0;
+    HIPCHK(hipHostMalloc(&pool->h_poll, sizeof(int32_t) * n));
+    pool->poll_cap = n;
+  }
+  HIPCHK(hipMemcpyAsync(pool->h_poll, eng.err_table(), sizeof(int32_t) * n,
+                        hipMemcpyDeviceToHost, eng.stream()));
+  HIPCHK(hipEventRecord(pool->poll_ev, eng.stream()));
+  pool->poll_who.clear();
+  for (Solve *s : eng.members()) pool->poll_who.push_back({s->ticket, s->slot});
+  pool->poll_pending = true;
+}
+
 dilbm_status dilbm_pool_run(dilbm_pool *pool, int32_t steps) {
   if (!pool || steps < 0) return DILBM_EINVAL;
   return guard(&pool->last_error, [&] {
@@ -1580,16 +1652,15 @@ dilbm_status dilbm_pool_run(dilbm_pool *pool, int32_t steps) {
       const int k = std::min(left, K);
       eng.run_chunk(k, true);
       left -= k;
-      // members whose last step is enqueued leave the member set; their completion is
-      // marked by an event after this chunk
+      // members whose last step is enqueued leave the member set
       std::vector<Solve *> done;
       for (Solve *s : eng.members())
         if (s->remaining() <= 0) done.push_back(s);
-      for (Solve *s : done) {
-        HIPCHK(hipEventRecord(s->done_ev, eng.stream()));
-        s->finished = true;
-        eng.leave(s);
-      }
+      for (Solve *s : done) finish_member(eng, s);
+      // the flags as of the previous chunk's end: waiting for them leaves this chunk
+      // queued, so the device does not idle; a failed member stops one chunk later
+      poll_wait(pool);
+      poll_copy_async(pool);
     }
   });
 }
@@ -1599,6 +1670,7 @@ dilbm_status dilbm_pool_sync(dilbm_pool *pool) {
   return guard(&pool->last_error, [&] {
     HIPCHK(hipSetDevice(pool->eng->device()));
     HIPCHK(hipStreamSynchronize(pool->eng->stream()));
+    poll_wait(pool);
     process_deferred(pool);
   });
 }
@@ -1624,19 +1696,7 @@ static void ready_for_results(dilbm_pool *pool, Solve *s) {
   Engine &eng = *pool->eng;
   HIPCHK(hipSetDevice(eng.device()));
   HIPCHK(hipEventSynchronize(s->done_ev));
-  if (s->poison == DILBM_OK) {
-    const int32_t e = eng.read_error_of(*s, eng.aux());
-    if (e & kErrInternal) {
-      s->poison = DILBM_EDEVICE;
-      s->err = "internal error: a kernel met an out-of-range body index";
-    } else if (e & kErrCapacity) {
-      s->poison = DILBM_ECAPACITY;
-      s->err = "a tile body list overflowed";
-    } else if (e & kErrUnstable) {
-      s->poison = DILBM_EUNSTABLE;
-      s->err = "unstable";
-    }
-  }
+  if (s->poison == DILBM_OK) poison_from_flags(s, eng.read_error_of(*s, eng.aux()));
 }
 
 dilbm_status dilbm_pool_get_fields(dilbm_pool *pool, int64_t ticket, double *rho, double *ux,
@@ -1828,6 +1888,8 @@ void dilbm_pool_destroy(dilbm_pool *pool) {
       }
       pool->deferred.clear();
       (void)hipFree(pool->scratch);
+      (void)hipHostFree(pool->h_poll);
+      if (pool->poll_ev) (void)hipEventDestroy(pool->poll_ev);
       pool->eng.reset();
     }
     pool->arena.reset();

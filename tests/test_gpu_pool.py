@@ -174,3 +174,39 @@ def test_tile_shape_change_rebins_every_member():
         xp, up, wp = pool.get_particles(t)
         assert np.abs(xp - xo).max() < 1e-6
     pool.close()
+
+
+def test_failed_member_stops_within_a_chunk():
+    """A member driven past the stability bound (uniform acceleration, G = 1e-3: |u| passes
+    0.5 at step 500) leaves the pool at most one chunk after the chunk in which it failed,
+    and its results report the failure; the other members run all their steps and equal
+    their solves run alone."""
+    K = 32
+    wls = [inputs.Workload(**{**wl.__dict__, "nsteps": 1500}) for wl in _members(9, 3)]
+    bad = inputs.Workload(name="blowup", nx=64, ny=48, tau=0.8, nsteps=4000, G=(1e-3, 0.0))
+    log_case(f"pool member blow-up, K={K}")
+    pool = dilbm.Pool(arena_bytes=256 << 20)
+    pool.set_launch(K, 0)
+    tb = _submit(pool, bad)
+    tickets = [_submit(pool, wl) for wl in wls]
+    for _ in range(200):
+        pool.run(100)
+        if all(pool.query(t)[1] for t in tickets + [tb]):
+            break
+    pool.sync()
+    steps, done = pool.query(tb)
+    assert done and 500 < steps <= 501 + 2 * K, steps
+    with pytest.raises(dilbm.DilbmError) as e:
+        pool.get_fields(tb)
+    assert e.value.status == dilbm.EUNSTABLE
+    for t, wl in zip(tickets, wls):
+        assert pool.query(t) == (wl.nsteps, True)
+        _, uxp, uyp = pool.get_fields(t)
+        g = gpu_solver(wl, tile=0)
+        g.step(wl.nsteps)
+        _, uxa, uya = g.get_fields()
+        assert velocity_rel_l2(uxp, uyp, uxa, uya) < 1e-6, wl.name
+        g.close()
+        pool.release(t)
+    pool.release(tb)
+    pool.close()
