@@ -14,11 +14,12 @@ How each single-solve leg is measured:
 1. set-up (create, bodies) on the host;
 2. the copy bandwidth, the roofline's second denominator: device copies of the population
    volume back to back on the solve's stream;
-3. a settle phase: untimed steps of the same solve for about 0.3 s.  After an idle spell
-   the first ~60 steps (10-15 ms of streaming) run up to 10% slower while the chip's
-   clocks settle (kernel traces show it; back-to-back copies before the steps shorten
-   the transient but do not remove it), so a short timed region right after set-up would
-   measure the transient rather than the step;
+3. a settle phase: untimed calls of K steps of the same solve for about 0.3 s.  After an
+   idle spell the first ~60 steps (10-15 ms of streaming) run up to 10% slower while the
+   chip's clocks settle (kernel traces show it; back-to-back copies before the steps
+   shorten the transient but do not remove it), so a short timed region right after
+   set-up would measure the transient rather than the step; calls of K steps also capture
+   the K-step graph the timed runs replay;
 4. W warm-up steps, then five timed runs of exactly K steps each (production path: HIP
    graph chunks), each bracketed by device synchronisations; `value` and `ms_per_step`
    come from the median run, and all five are reported;
@@ -145,16 +146,19 @@ def copy_bandwidth(stream, nbytes, seconds=0.2):
     return gbs
 
 
-def settle_steps(step, seconds=0.3):
-    """Untimed steps of the solve for about `seconds` (see the module docstring)."""
+def settle_steps(step, chunk, seconds=0.3):
+    """Untimed calls of `chunk` steps of the solve for about `seconds` (see the module
+    docstring); the calls are the timed runs' own length, so the timed runs replay a
+    graph already captured."""
     import torch
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    step(16)
-    torch.cuda.synchronize()
-    per = max((time.perf_counter() - t0) / 16, 1e-6)
-    step(max(16, int(seconds / per)))
+    while True:
+        step(chunk)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            break
 
 
 def timed_runs(step, steps):
@@ -206,7 +210,7 @@ def single_solve(wl, storage, steps, warmup, tile, stream, bytes_per_node, traff
     s = dilbm.Solver(prm)
     s.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
     copy_gbs = copy_bandwidth(stream, 9 * wl.nodes * (4 if storage == dilbm.STORE_FP32 else 2))
-    settle_steps(s.step)
+    settle_steps(s.step, steps)
     s.step(warmup)
     runs = timed_runs(s.step, steps)
     ms = launch_pass(s, max(steps, 200))
@@ -228,7 +232,7 @@ def suspension3d_leg(steps, warmup, stream, q=19):
                                                       lattice=q))
     s.set_particles(w3.pos, w3.radius, w3.density, w3.vel, w3.omega, w3.fixed)
     copy_gbs = copy_bandwidth(stream, q * 4 * w3.nodes)
-    settle_steps(s.step)
+    settle_steps(s.step, steps)
     s.step(warmup)
     runs = timed_runs(s.step, steps)
     ms = launch_pass(s, max(steps, 100))

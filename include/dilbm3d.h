@@ -90,13 +90,21 @@ dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *p
                                    const double *radius, const double *density,
                                    const uint8_t *fixed);
 
-/* Populations in and out, [19][nz][ny][nx] deviations f_i - w_i rho0 at the current step
- * (stored as FP32: values are rounded on the way in). */
+/* Populations in and out, [q][nz][ny][nx] deviations f_i - w_i rho0 at the current step,
+ * q = 19 or 27 (the lattice; stored as FP32: values are rounded on the way in). */
 dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev);
 dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev);
 
-/* Advance nsteps >= 0 steps; synchronous. */
+/* Advance nsteps >= 0 steps (the procedure of Section 2.3 per step: Eqs. (13)-(19) on the
+ * fluid, Eqs. (22)-(24) and (28)-(29) on the spheres); synchronous.  The sticky error
+ * flags are checked every 32 steps while later steps run: a solve that becomes unstable
+ * (rho <= 0, |u| > 0.5 or a non-finite value) or overflows a tile sphere list stops
+ * within 64 steps of the failure, the call returns the error, and the solver refuses
+ * further steps (DILBM_ESTATE). */
 dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps);
+
+/* Steps taken so far (including those a failed call ran before it stopped). */
+dilbm_status dilbm3d_get_step_count(dilbm3d_solver *s, int64_t *steps);
 
 /* rho and the corrected velocity of Eq. (17) at every node, [nz][ny][nx] each; any
  * pointer may be NULL. */

@@ -34,13 +34,20 @@ constexpr int kQ3Max = 27;   // D3Q27
 #endif
 constexpr int kMaxListCap3 = 1024;
 
+// A multi-step call checks the sticky error flags every this many steps.
+constexpr int64_t kPollSteps3 = 32;
+
+// Population bytes (both buffers) above which the collide kernel stores with the
+// non-temporal hint: MI355X's last-level cache (Infinity Cache) holds 256 MB.
+constexpr uint64_t kStoreNtMinBytes3 = 256ull << 20;
+
 // Register budget of the collide kernel: compiled for at least this many waves per SIMD.
 #ifndef DILBM3D_COLLIDE_WAVES
-#define DILBM3D_COLLIDE_WAVES 4
+#define DILBM3D_COLLIDE_WAVES 5
 #endif
 // the same for the D3Q27 instances (27 populations per node)
 #ifndef DILBM3D27_COLLIDE_WAVES
-#define DILBM3D27_COLLIDE_WAVES 3
+#define DILBM3D27_COLLIDE_WAVES 5
 #endif
 
 // Chunk of tiles each collide block sweeps (the grid never drops below one resident
@@ -77,6 +84,7 @@ struct Desc3 {
   float phi_k;        // 4 / eps * log2(e)
   float wall_h;
   uint32_t wall_mask; // bit 0 y, bit 1 x, bit 2 z
+  int32_t store_nt;   // population stores carry the non-temporal hint
   // nodes within h + cutoff*eps of a walled seam: [0, lo) and [hi, n) on each axis
   int32_t wall_lo[3], wall_hi[3];  // axis order x, y, z
   // FP64 sphere constants

@@ -55,6 +55,13 @@ constexpr int32_t kListIndexMask = (1 << kListIndexBits) - 1;
 // Measured on the 4096^2 suspension: FP32 (256 x 1 tiles) 6 waves (80 VGPRs) against 7:
 // 0.5% faster with discs, 2% without; FP16 7 waves (72 VGPRs) against 6: 3-4% faster;
 // 8 waves (64 VGPRs) makes both slower and spills in the FP16 instances.
+// Population bytes (both buffers, all solves of a launch) above which the collide kernels
+// store with the non-temporal hint: MI355X's last-level cache (Infinity Cache) holds 256 MB.
+#ifndef DILBM_STORE_NT_MIN_MB
+#define DILBM_STORE_NT_MIN_MB 256
+#endif
+constexpr uint64_t kStoreNtMinBytes = (uint64_t)DILBM_STORE_NT_MIN_MB << 20;
+
 #ifndef DILBM_COLLIDE_WAVES_F32
 #define DILBM_COLLIDE_WAVES_F32 6
 #endif
@@ -128,6 +135,7 @@ struct SolveDesc {
   float prof_y0, prof_inv_h;   // parabolic profile: s = (y + 1/2 - prof_y0) * prof_inv_h
   float store_scale, store_inv;
   int32_t storage;
+  int32_t store_nt;            // population stores carry the non-temporal hint
   // FP64 body constants
   double rho0_d;
   double gx, gy;

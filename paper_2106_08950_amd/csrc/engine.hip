@@ -768,6 +768,14 @@ class Engine {
       addr_ = addr;
       clear_graphs();
     }
+    // non-temporal population stores for members whose rows start on 128-byte lines, once
+    // the members' populations together exceed the last-level cache
+    uint64_t total_pop = 0;
+    for (Solve *s : members_) total_pop += pop_bytes(s->prm);
+    for (Solve *s : members_) {
+      const uint64_t row = (uint64_t)s->prm.nx * (s->prm.storage == DILBM_STORE_FP16 ? 2 : 4);
+      s->desc.store_nt = (total_pop > kStoreNtMinBytes && row % 128 == 0) ? 1 : 0;
+    }
     bool open = false;
     for (Solve *s : members_) open = open || s->prm.x_boundary != DILBM_XBC_PERIODIC;
     if (open != open_) {
@@ -1359,7 +1367,8 @@ dilbm_status dilbm_step(dilbm_solver *h, int64_t nsteps) {
     }
     eng.collect_timing();
     HIPCHK(hipStreamSynchronize(eng.stream()));
-    poll_errors(eng, h->s);
+    // the copy queued after the last chunk has completed with the stream
+    raise_errors(h->s, eng.flag_wait());
   });
 }
 

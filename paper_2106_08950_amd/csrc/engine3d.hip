@@ -137,6 +137,8 @@ struct dilbm3d_solver {
   Desc3 h{};
   Desc3 *d_desc = nullptr;
   int32_t *d_err = nullptr;
+  int32_t *h_flag = nullptr;      // pinned copy of the error word, taken after a chunk
+  hipEvent_t flag_ev = nullptr;   // marks that copy
   dilbm_status poison = DILBM_OK;
   std::string last_error;
   // kernel timing
@@ -227,6 +229,10 @@ void fill_desc3(dilbm3d_solver &s) {
   d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
   d.wall_h = (float)p.wall_half_thickness;
   d.wall_mask = p.wall_mask;
+  // non-temporal population stores once the populations exceed the last-level cache, when
+  // rows start on 128-byte lines
+  const uint64_t pops = 2ull * q_of(p) * 4ull * (uint64_t)p.nx * p.ny * p.nz;
+  d.store_nt = (pops > kStoreNtMinBytes3 && p.nx % 32 == 0) ? 1 : 0;
   const int n3[3] = {p.nx, p.ny, p.nz};
   const double reach = p.wall_half_thickness + p.phi_cutoff * p.interface_width;
   for (int a = 0; a < 3; ++a) {
@@ -275,10 +281,7 @@ void check_usable3(dilbm3d_solver *s) {
   if (s->poison != DILBM_OK) fail3(DILBM_ESTATE, "handle poisoned: " + s->last_error);
 }
 
-void poll_errors3(dilbm3d_solver &s) {
-  int32_t e = 0;
-  HIPCHK3(hipMemcpyAsync(&e, s.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-  HIPCHK3(hipStreamSynchronize(s.stream));
+void raise_errors3(dilbm3d_solver &s, int32_t e) {
   if (e & kErrInternal) {
     s.poison = DILBM_EDEVICE;
     fail3(DILBM_EDEVICE, "internal error: a kernel met an out-of-range sphere index");
@@ -291,6 +294,21 @@ void poll_errors3(dilbm3d_solver &s) {
     s.poison = DILBM_EUNSTABLE;
     fail3(DILBM_EUNSTABLE, "unstable: rho <= 0, |u| > 0.5 or a non-finite value");
   }
+}
+
+void poll_errors3(dilbm3d_solver &s) {
+  int32_t e = 0;
+  HIPCHK3(hipMemcpyAsync(&e, s.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  HIPCHK3(hipStreamSynchronize(s.stream));
+  raise_errors3(s, e);
+}
+
+// The error word after the work enqueued so far, copied to pinned memory (asynchronous).
+void flag_copy_async3(dilbm3d_solver &s) {
+  if (!s.flag_ev) HIPCHK3(hipEventCreateWithFlags(&s.flag_ev, hipEventDisableTiming));
+  if (!s.h_flag) HIPCHK3(hipHostMalloc(&s.h_flag, sizeof(int32_t)));
+  HIPCHK3(hipMemcpyAsync(s.h_flag, s.d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  HIPCHK3(hipEventRecord(s.flag_ev, s.stream));
 }
 
 void collect_timing3(dilbm3d_solver &s) {
@@ -477,7 +495,19 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
     check_usable3(s);
     if (nsteps < 0) fail3(DILBM_EINVAL, "nsteps must be >= 0");
     HIPCHK3(hipSetDevice(s->device));
+    bool pending = false;
     for (int64_t k = 0; k < nsteps; ++k) {
+      // every kPollSteps3 steps: the flags as of the previous chunk's end (waiting for them
+      // leaves this chunk queued), then a copy of the current ones; a failure stops the
+      // call one chunk later
+      if (k > 0 && k % kPollSteps3 == 0) {
+        if (pending) {
+          HIPCHK3(hipEventSynchronize(s->flag_ev));
+          raise_errors3(*s, *s->h_flag);
+        }
+        flag_copy_async3(*s);
+        pending = true;
+      }
       const int p = s->parity;
       if (s->timing) {
         std::pair<hipEvent_t, hipEvent_t> ev;
@@ -560,6 +590,12 @@ dilbm_status dilbm3d_get_particles(dilbm3d_solver *s, double *pos, double *vel, 
   });
 }
 
+dilbm_status dilbm3d_get_step_count(dilbm3d_solver *s, int64_t *steps) {
+  if (!s || !steps) return DILBM_EINVAL;
+  *steps = s->steps;
+  return DILBM_OK;
+}
+
 dilbm_status dilbm3d_get_wall_force(dilbm3d_solver *s, double *force) {
   if (!s || !force) return DILBM_EINVAL;
   return guard3(&s->last_error, [&] {
@@ -619,6 +655,8 @@ void dilbm3d_destroy(dilbm3d_solver *s) {
     free3(s->body);
     if (s->d_desc) (void)hipFree(s->d_desc);
     if (s->d_err) (void)hipFree(s->d_err);
+    if (s->h_flag) (void)hipHostFree(s->h_flag);
+    if (s->flag_ev) (void)hipEventDestroy(s->flag_ev);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   } catch (...) {
   }

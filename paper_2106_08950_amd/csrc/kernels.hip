@@ -21,6 +21,8 @@
 // (neighbouring tiles share L2 lines at their edges).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "dilbm_internal.h"
 #include "kernels.h"
@@ -50,17 +52,23 @@ struct StoreF32 {
                                               uint32_t soff, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void stb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                              uint32_t soff, float v, float) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff,
+                                          NT ? kStoreNT : 0);
   }
   static __device__ __forceinline__ float ld(const T *p, int64_t i, float) { return p[i]; }
-  static __device__ __forceinline__ void st(T *p, int64_t i, float v, float) { p[i] = v; }
+  template <bool NT = false>
+  static __device__ __forceinline__ void st(T *p, int64_t i, float v, float) {
+    put<NT>(v, p + i);
+  }
   static __device__ __forceinline__ float ldo(const T *plane, uint32_t byte_off, float) {
     return *(const DILBM_GLOBAL T *)((const DILBM_GLOBAL char *)plane + byte_off);
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float) {
-    *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = v;
+    put<NT>(v, (DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off));
   }
 };
 
@@ -100,37 +108,44 @@ struct StoreF16 {
     z = __builtin_amdgcn_cvt_sr_f16_f32(z, x, rnd, false);
     return __builtin_bit_cast(uint16_t, z.x);
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void stb_bits(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                                   uint32_t soff, uint16_t h) {
-    __builtin_amdgcn_raw_buffer_store_b16(h, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(h, r, voff, soff, NT ? kStoreNT : 0);
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void st_bits(T *p, int64_t i, uint16_t h) {
-    ((uint16_t *)p)[i] = h;
+    put<NT>(h, (uint16_t *)p + i);
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void sto_bits(T *plane, uint32_t byte_off, uint16_t h) {
-    *(DILBM_GLOBAL uint16_t *)((DILBM_GLOBAL char *)plane + byte_off) = h;
+    put<NT>(h, (DILBM_GLOBAL uint16_t *)((DILBM_GLOBAL char *)plane + byte_off));
   }
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                               uint32_t soff, float inv) {
     const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
     return (float)__builtin_bit_cast(_Float16, h) * inv;
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void stb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                              uint32_t soff, float v, float scale) {
     const _Float16 h = (_Float16)(v * scale);  // round to nearest even
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, h), r, voff, soff,
+                                          NT ? kStoreNT : 0);
   }
   static __device__ __forceinline__ float ld(const T *p, int64_t i, float inv) {
     return (float)p[i] * inv;
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void st(T *p, int64_t i, float v, float scale) {
-    p[i] = (_Float16)(v * scale);  // round to nearest even
+    put<NT>((_Float16)(v * scale), p + i);  // round to nearest even
   }
   static __device__ __forceinline__ float ldo(const T *plane, uint32_t byte_off, float inv) {
     return (float)*(const DILBM_GLOBAL T *)((const DILBM_GLOBAL char *)plane + byte_off) * inv;
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void sto(T *plane, uint32_t byte_off, float v, float scale) {
-    *(DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off) = (_Float16)(v * scale);
+    put<NT>((_Float16)(v * scale), (DILBM_GLOBAL T *)((DILBM_GLOBAL char *)plane + byte_off));
   }
 };
 
@@ -745,7 +760,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 #pragma unroll
     for (int i = 0; i < kQ; ++i) hb[i] = ST::round_bits(out[i], sc, hh[i >> 1], i & 1);
   }
-  if (valid) {
+  // non-temporal stores or not, per solve (the engine's choice); the branch is uniform
+  auto put_all = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
     if (AM == kAddrBuf && TX >= 64) {
       const __amdgpu_buffer_rsrc_t rd =
           __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
@@ -753,9 +770,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
         if constexpr (ST::kStochastic)
-          ST::stb_bits(rd, o_x0, i * pb + s0, hb[i]);
+          ST::template stb_bits<NT>(rd, o_x0, i * pb + s0, hb[i]);
         else
-          ST::stb(rd, o_x0, i * pb + s0, out[i], sc);
+          ST::template stb<NT>(rd, o_x0, i * pb + s0, out[i], sc);
       }
     } else if (AM == kAddrBuf) {
       const __amdgpu_buffer_rsrc_t rd =
@@ -764,29 +781,35 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
         if constexpr (ST::kStochastic)
-          ST::stb_bits(rd, o, i * pb, hb[i]);
+          ST::template stb_bits<NT>(rd, o, i * pb, hb[i]);
         else
-          ST::stb(rd, o, i * pb, out[i], sc);
+          ST::template stb<NT>(rd, o, i * pb, out[i], sc);
       }
     } else if (AM == kAddrG32) {
       const uint32_t o = o_r0 + o_x0;
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
         if constexpr (ST::kStochastic)
-          ST::sto_bits(dst + i * plane, o, hb[i]);
+          ST::template sto_bits<NT>(dst + i * plane, o, hb[i]);
         else
-          ST::sto(dst + i * plane, o, out[i], sc);
+          ST::template sto<NT>(dst + i * plane, o, out[i], sc);
       }
     } else {
       const int64_t o = (int64_t)yc * nx + xc;
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
         if constexpr (ST::kStochastic)
-          ST::st_bits(dst, i * plane + o, hb[i]);
+          ST::template st_bits<NT>(dst, i * plane + o, hb[i]);
         else
-          ST::st(dst, i * plane + o, out[i], sc);
+          ST::template st<NT>(dst, i * plane + o, out[i], sc);
       }
     }
+  };
+  if (valid) {
+    if (d.store_nt)
+      put_all(std::true_type{});
+    else
+      put_all(std::false_type{});
   }
 }
 
@@ -1148,7 +1171,8 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
     for (int i = 0; i < kQ; ++i)
       hw[i] |= (uint32_t)ST::round_bits(out[k][i], sc, hh[i >> 1], i & 1) << (16 * k);
   }
-  if (valid) {
+  auto put_all = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
     if (AM == kAddrBuf) {
       const uint32_t pb = (uint32_t)plane * 2u;
       const __amdgpu_buffer_rsrc_t rd =
@@ -1156,12 +1180,19 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
       const uint32_t s0 = (uint32_t)(y * nx) * 2u;
 #pragma unroll
       for (int i = 0; i < kQ; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(hw[i], rd, 2u * (uint32_t)xc, i * pb + s0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(hw[i], rd, 2u * (uint32_t)xc, i * pb + s0,
+                                              NT ? kStoreNT : 0);
     } else {
       const int64_t o = (int64_t)y * nx + xc;
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) *(uint32_t *)(dst + i * plane + o) = hw[i];
+      for (int i = 0; i < kQ; ++i) put<NT>(hw[i], (uint32_t *)(dst + i * plane + o));
     }
+  };
+  if (valid) {
+    if (d.store_nt)
+      put_all(std::true_type{});
+    else
+      put_all(std::false_type{});
   }
 }
 

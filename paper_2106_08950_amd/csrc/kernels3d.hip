@@ -119,21 +119,32 @@ __device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >
 
 enum Mode3 { kStep3 = 0, kFields3 = 1 };
 
+#ifndef DILBM3D27_STASH
+#define DILBM3D27_STASH 19
+#endif
+// populations held in LDS during the sphere loop
+template <int L>
+constexpr int kStash3 = L == 27 ? DILBM3D27_STASH : L;
+
 // One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
 template <int MODE, int TX, int L>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
-                                      const int64_t t, float (*red)[6][64],
+                                      const int64_t t, float (*red)[6][64], float *stash,
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
                                       double *__restrict__ out_uy,
                                       double *__restrict__ out_uz) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int nx = d.nx, ny = d.ny, nz = d.nz;
-  const int64_t trow = lt / d.tiles_x;
-  const int txi = (int)(lt - trow * d.tiles_x);
-  const int z = (int)(trow / d.tiles_y);
-  const int tyi = (int)(trow - (int64_t)z * d.tiles_y);
+  // the sizes pass through an empty asm: what is derived from them (the divisions'
+  // reciprocals, float copies for the wall distances) is then formed per tile in scalar
+  // or short-lived registers, not held in vector registers across the tile loop
+  int nx = d.nx, ny = d.ny, nz = d.nz, ntx = d.tiles_x, nty = d.tiles_y;
+  asm volatile("" : "+s"(nx), "+s"(ny), "+s"(nz), "+s"(ntx), "+s"(nty));
+  const int64_t trow = lt / ntx;
+  const int txi = (int)(lt - trow * ntx);
+  const int z = (int)(trow / nty);
+  const int tyi = (int)(trow - (int64_t)z * nty);
   constexpr int TY = 256 / TX;
   const int x0 = txi * TX, y0 = tyi * TY;
   const int x = x0 + tid % TX;
@@ -238,6 +249,14 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const bool wz = (d.wall_mask & 4u) && (z < d.wall_lo[2] || z + 1 > d.wall_hi[2]);
   const bool any_solid = nb > 0 || wx || wy || wz;
   if (any_solid) {
+    // the populations wait in LDS while the spheres are summed, so that their registers
+    // serve the sphere loop (each lane its own slots: no barrier); the empty asm with a
+    // memory clobber keeps the compiler from forwarding the stored values past the loop
+    if (MODE == kStep3) {
+#pragma unroll
+      for (int i = 0; i < kStash3<L>; ++i) stash[i * 256 + tid] = g[i];
+      asm volatile("" ::: "memory");
+    }
     float lw[3] = {-1e30f, -1e30f, -1e30f};
     if (wx) {
       float c = (float)xc + 0.5f;
@@ -405,6 +424,11 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         }
       }
     }
+    if (MODE == kStep3) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < kStash3<L>; ++i) g[i] = stash[i * 256 + tid];
+    }
   }
 
   // ---- corrected velocity, Eq. (17): S rho u = S rho u* + (S/2) P, P = rho (A - Phi u*) --
@@ -475,10 +499,17 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
         (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
     const uint32_t s0r = row[1][1];
+    if (d.store_nt) {
 #pragma unroll
-    for (int i = 0; i < L; ++i)
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
-                                            (uint32_t)i * pb + s0r, 0);
+      for (int i = 0; i < L; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
+                                              (uint32_t)i * pb + s0r, kStoreNT);
+    } else {
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
+                                              (uint32_t)i * pb + s0r, 0);
+    }
   }
 }
 
@@ -486,12 +517,13 @@ template <int TX, int L>
 __global__ __launch_bounds__(256, (L == 19 ? DILBM3D_COLLIDE_WAVES : DILBM3D27_COLLIDE_WAVES))
 void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
+  __shared__ float stash[kStash3<L> * 256];  // populations of the block's lanes
   const Desc3 &d = *desc;
   if (TX == 256) {
     // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
     // XCDs at once
     for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-      tile3<kStep3, TX, L>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
+      tile3<kStep3, TX, L>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
     return;
   }
   const WorkSplit ws = xcd_split(d.ntiles);
@@ -500,7 +532,7 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX, L>(d, t, p, step, red, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX, L>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
@@ -512,7 +544,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX, L>(d, t, p, step, nullptr, rho, ux, uy, uz);
+    tile3<kFields3, TX, L>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
 }
 
 // One block per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of

@@ -21,8 +21,8 @@ EXPORTED = [
     "dilbm3d_params_init", "dilbm3d_create", "dilbm3d_set_particles",
     "dilbm3d_set_populations", "dilbm3d_get_populations", "dilbm3d_step",
     "dilbm3d_get_fields", "dilbm3d_get_particle_forces", "dilbm3d_get_particles",
-    "dilbm3d_get_wall_force", "dilbm3d_set_kernel_timing", "dilbm3d_get_kernel_timing",
-    "dilbm3d_get_kernel_launch_times", "dilbm3d_destroy", "dilbm3d_last_error",
+    "dilbm3d_get_wall_force", "dilbm3d_get_step_count", "dilbm3d_set_kernel_timing",
+    "dilbm3d_get_kernel_timing", "dilbm3d_get_kernel_launch_times", "dilbm3d_destroy", "dilbm3d_last_error",
 ]
 
 
@@ -66,6 +66,7 @@ def load():
         "dilbm3d_get_particle_forces": (I32, [V, _dp, _dp]),
         "dilbm3d_get_particles": (I32, [V, _dp, _dp, _dp]),
         "dilbm3d_get_wall_force": (I32, [V, _dp]),
+        "dilbm3d_get_step_count": (I32, [V, C.POINTER(I64)]),
         "dilbm3d_set_kernel_timing": (I32, [V, I32]),
         "dilbm3d_get_kernel_timing": (I32, [V, C.POINTER(D), C.POINTER(I64)]),
         "dilbm3d_get_kernel_launch_times": (I32, [V, _dp, I64, C.POINTER(I64)]),
@@ -238,6 +239,11 @@ class Solver3D:
         self._check(load().dilbm3d_get_particles(self._h, _ptr(x), _ptr(u), _ptr(w)),
                     "dilbm3d_get_particles")
         return x[: self.nb], u[: self.nb], w[: self.nb]
+
+    def step_count(self) -> int:
+        v = C.c_int64(0)
+        self._check(load().dilbm3d_get_step_count(self._h, C.byref(v)), "dilbm3d_get_step_count")
+        return v.value
 
     def get_wall_force(self):
         f = np.zeros(3)

@@ -326,3 +326,17 @@ def test_populations_round_trip_mid_run():
     assert np.array_equal(a.get_populations(), b.get_populations())
     a.close()
     b.close()
+
+
+def test_failure_stops_a_long_call_within_two_chunks():
+    """Uniform acceleration G = 1e-3 drives |u| past 0.5 at step 500: a call of 4000 steps
+    stops within two 32-step chunks of the failure and returns the error."""
+    wl = inputs3d.Workload3D(name="blowup", nx=48, ny=16, nz=12, tau=0.8, nsteps=1,
+                             G=(1e-3, 0.0, 0.0))
+    log_case("3d blow-up in a long call")
+    g = gpu3(wl)
+    assert g.step_status(4000) == dilbm.EUNSTABLE
+    n = g.step_count()
+    assert 500 < n <= 501 + 2 * 32, n
+    assert g.step_status(1) == dilbm.ESTATE
+    g.close()

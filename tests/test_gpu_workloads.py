@@ -313,6 +313,19 @@ def test_blow_up_is_reported_and_poisons_handle():
     g.close()
 
 
+def test_failure_stops_a_long_call_within_two_chunks():
+    """Uniform acceleration G = 1e-3 drives |u| past 0.5 at step 500: a call of 4000 steps
+    (32-step graph chunks) stops within two chunks of the failure and returns the error."""
+    wl = inputs.Workload(name="blowup", nx=64, ny=48, tau=0.8, nsteps=1, G=(1e-3, 0.0))
+    log_case("blow-up in a long call")
+    g = gpu_solver(wl)
+    assert g.step_status(4000) == dilbm.EUNSTABLE
+    n = g.step_count()
+    assert 500 < n <= 501 + 2 * 32, n
+    assert g.step_status(1) == dilbm.ESTATE
+    g.close()
+
+
 def test_set_particles_between_steps_and_empty_body_set():
     wl, f0 = inputs.cylinder_channel(), None
     log_case("set_particles between steps")
