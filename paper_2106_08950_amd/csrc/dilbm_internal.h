@@ -122,6 +122,11 @@ struct SolveDesc {
   float rho0;
   float rho36;                 // 36 rho0
   float Gx, Gy;
+  // per-solve constants of the collision (uniform; formed on the host so the kernels take
+  // them as scalar operands): 9 c.G and 3 c.G for the direction pairs (1,3), (2,4),
+  // (5,7), (6,8), and khalf K for K = 4 and 16
+  float g9[4], g3[4];
+  float khk4, khk16;
   float phi_k;                 // 4 / eps * log2(e): phi = 1 / (1 + 2^(-l * phi_k))
   float lcut;                  // -cutoff * eps
   float wall_h;

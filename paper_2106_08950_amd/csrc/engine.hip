@@ -307,6 +307,16 @@ void fill_desc(Solve &s) {
   d.rho36 = (float)(36.0 * p.rho0);
   d.Gx = (float)p.body_force[0];
   d.Gy = (float)p.body_force[1];
+  {
+    // in FP32 arithmetic: the values the kernels' own expressions in d.Gx, d.Gy would take
+    const float cg[4] = {d.Gx, d.Gy, d.Gx + d.Gy, d.Gy - d.Gx};
+    for (int k = 0; k < 4; ++k) {
+      d.g9[k] = 9.0f * cg[k];
+      d.g3[k] = 3.0f * cg[k];
+    }
+    d.khk4 = d.khalf * 4.0f;
+    d.khk16 = d.khalf * 16.0f;
+  }
   d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
   d.lcut = (float)(-p.phi_cutoff * p.interface_width);
   d.wall_h = (float)p.wall_half_thickness;

@@ -48,6 +48,7 @@ struct StoreF32 {
   static constexpr bool kFrame = true;  // stored in the moving frame of ref_velocity
   static constexpr int kRefLog2 = -17;  // |V_t| < 2^-17
   static constexpr bool kStochastic = false;
+  static constexpr bool kScaled = false;  // stored values are g_i itself
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                               uint32_t soff, float) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
@@ -89,6 +90,9 @@ struct StoreF16 {
   static constexpr bool kFrame = false;
   static constexpr int kRefLog2 = 0;
   static constexpr bool kStochastic = true;
+  // the collide kernel works on the stored scale g_i 2^k directly (no multiply by 2^-k
+  // after each load or by 2^k before each store)
+  static constexpr bool kScaled = true;
   // v * scale rounded stochastically to FP16.  The gfx950 conversion v_cvt_sr_f16_f32 adds
   // the top 13 bits of its random operand to the 13 FP32 mantissa bits that FP16 drops,
   // then truncates (normal range), so with 13 uniform random bits the stored value rounds
@@ -245,9 +249,13 @@ struct NodeState {
 //   geq_i = K_i [drho + 3 c.(rho u - V) + rho (4.5 (c.u)^2 - 1.5 u^2)]   (frame V),
 //   S_i   = 3 (c - u).G + 9 (c.u)(c.G)                          (body-force forcing)
 //         + 3 c.P + 4.5 c.Q.c - 1.5 tr Q   when the tile has solid (Eq. (15) summed).
-template <bool SOLID>
+template <bool SOLID, bool SCALED = false>
 __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], const NodeState &n,
-                                             float Gx, float Gy, float om, float kh) {
+                                             const SolveDesc &d, float inv = 1.0f,
+                                             float scale = 1.0f) {
+  // SCALED: f and out are at the storage scale (g_i 2^k, as FP16 stores them); the update
+  // is formed in g units and applied at that scale (inv = 2^-k, scale = 2^k, both exact)
+  const float Gx = d.Gx, Gy = d.Gy, om = d.omega;
   const float usq = n.ux * n.ux + n.uy * n.uy;
   const float even0 = fmaf(-1.5f * n.rho, usq, n.drho);
   const float r45 = 4.5f * n.rho;
@@ -255,26 +263,34 @@ __device__ __forceinline__ void collide_node(const float f[kQ], float out[kQ], c
   if (SOLID) se0 = fmaf(-1.5f, n.Qxx + n.Qyy, se0);
   // each output is f + (small update): the update's own roundings are tiny, and the one
   // rounding at the scale of f sees an addend that changes from step to step
-  out[0] = f[0] + fmaf(om, 16.0f * even0 - f[0], (kh * 16.0f) * se0);
-  auto pair = [&](int i, int j, float K, float cu, float cm, float cG, float cP, float cQc) {
+  if (SCALED)
+    out[0] = fmaf(scale, fmaf(om, fmaf(-inv, f[0], 16.0f * even0), d.khk16 * se0), f[0]);
+  else
+    out[0] = f[0] + fmaf(om, 16.0f * even0 - f[0], d.khk16 * se0);
+  auto pair = [&](int i, int j, float K, float khK, float g9, float g3, float cu, float cm,
+                  float cP, float cQc) {
     const float E = fmaf(r45, cu * cu, even0);
     const float O = 3.0f * cm;
-    float Se = fmaf(9.0f * cG, cu, se0);
-    float So = 3.0f * cG;
+    float Se = fmaf(g9, cu, se0);
+    float So = g3;
     if (SOLID) {
       Se = fmaf(4.5f, cQc, Se);
       So = fmaf(3.0f, cP, So);
     }
-    const float khK = kh * K;
-    out[i] = f[i] + fmaf(om, K * (E + O) - f[i], khK * (Se + So));
-    out[j] = f[j] + fmaf(om, K * (E - O) - f[j], khK * (Se - So));
+    if (SCALED) {
+      out[i] = fmaf(scale, fmaf(om, fmaf(-inv, f[i], K * (E + O)), khK * (Se + So)), f[i]);
+      out[j] = fmaf(scale, fmaf(om, fmaf(-inv, f[j], K * (E - O)), khK * (Se - So)), f[j]);
+    } else {
+      out[i] = f[i] + fmaf(om, K * (E + O) - f[i], khK * (Se + So));
+      out[j] = f[j] + fmaf(om, K * (E - O) - f[j], khK * (Se - So));
+    }
   };
   // (1,0)/(-1,0), (0,1)/(0,-1), (1,1)/(-1,-1), (-1,1)/(1,-1)
-  pair(1, 3, 4.0f, n.ux, n.momx, Gx, n.Px, n.Qxx);
-  pair(2, 4, 4.0f, n.uy, n.momy, Gy, n.Py, n.Qyy);
-  pair(5, 7, 1.0f, n.ux + n.uy, n.momx + n.momy, Gx + Gy, n.Px + n.Py,
+  pair(1, 3, 4.0f, d.khk4, d.g9[0], d.g3[0], n.ux, n.momx, n.Px, n.Qxx);
+  pair(2, 4, 4.0f, d.khk4, d.g9[1], d.g3[1], n.uy, n.momy, n.Py, n.Qyy);
+  pair(5, 7, 1.0f, d.khalf, d.g9[2], d.g3[2], n.ux + n.uy, n.momx + n.momy, n.Px + n.Py,
        n.Qxx + 2.0f * n.Qxy + n.Qyy);
-  pair(6, 8, 1.0f, n.uy - n.ux, n.momy - n.momx, Gy - Gx, n.Py - n.Px,
+  pair(6, 8, 1.0f, d.khalf, d.g9[3], d.g3[3], n.uy - n.ux, n.momy - n.momx, n.Py - n.Px,
        n.Qxx - 2.0f * n.Qxy + n.Qyy);
 }
 
@@ -405,6 +421,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   const int ym = (yc == 0) ? ny - 1 : yc - 1;
   const int yp = (yc + 1 == ny) ? 0 : yc + 1;
   const float inv = d.store_inv;
+  const float sc = d.store_scale;
+  // scaled storage: f holds the stored values g_i 2^k (the loads skip the multiply)
+  const float ld_inv = ST::kScaled ? 1.0f : inv;
   float f[kQ];
   // byte offsets inside a plane: 32-bit unless the plane reaches 2 GB
   uint32_t o_r0 = 0, o_rm = 0, o_rp = 0, o_x0 = 0, o_xm = 0, o_xp = 0;
@@ -426,48 +445,48 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     const uint32_t s0 = __builtin_amdgcn_readfirstlane(o_r0);
     const uint32_t sm = __builtin_amdgcn_readfirstlane(o_rm);
     const uint32_t sp = __builtin_amdgcn_readfirstlane(o_rp);
-    f[0] = ST::ldb(rs, o_x0, 0 * pb + s0, inv);
-    f[1] = ST::ldb(rs, o_xm, 1 * pb + s0, inv);
-    f[2] = ST::ldb(rs, o_x0, 2 * pb + sm, inv);
-    f[3] = ST::ldb(rs, o_xp, 3 * pb + s0, inv);
-    f[4] = ST::ldb(rs, o_x0, 4 * pb + sp, inv);
-    f[5] = ST::ldb(rs, o_xm, 5 * pb + sm, inv);
-    f[6] = ST::ldb(rs, o_xp, 6 * pb + sm, inv);
-    f[7] = ST::ldb(rs, o_xp, 7 * pb + sp, inv);
-    f[8] = ST::ldb(rs, o_xm, 8 * pb + sp, inv);
+    f[0] = ST::ldb(rs, o_x0, 0 * pb + s0, ld_inv);
+    f[1] = ST::ldb(rs, o_xm, 1 * pb + s0, ld_inv);
+    f[2] = ST::ldb(rs, o_x0, 2 * pb + sm, ld_inv);
+    f[3] = ST::ldb(rs, o_xp, 3 * pb + s0, ld_inv);
+    f[4] = ST::ldb(rs, o_x0, 4 * pb + sp, ld_inv);
+    f[5] = ST::ldb(rs, o_xm, 5 * pb + sm, ld_inv);
+    f[6] = ST::ldb(rs, o_xp, 6 * pb + sm, ld_inv);
+    f[7] = ST::ldb(rs, o_xp, 7 * pb + sp, ld_inv);
+    f[8] = ST::ldb(rs, o_xm, 8 * pb + sp, ld_inv);
   } else if (AM == kAddrBuf) {
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)(kQ * pb), kBufferFlags);
-    f[0] = ST::ldb(rs, o_r0 + o_x0, 0 * pb, inv);
-    f[1] = ST::ldb(rs, o_r0 + o_xm, 1 * pb, inv);
-    f[2] = ST::ldb(rs, o_rm + o_x0, 2 * pb, inv);
-    f[3] = ST::ldb(rs, o_r0 + o_xp, 3 * pb, inv);
-    f[4] = ST::ldb(rs, o_rp + o_x0, 4 * pb, inv);
-    f[5] = ST::ldb(rs, o_rm + o_xm, 5 * pb, inv);
-    f[6] = ST::ldb(rs, o_rm + o_xp, 6 * pb, inv);
-    f[7] = ST::ldb(rs, o_rp + o_xp, 7 * pb, inv);
-    f[8] = ST::ldb(rs, o_rp + o_xm, 8 * pb, inv);
+    f[0] = ST::ldb(rs, o_r0 + o_x0, 0 * pb, ld_inv);
+    f[1] = ST::ldb(rs, o_r0 + o_xm, 1 * pb, ld_inv);
+    f[2] = ST::ldb(rs, o_rm + o_x0, 2 * pb, ld_inv);
+    f[3] = ST::ldb(rs, o_r0 + o_xp, 3 * pb, ld_inv);
+    f[4] = ST::ldb(rs, o_rp + o_x0, 4 * pb, ld_inv);
+    f[5] = ST::ldb(rs, o_rm + o_xm, 5 * pb, ld_inv);
+    f[6] = ST::ldb(rs, o_rm + o_xp, 6 * pb, ld_inv);
+    f[7] = ST::ldb(rs, o_rp + o_xp, 7 * pb, ld_inv);
+    f[8] = ST::ldb(rs, o_rp + o_xm, 8 * pb, ld_inv);
   } else if (AM == kAddrG32) {
-    f[0] = ST::ldo(src + 0 * plane, o_r0 + o_x0, inv);
-    f[1] = ST::ldo(src + 1 * plane, o_r0 + o_xm, inv);
-    f[2] = ST::ldo(src + 2 * plane, o_rm + o_x0, inv);
-    f[3] = ST::ldo(src + 3 * plane, o_r0 + o_xp, inv);
-    f[4] = ST::ldo(src + 4 * plane, o_rp + o_x0, inv);
-    f[5] = ST::ldo(src + 5 * plane, o_rm + o_xm, inv);
-    f[6] = ST::ldo(src + 6 * plane, o_rm + o_xp, inv);
-    f[7] = ST::ldo(src + 7 * plane, o_rp + o_xp, inv);
-    f[8] = ST::ldo(src + 8 * plane, o_rp + o_xm, inv);
+    f[0] = ST::ldo(src + 0 * plane, o_r0 + o_x0, ld_inv);
+    f[1] = ST::ldo(src + 1 * plane, o_r0 + o_xm, ld_inv);
+    f[2] = ST::ldo(src + 2 * plane, o_rm + o_x0, ld_inv);
+    f[3] = ST::ldo(src + 3 * plane, o_r0 + o_xp, ld_inv);
+    f[4] = ST::ldo(src + 4 * plane, o_rp + o_x0, ld_inv);
+    f[5] = ST::ldo(src + 5 * plane, o_rm + o_xm, ld_inv);
+    f[6] = ST::ldo(src + 6 * plane, o_rm + o_xp, ld_inv);
+    f[7] = ST::ldo(src + 7 * plane, o_rp + o_xp, ld_inv);
+    f[8] = ST::ldo(src + 8 * plane, o_rp + o_xm, ld_inv);
   } else {
     const int64_t r0 = (int64_t)yc * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
-    f[0] = ST::ld(src, 0 * plane + r0 + xc, inv);
-    f[1] = ST::ld(src, 1 * plane + r0 + xm, inv);
-    f[2] = ST::ld(src, 2 * plane + rm + xc, inv);
-    f[3] = ST::ld(src, 3 * plane + r0 + xp, inv);
-    f[4] = ST::ld(src, 4 * plane + rp + xc, inv);
-    f[5] = ST::ld(src, 5 * plane + rm + xm, inv);
-    f[6] = ST::ld(src, 6 * plane + rm + xp, inv);
-    f[7] = ST::ld(src, 7 * plane + rp + xp, inv);
-    f[8] = ST::ld(src, 8 * plane + rp + xm, inv);
+    f[0] = ST::ld(src, 0 * plane + r0 + xc, ld_inv);
+    f[1] = ST::ld(src, 1 * plane + r0 + xm, ld_inv);
+    f[2] = ST::ld(src, 2 * plane + rm + xc, ld_inv);
+    f[3] = ST::ld(src, 3 * plane + r0 + xp, ld_inv);
+    f[4] = ST::ld(src, 4 * plane + rp + xc, ld_inv);
+    f[5] = ST::ld(src, 5 * plane + rm + xm, ld_inv);
+    f[6] = ST::ld(src, 6 * plane + rm + xp, ld_inv);
+    f[7] = ST::ld(src, 7 * plane + rp + xp, ld_inv);
+    f[8] = ST::ld(src, 8 * plane + rp + xm, ld_inv);
   }
 
   // the tile's head (body count and first list entry, one scalar load) and that body's
@@ -508,9 +527,14 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 
   // ---- moments, Eqs. (5) and (16); u* carries half the fluid body force ----------------
   // (in g units: D = 36 delta rho, J = 36 j - 36 V, R = 36 rho; the frame carries no mass)
-  const float D = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const float Jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const float Jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  float D = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  float Jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  float Jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  if (ST::kScaled) {  // back to g units (exact: a power of two)
+    D *= inv;
+    Jx *= inv;
+    Jy *= inv;
+  }
   const float R = d.rho36 + D;
   // rho enters only second-order and body terms, drho only the mass term: a constant
   // relative error of 7.5e-9 from fl(1/36) there is harmless
@@ -735,19 +759,24 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   n.Qyy = rho * (Myy - Phi * usy * usy);
   float out[kQ];
   if (any_solid)
-    collide_node<true>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
+    collide_node<true, ST::kScaled>(f, out, n, d, inv, sc);
   else
-    collide_node<false>(f, out, n, d.Gx, d.Gy, d.omega, d.khalf);
+    collide_node<false, ST::kScaled>(f, out, n, d, inv, sc);
   // inlet / outlet nodes replace the result (after the collision: no registers held
   // across it for the few boundary lanes)
   float rho_r = rho, uxr = ux, uyr = uy;
   if constexpr (OPEN) {
-    if (any_bnd && bnd) nee_node<ST>(d, src, plane, x, y, fs, V36x, V36y, out, rho_r, uxr, uyr);
+    if (any_bnd && bnd) {
+      nee_node<ST>(d, src, plane, x, y, fs, V36x, V36y, out, rho_r, uxr, uyr);
+      if (ST::kScaled) {  // to the stored scale
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) out[i] *= sc;
+      }
+    }
   }
   const float usq = uxr * uxr + uyr * uyr;
   if (__ballot(valid && !(rho_r > 0.0f && usq <= 0.25f)) != 0 && lane == 0)
     atomicOr(d.err, (int32_t)kErrUnstable);
-  const float sc = d.store_scale;
   uint16_t hb[kQ];  // FP16: the stochastically rounded halves
   if constexpr (ST::kStochastic) {
     // 13 random bits per population: five 32-bit words, one hash of (node, step) and four
@@ -758,7 +787,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
 #pragma unroll
     for (int r = 1; r < 5; ++r) hh[r] = xorshift32(hh[r - 1]);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) hb[i] = ST::round_bits(out[i], sc, hh[i >> 1], i & 1);
+    for (int i = 0; i < kQ; ++i)
+      hb[i] = ST::round_bits(out[i], ST::kScaled ? 1.0f : sc, hh[i >> 1], i & 1);
   }
   // non-temporal stores or not, per solve (the engine's choice); the branch is uniform
   auto put_all = [&](auto nt) {
@@ -1140,9 +1170,9 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
     n.Qxy = rho[k] * (Mxy[k] - Phi[k] * usx[k] * usy[k]);
     n.Qyy = rho[k] * (Myy[k] - Phi[k] * usy[k] * usy[k]);
     if (any_solid)
-      collide_node<true>(f[k], out[k], n, d.Gx, d.Gy, d.omega, d.khalf);
+      collide_node<true>(f[k], out[k], n, d);
     else
-      collide_node<false>(f[k], out[k], n, d.Gx, d.Gy, d.omega, d.khalf);
+      collide_node<false>(f[k], out[k], n, d);
     float rho_r = rho[k], uxr = n.ux, uyr = n.uy;
     if constexpr (OPEN) {
       if (any_bnd && bnd[k])
