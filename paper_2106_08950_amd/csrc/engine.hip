@@ -150,8 +150,10 @@ void validate(const dilbm_params *p) {
   if (!p) fail(DILBM_EINVAL, "params is NULL");
   if (p->abi_version != DILBM_ABI_VERSION) fail(DILBM_EABI, "abi_version mismatch");
   if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536 ||
-      (int64_t)p->nx * p->ny >= (int64_t)1 << 31)
-    fail(DILBM_EINVAL, "nx, ny must be in [1, 65536] with nx*ny < 2^31");
+      (int64_t)row_pitch(p->nx, p->storage) * p->ny >= (int64_t)1 << 31)
+    fail(DILBM_EINVAL,
+         "nx, ny must be in [1, 65536] with nx*ny < 2^31 (nx rounded up to a multiple of 32, "
+         "64 for FP16)");
   auto fin = [](double v) { return std::isfinite(v); };
   if (!(p->tau > 0.5) || !fin(p->tau)) fail(DILBM_EINVAL, "tau must be > 0.5");
   if (!(p->rho0 > 0.0) || !fin(p->rho0)) fail(DILBM_EINVAL, "rho0 must be > 0");
@@ -261,9 +263,13 @@ int default_shape(const dilbm_params &p) {
   return (p.storage == DILBM_STORE_FP32 && p.nx >= 1024) ? 2 : 0;
 }
 
-uint64_t pop_bytes(const dilbm_params &p) {
-  return align_up(2ull * kQ * (uint64_t)p.nx * p.ny * (p.storage == DILBM_STORE_FP16 ? 2 : 4));
+// one population buffer: nine planes of ny rows of row_pitch values
+uint64_t pop_half_bytes(const dilbm_params &p) {
+  return (uint64_t)kQ * row_pitch(p.nx, p.storage) * p.ny *
+         (p.storage == DILBM_STORE_FP16 ? 2 : 4);
 }
+
+uint64_t pop_bytes(const dilbm_params &p) { return align_up(2ull * pop_half_bytes(p)); }
 
 // ---------------------------------------------------------------------------------------
 
@@ -294,6 +300,7 @@ void fill_desc(Solve &s) {
   SolveDesc &d = s.desc;
   d.nx = p.nx;
   d.ny = p.ny;
+  d.pitch = row_pitch(p.nx, p.storage);
   d.tx = kTileTX[s.shape];
   d.ty = kTileTY[s.shape];
   d.tiles_x = (p.nx + d.tx - 1) / d.tx;
@@ -361,7 +368,7 @@ void fill_desc(Solve &s) {
   d.xi = p.coll_xi;
   d.wall_h_d = p.wall_half_thickness;
   d.support = p.phi_cutoff * p.interface_width;
-  const uint64_t half = (uint64_t)kQ * p.nx * p.ny * (p.storage == DILBM_STORE_FP16 ? 2 : 4);
+  const uint64_t half = pop_half_bytes(p);
   char *pp = (char *)s.pops.ptr;
   d.pop[0] = pp;
   d.pop[1] = pp + half;
@@ -769,8 +776,7 @@ class Engine {
     // stays under 2 GB, 32-bit plane offsets while a plane stays under 2 GB, else 64-bit
     int addr = 0;
     for (Solve *s : members_) {
-      const uint64_t pb = (uint64_t)s->prm.nx * s->prm.ny *
-                          (s->prm.storage == DILBM_STORE_FP16 ? 2 : 4);
+      const uint64_t pb = pop_half_bytes(s->prm) / kQ;
       const int a = kQ * pb < (1ull << 31) ? 0 : (pb < (1ull << 31) ? 1 : 2);
       addr = std::max(addr, a);
     }
@@ -778,14 +784,11 @@ class Engine {
       addr_ = addr;
       clear_graphs();
     }
-    // non-temporal population stores for members whose rows start on 128-byte lines, once
-    // the members' populations together exceed the last-level cache
+    // non-temporal population stores once the members' populations together exceed the
+    // last-level cache (rows start on 128-byte lines: row_pitch)
     uint64_t total_pop = 0;
     for (Solve *s : members_) total_pop += pop_bytes(s->prm);
-    for (Solve *s : members_) {
-      const uint64_t row = (uint64_t)s->prm.nx * (s->prm.storage == DILBM_STORE_FP16 ? 2 : 4);
-      s->desc.store_nt = (total_pop > kStoreNtMinBytes && row % 128 == 0) ? 1 : 0;
-    }
+    for (Solve *s : members_) s->desc.store_nt = total_pop > kStoreNtMinBytes ? 1 : 0;
     bool open = false;
     for (Solve *s : members_) open = open || s->prm.x_boundary != DILBM_XBC_PERIODIC;
     if (open != open_) {

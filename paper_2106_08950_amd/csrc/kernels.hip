@@ -344,7 +344,7 @@ __device__ void nee_node(const SolveDesc &d, const typename ST::T *src, int64_t 
   for (int i = 0; i < kQ; ++i) {
     int ys = y - CY[i];
     ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-    g[i] = ST::ld(src, i * plane + (int64_t)ys * nx + (xn - CX[i]), d.store_inv);
+    g[i] = ST::ld(src, i * plane + (int64_t)ys * d.pitch + (xn - CX[i]), d.store_inv);
   }
   fs.apply(g);
   const float D = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
@@ -415,7 +415,8 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   using T = typename ST::T;
   const T *__restrict__ src = (const T *)d.pop[p];
   T *__restrict__ dst = (T *)d.pop[p ^ 1];
-  const int64_t plane = (int64_t)nx * ny;
+  const int pitch = d.pitch;  // row stride of the planes (rows start on 128-byte lines)
+  const int64_t plane = (int64_t)pitch * ny;
   const int xm = (xc == 0) ? nx - 1 : xc - 1;
   const int xp = (xc + 1 == nx) ? 0 : xc + 1;
   const int ym = (yc == 0) ? ny - 1 : yc - 1;
@@ -429,9 +430,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   uint32_t o_r0 = 0, o_rm = 0, o_rp = 0, o_x0 = 0, o_xm = 0, o_xp = 0;
   constexpr uint32_t es = sizeof(T);
   if (AM != kAddrWide) {
-    o_r0 = (uint32_t)(yc * nx) * es;
-    o_rm = (uint32_t)(ym * nx) * es;
-    o_rp = (uint32_t)(yp * nx) * es;
+    o_r0 = (uint32_t)(yc * pitch) * es;
+    o_rm = (uint32_t)(ym * pitch) * es;
+    o_rp = (uint32_t)(yp * pitch) * es;
     o_x0 = (uint32_t)xc * es;
     o_xm = (uint32_t)xm * es;
     o_xp = (uint32_t)xp * es;
@@ -477,7 +478,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
     f[7] = ST::ldo(src + 7 * plane, o_rp + o_xp, ld_inv);
     f[8] = ST::ldo(src + 8 * plane, o_rp + o_xm, ld_inv);
   } else {
-    const int64_t r0 = (int64_t)yc * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+    const int64_t r0 = (int64_t)yc * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
     f[0] = ST::ld(src, 0 * plane + r0 + xc, ld_inv);
     f[1] = ST::ld(src, 1 * plane + r0 + xm, ld_inv);
     f[2] = ST::ld(src, 2 * plane + rm + xc, ld_inv);
@@ -825,7 +826,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
           ST::template sto<NT>(dst + i * plane, o, out[i], sc);
       }
     } else {
-      const int64_t o = (int64_t)yc * nx + xc;
+      const int64_t o = (int64_t)yc * pitch + xc;
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
         if constexpr (ST::kStochastic)
@@ -898,7 +899,8 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
   const float inv = d.store_inv;
   const uint16_t *__restrict__ src = (const uint16_t *)d.pop[p];
   uint16_t *__restrict__ dst = (uint16_t *)d.pop[p ^ 1];
-  const int64_t plane = (int64_t)nx * ny;
+  const int pitch = d.pitch;  // row stride of the planes (a multiple of 64)
+  const int64_t plane = (int64_t)pitch * ny;
   // elements pulled across x: c_x = +1 from (xc - 1, xc), c_x = -1 from (xc + 1, xc + 2)
   const int em0 = xc == 0 ? nx - 1 : xc - 1, em1 = xc;
   const int ep0 = xc + 1, ep1 = xc + 2 == nx ? 0 : xc + 2;
@@ -909,8 +911,8 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
     const uint32_t pb = (uint32_t)plane * 2u;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)(kQ * pb), kBufferFlags);
-    const uint32_t s0 = (uint32_t)(y * nx) * 2u, sm = (uint32_t)(ym * nx) * 2u,
-                   sp = (uint32_t)(yp * nx) * 2u;
+    const uint32_t s0 = (uint32_t)(y * pitch) * 2u, sm = (uint32_t)(ym * pitch) * 2u,
+                   sp = (uint32_t)(yp * pitch) * 2u;
     w[0] = ld_pair_buf(rs, 0 * pb + s0, xc, xc + 1);
     w[1] = ld_pair_buf(rs, 1 * pb + s0, em0, em1);
     w[2] = ld_pair_buf(rs, 2 * pb + sm, xc, xc + 1);
@@ -921,7 +923,7 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
     w[7] = ld_pair_buf(rs, 7 * pb + sp, ep0, ep1);
     w[8] = ld_pair_buf(rs, 8 * pb + sp, em0, em1);
   } else {
-    const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+    const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
     w[0] = ld_pair_ptr(src + 0 * plane + r0, xc, xc + 1);
     w[1] = ld_pair_ptr(src + 1 * plane + r0, em0, em1);
     w[2] = ld_pair_ptr(src + 2 * plane + rm, xc, xc + 1);
@@ -1207,13 +1209,13 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
       const uint32_t pb = (uint32_t)plane * 2u;
       const __amdgpu_buffer_rsrc_t rd =
           __builtin_amdgcn_make_buffer_rsrc((void *)dst, (short)0, (int)(kQ * pb), kBufferFlags);
-      const uint32_t s0 = (uint32_t)(y * nx) * 2u;
+      const uint32_t s0 = (uint32_t)(y * pitch) * 2u;
 #pragma unroll
       for (int i = 0; i < kQ; ++i)
         __builtin_amdgcn_raw_buffer_store_b32(hw[i], rd, 2u * (uint32_t)xc, i * pb + s0,
                                               NT ? kStoreNT : 0);
     } else {
-      const int64_t o = (int64_t)y * nx + xc;
+      const int64_t o = (int64_t)y * pitch + xc;
 #pragma unroll
       for (int i = 0; i < kQ; ++i) put<NT>(hw[i], (uint32_t *)(dst + i * plane + o));
     }
@@ -1532,7 +1534,8 @@ template <class ST>
 __global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p,
                            const double *__restrict__ fin) {
   const SolveDesc &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny;
+  const int64_t plane = (int64_t)d.nx * d.ny;     // the caller's dense planes
+  const int64_t dplane = (int64_t)d.pitch * d.ny;  // the stored planes
   const float2 V = frame_velocity<ST>(d.step0);
   typename ST::T *dst = (typename ST::T *)d.pop[p];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
@@ -1545,15 +1548,16 @@ __global__ void k_set_pops(const SolveDesc *__restrict__ desc, int p,
     if (xs >= d.nx) xs -= d.nx;
     if (ys < 0) ys += d.ny;
     if (ys >= d.ny) ys -= d.ny;
-    ST::st(dst, i * plane + (int64_t)ys * d.nx + xs, (float)(36.0 * fin[e] - frame_offset(i, V)),
-           d.store_scale);
+    ST::st(dst, i * dplane + (int64_t)ys * d.pitch + xs,
+           (float)(36.0 * fin[e] - frame_offset(i, V)), d.store_scale);
   }
 }
 
 template <class ST>
 __global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__restrict__ fout) {
   const SolveDesc &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny;
+  const int64_t plane = (int64_t)d.nx * d.ny;     // the caller's dense planes
+  const int64_t dplane = (int64_t)d.pitch * d.ny;  // the stored planes
   const float2 V = frame_velocity<ST>(d.step0);
   const typename ST::T *src = (const typename ST::T *)d.pop[p];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
@@ -1566,7 +1570,7 @@ __global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__
     if (xs >= d.nx) xs -= d.nx;
     if (ys < 0) ys += d.ny;
     if (ys >= d.ny) ys -= d.ny;
-    const double g = (double)ST::ld(src, i * plane + (int64_t)ys * d.nx + xs, d.store_inv);
+    const double g = (double)ST::ld(src, i * dplane + (int64_t)ys * d.pitch + xs, d.store_inv);
     fout[e] = (g + frame_offset(i, V)) / 36.0;
   }
 }
@@ -1576,7 +1580,7 @@ __global__ void k_get_pops(const SolveDesc *__restrict__ desc, int p, double *__
 template <class ST>
 __global__ void k_rest_pops(const SolveDesc *__restrict__ desc) {
   const SolveDesc &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny;
+  const int64_t plane = (int64_t)d.pitch * d.ny;  // padding columns included
   const float2 V = frame_velocity<ST>(d.step0);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kQ * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
