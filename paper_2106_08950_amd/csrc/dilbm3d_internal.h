@@ -34,6 +34,9 @@ constexpr int kQ3Max = 27;   // D3Q27
 #endif
 constexpr int kMaxListCap3 = 1024;
 
+// Row pitch of the population planes (populations per row).
+inline int32_t row_pitch3(int32_t nx) { return (nx + 31) / 32 * 32; }
+
 // A multi-step call checks the sticky error flags every this many steps.
 constexpr int64_t kPollSteps3 = 32;
 
@@ -69,6 +72,8 @@ struct SphereSnap {
 
 struct Desc3 {
   int32_t nx, ny, nz;
+  int32_t pitch;      // row stride of the population planes: nx rounded up to 32 (whole
+                      // 128-byte lines, as in the 2-D planes); padding is never touched
   int32_t tile_x;     // 64 or 256
   int32_t tiles_x, tiles_y;
   int64_t ntiles;

@@ -73,9 +73,9 @@ void validate3(const dilbm3d_params *p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) fail3(DILBM_EINVAL, "nx, ny, nz must be >= 1");
   if (p->lattice != 0 && p->lattice != 19 && p->lattice != 27)
     fail3(DILBM_EINVAL, "lattice must be 19 (D3Q19) or 27 (D3Q27)");
-  const uint64_t nodes = (uint64_t)p->nx * p->ny * p->nz;
-  if (nodes * (uint64_t)q_of(*p) * 4ull >= (1ull << 32) - 256)
-    fail3(DILBM_EINVAL, "q * 4 bytes * nx * ny * nz must stay under 4 GB");
+  const uint64_t cells = (uint64_t)row_pitch3(p->nx) * p->ny * p->nz;
+  if (cells * (uint64_t)q_of(*p) * 4ull >= (1ull << 32) - 256)
+    fail3(DILBM_EINVAL, "q * 4 bytes * nx * ny * nz (nx rounded up to 32) must stay under 4 GB");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) fail3(DILBM_EINVAL, "tau must be > 0.5");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) fail3(DILBM_EINVAL, "rho0 must be > 0");
   if (!(p->interface_width > 0.0) || !std::isfinite(p->interface_width))
@@ -212,6 +212,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.nx = p.nx;
   d.ny = p.ny;
   d.nz = p.nz;
+  d.pitch = row_pitch3(p.nx);
   d.tile_x = s.tile_x;
   d.tiles_x = (p.nx + d.tile_x - 1) / d.tile_x;
   d.tiles_y = (p.ny + 256 / d.tile_x - 1) / (256 / d.tile_x);
@@ -229,10 +230,9 @@ void fill_desc3(dilbm3d_solver &s) {
   d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);
   d.wall_h = (float)p.wall_half_thickness;
   d.wall_mask = p.wall_mask;
-  // non-temporal population stores once the populations exceed the last-level cache, when
-  // rows start on 128-byte lines
-  const uint64_t pops = 2ull * q_of(p) * 4ull * (uint64_t)p.nx * p.ny * p.nz;
-  d.store_nt = (pops > kStoreNtMinBytes3 && p.nx % 32 == 0) ? 1 : 0;
+  // non-temporal population stores once the populations exceed the last-level cache
+  const uint64_t pops = 2ull * q_of(p) * 4ull * (uint64_t)row_pitch3(p.nx) * p.ny * p.nz;
+  d.store_nt = pops > kStoreNtMinBytes3 ? 1 : 0;
   const int n3[3] = {p.nx, p.ny, p.nz};
   const double reach = p.wall_half_thickness + p.phi_cutoff * p.interface_width;
   for (int a = 0; a < 3; ++a) {
@@ -253,7 +253,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.xi = p.coll_xi;
   d.wall_h_d = p.wall_half_thickness;
   d.support = p.phi_cutoff * p.interface_width;
-  const uint64_t half = (uint64_t)q_of(p) * p.nx * p.ny * p.nz * 4;
+  const uint64_t half = (uint64_t)q_of(p) * row_pitch3(p.nx) * p.ny * p.nz * 4;
   d.pop[0] = (float *)s.pops.ptr;
   d.pop[1] = (float *)((char *)s.pops.ptr + half);
   char *bb = (char *)s.body.ptr;
@@ -375,7 +375,7 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
       HIPCHK3(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
       s.own_stream = true;
     }
-    const uint64_t half = (uint64_t)q_of(*p) * p->nx * p->ny * p->nz * 4;
+    const uint64_t half = (uint64_t)q_of(*p) * row_pitch3(p->nx) * p->ny * p->nz * 4;
     s.pops = alloc3(2 * half);
     HIPCHK3(hipMalloc(&s.d_desc, sizeof(Desc3)));
     HIPCHK3(hipMalloc(&s.d_err, sizeof(int32_t)));

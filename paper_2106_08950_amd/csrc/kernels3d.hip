@@ -139,8 +139,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // the sizes pass through an empty asm: what is derived from them (the divisions'
   // reciprocals, float copies for the wall distances) is then formed per tile in scalar
   // or short-lived registers, not held in vector registers across the tile loop
-  int nx = d.nx, ny = d.ny, nz = d.nz, ntx = d.tiles_x, nty = d.tiles_y;
-  asm volatile("" : "+s"(nx), "+s"(ny), "+s"(nz), "+s"(ntx), "+s"(nty));
+  int nx = d.nx, ny = d.ny, nz = d.nz, ntx = d.tiles_x, nty = d.tiles_y, pitch = d.pitch;
+  asm volatile("" : "+s"(nx), "+s"(ny), "+s"(nz), "+s"(ntx), "+s"(nty), "+s"(pitch));
   const int64_t trow = lt / ntx;
   const int txi = (int)(lt - trow * ntx);
   const int z = (int)(trow / nty);
@@ -155,7 +155,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) ------------------------------
   // one buffer resource per population buffer; the row of every direction is
   // wave-uniform (scalar offset), the column is one of three per-lane offsets
-  const uint32_t plane = (uint32_t)nx * (uint32_t)ny * (uint32_t)nz;
+  const uint32_t plane = (uint32_t)pitch * (uint32_t)ny * (uint32_t)nz;
   const uint32_t pb = plane * 4u;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(L * pb), kBufferFlags);
@@ -169,7 +169,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     for (int dy = -1; dy <= 1; ++dy)
       row[dz + 1][dy + 1] = __builtin_amdgcn_readfirstlane(
           ((uint32_t)wrapi(z + dz, nz) * (uint32_t)ny + (uint32_t)wrapi(yc + dy, ny)) *
-          (uint32_t)nx * 4u);
+          (uint32_t)pitch * 4u);
   float g[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -747,7 +747,8 @@ template <int L>
 __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             const double *__restrict__ fin) {
   const Desc3 &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;      // the caller's dense planes
+  const int64_t dplane = (int64_t)d.pitch * d.ny * d.nz;  // the stored planes
   const float3 V = ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -758,7 +759,7 @@ __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] =
+    d.pop[p][i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs] =
         (float)((double)Lat3<L>::S * fin[e] - frame_offset3<L>(i, V));
   }
 }
@@ -767,7 +768,8 @@ template <int L>
 __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             double *__restrict__ fout) {
   const Desc3 &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;      // the caller's dense planes
+  const int64_t dplane = (int64_t)d.pitch * d.ny * d.nz;  // the stored planes
   const float3 V = ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -778,7 +780,7 @@ __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    fout[e] = ((double)d.pop[p][i * plane + ((int64_t)zs * d.ny + ys) * d.nx + xs] +
+    fout[e] = ((double)d.pop[p][i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs] +
                frame_offset3<L>(i, V)) /
               (double)Lat3<L>::S;
   }
@@ -788,7 +790,7 @@ __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
 template <int L>
 __global__ void k3_rest_pops(const Desc3 *__restrict__ desc, int64_t step) {
   const Desc3 &d = *desc;
-  const int64_t plane = (int64_t)d.nx * d.ny * d.nz;
+  const int64_t plane = (int64_t)d.pitch * d.ny * d.nz;  // padding columns included
   const float3 V = ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
