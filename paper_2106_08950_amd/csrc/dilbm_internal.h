@@ -94,6 +94,11 @@ enum ErrBits : int32_t { kErrUnstable = 1, kErrCapacity = 2, kErrInternal = 4 };
 // kNbrCap entries is marked -1: that body sweeps every step until the next rebuild.
 constexpr int kNbrCap = 64;
 constexpr double kNbrSkin = 2.0;
+// Tile lists are built with the reach R + support + kBinSkin and rebuilt only once some
+// body of the solve has moved half that skin since: a body moves well under half of it
+// per step, so until the rebuild every node within R + support of it lies in a listed
+// tile.
+constexpr double kBinSkin = 2.0;
 
 // One body as the collide kernel sees it at a step: position (FP64, so that node - centre
 // differences keep FP64 accuracy before they are rounded), rigid velocity, spin and radius.
@@ -177,6 +182,13 @@ struct SolveDesc {
   int32_t *nbr_list;
   double *nbr_ref;
   int32_t *nl_flag;
+  // tile lists kept across steps: lsel[p] names the list set (0 or 1) the steps of parity
+  // p read; rb_flag[p] asks the body step of parity p to rebin every body (into the other
+  // set, with the reach R + support + kBinSkin); bin_ref holds each body's position when
+  // it was last binned
+  int32_t *lsel;
+  int32_t *rb_flag;
+  double *bin_ref;
 };
 
 // A rectangle of nodes [x, x + w) x [y, y + h) inside one solve.

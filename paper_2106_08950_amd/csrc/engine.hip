@@ -221,7 +221,8 @@ void validate_bodies(int32_t n, const double *pos, const double *vel, const doub
 struct BodyLayout {
   int cap = 1;
   uint64_t heads = 0, lists = 0, bstate = 0, bconst = 0, bsnap = 0, bxy = 0, acc = 0;
-  uint64_t nbr_cnt = 0, nbr_list = 0, nbr_ref = 0, nl_flag = 0, total = 0;
+  uint64_t nbr_cnt = 0, nbr_list = 0, nbr_ref = 0, nl_flag = 0, lsel = 0, rb_flag = 0,
+           bin_ref = 0, total = 0;
 };
 
 BodyLayout body_layout(const dilbm_params &p, int nb) {
@@ -251,6 +252,12 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   o += align_up(2 * 8 * (uint64_t)std::max(nb, 1));
   L.nl_flag = o;
   o += align_up(2 * 4);
+  L.lsel = o;
+  o += align_up(2 * 4);
+  L.rb_flag = o;
+  o += align_up(2 * 4);
+  L.bin_ref = o;
+  o += align_up(2 * 8 * (uint64_t)std::max(nb, 1));
   L.total = o;
   return L;
 }
@@ -392,6 +399,9 @@ void fill_desc(Solve &s) {
   d.nbr_list = (int32_t *)(bb + s.L.nbr_list);
   d.nbr_ref = (double *)(bb + s.L.nbr_ref);
   d.nl_flag = (int32_t *)(bb + s.L.nl_flag);
+  d.lsel = (int32_t *)(bb + s.L.lsel);
+  d.rb_flag = (int32_t *)(bb + s.L.rb_flag);
+  d.bin_ref = (double *)(bb + s.L.bin_ref);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -526,10 +536,14 @@ class Engine {
     return d_one_desc_ + which;
   }
 
-  // Bin the bodies of s's current state into its current-parity lists.
+  // Bin the bodies of s's current state into list set 0, which the next step reads (both
+  // sets emptied, no rebin pending).
   void bin_current(Solve &s, hipStream_t st) {
-    const int p = s.parity();
-    HIPCHK(launch_fill_i32(s.desc.tile_head[p], 2 * max_tiles_for(s.prm.nx, s.prm.ny), 0, st));
+    const int64_t mt = max_tiles_for(s.prm.nx, s.prm.ny);
+    HIPCHK(launch_fill_i32(s.desc.tile_head[0], 2 * mt, 0, st));
+    HIPCHK(launch_fill_i32(s.desc.tile_head[1], 2 * mt, 0, st));
+    HIPCHK(launch_fill_i32(s.desc.lsel, 2, 0, st));
+    HIPCHK(launch_fill_i32(s.desc.rb_flag, 2, 0, st));
     if (s.nb == 0) return;
     SolveDesc *dd = one_desc(s, st, 0);
     if (s.nb > one_bodies_cap_) {

@@ -495,21 +495,27 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
   // is known: it is clamped into range for the snapshot load and used only when the
   // count lists it.  An overflowed list (count > capacity) is flagged by the binning:
   // read only what fits.
-  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * (int64_t)lt);
+  const int ls = *(const DILBM_CONST int32_t *)(d.lsel + p);  // the list set of this step
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[ls] + 2 * (int64_t)lt);
   const int32_t raw0 = (int32_t)(hv >> 32);
   const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
   const int nbs = d.nbodies;
   const DILBM_CONST int32_t *list =
-      (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
+      (const DILBM_CONST int32_t *)(d.tile_list[ls] + (int64_t)lt * d.list_cap);
   const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
   BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
   if (nbs > 0) s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
   if (MODE == kModeStep) {
-    if (tid == 0) d.tile_head[p ^ 1][2 * (int64_t)lt] = 0;  // lists of the next step start empty
+    // the body step after this one rebins into the other set: it starts empty
+    if (tid == 0 && *(const DILBM_CONST int32_t *)(d.rb_flag + p) != 0)
+      d.tile_head[ls ^ 1][2 * (int64_t)lt] = 0;
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
       for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
-      if (tid == 0) d.nl_flag[p ^ 1] = 0;  // read by the last body step, raised by the next
+      if (tid == 0) {  // read by the last body step, raised by the next
+        d.nl_flag[p ^ 1] = 0;
+        d.rb_flag[p ^ 1] = 0;
+      }
     }
   }
 
@@ -936,20 +942,26 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
   }
 
   // the tile's head and its first body's snapshot, in flight with the populations
-  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * (int64_t)lt);
+  const int ls = *(const DILBM_CONST int32_t *)(d.lsel + p);  // the list set of this step
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[ls] + 2 * (int64_t)lt);
   const int32_t raw0 = (int32_t)(hv >> 32);
   const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
   const int nbs = d.nbodies;
   const DILBM_CONST int32_t *list =
-      (const DILBM_CONST int32_t *)(d.tile_list[p] + (int64_t)lt * d.list_cap);
+      (const DILBM_CONST int32_t *)(d.tile_list[ls] + (int64_t)lt * d.list_cap);
   const DILBM_CONST BodySnap *snap = (const DILBM_CONST BodySnap *)d.bsnap[p];
   BodySnap s0{0.0, 0.0, 0.f, 0.f, 0.f, 0.f};
   if (nbs > 0) s0 = load_snap(snap + min(raw0 & kListIndexMask, nbs - 1));
-  if (tid == 0) d.tile_head[p ^ 1][2 * (int64_t)lt] = 0;  // lists of the next step start empty
+  // the body step after this one rebins into the other set: it starts empty
+  if (tid == 0 && *(const DILBM_CONST int32_t *)(d.rb_flag + p) != 0)
+    d.tile_head[ls ^ 1][2 * (int64_t)lt] = 0;
   if (lt == 0) {
     double *a = d.acc[p ^ 1];
     for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
-    if (tid == 0) d.nl_flag[p ^ 1] = 0;  // read by the last body step, raised by the next
+    if (tid == 0) {  // read by the last body step, raised by the next
+      d.nl_flag[p ^ 1] = 0;
+      d.rb_flag[p ^ 1] = 0;
+    }
   }
 
   float f[2][kQ];
@@ -1320,6 +1332,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
     const bool fixed = d.bconst[4 * nb + b] != 0.0;
     int q = p;
     if (BIN_ONLY && b == 0 && lane == 0) d.nl_flag[p] = 1;  // new bodies: build the lists
+    // tile lists: the set this step read, and whether this body step rebuilds them (into
+    // the other set; a fresh binning writes set 0, emptied by the host)
+    const int ls = d.lsel[p];
+    const bool rebin = BIN_ONLY || d.rb_flag[p] != 0;
+    const int lnew = BIN_ONLY ? 0 : (rebin ? ls ^ 1 : ls);
     if (!BIN_ONLY) {
       // hydrodynamic force and torque of the step (read now: in flight with the pair loads)
       const double *acc = d.acc[p];
@@ -1459,6 +1476,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
         const double my = min_image(Y - d.nbr_ref[2 * b + 1], dny);
         if (lane == 0 && !(mx * mx + my * my <= 0.25 * kNbrSkin * kNbrSkin)) d.nl_flag[p ^ 1] = 1;
       }
+      // the same for the tile lists, unless this step rebins (from the new position)
+      if (!rebin) {
+        const double mx = min_image(X - d.bin_ref[2 * b], dnx);
+        const double my = min_image(Y - d.bin_ref[2 * b + 1], dny);
+        if (lane == 0 && !(mx * mx + my * my <= 0.25 * kBinSkin * kBinSkin)) d.rb_flag[p ^ 1] = 1;
+      }
+      if (b == 0 && lane == 0) d.lsel[p ^ 1] = lnew;  // the set the next step reads
       q = p ^ 1;
       if (lane == 0) {
         double *sn = d.bstate[q];
@@ -1479,15 +1503,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_bodies(const SolveDesc *__res
       if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
       continue;
     }
-    // bin into the tile lists of parity q: every tile holding a node within R + support
-    const double H = R + d.support + 1e-3;
+    if (!rebin) continue;  // the lists of the last rebuild still cover this body
+    if (lane == 0) {
+      d.bin_ref[2 * b] = X;
+      d.bin_ref[2 * b + 1] = Y;
+    }
+    // bin into list set lnew: every tile holding a node within R + support + skin
+    const double H = R + d.support + kBinSkin + 1e-3;
     const AxisTiles ax = axis_tiles(X, H, d.nx, d.tx, d.tiles_x);
     const AxisTiles ay = axis_tiles(Y, H, d.ny, d.ty, d.tiles_y);
     const int na = (ax.a1 - ax.a0 + 1) + max(0, ax.b1 - ax.b0 + 1);
     const int nbb = (ay.a1 - ay.a0 + 1) + max(0, ay.b1 - ay.b0 + 1);
     const int na1 = ax.a1 - ax.a0 + 1, nb1 = ay.a1 - ay.a0 + 1;
-    int32_t *hd = d.tile_head[q];
-    int32_t *lst = d.tile_list[q];
+    int32_t *hd = d.tile_head[lnew];
+    int32_t *lst = d.tile_list[lnew];
     for (int e = lane; e < na * nbb; e += 64) {
       const int ia = e % na, ib = e / na;
       const int tx = ia < na1 ? ax.a0 + ia : ax.b0 + (ia - na1);

@@ -75,3 +75,29 @@ def test_list_overflow_falls_back_to_the_full_sweep():
     _, uxg, uyg = g.get_fields()
     assert velocity_rel_l2(uxg, uyg, uxo, uyo) <= 1e-5
     g.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_tile_lists_follow_a_fast_disc(storage):
+    """The tile lists are kept across steps and rebuilt once a body has moved half their
+    skin: a disc driven at a prescribed 0.25 lattice units per step crosses 75 units of the
+    lattice in 300 steps (a rebuild every few steps, each one step after its trigger) past
+    a free disc, against the oracle, which rebuilds the solid field every step."""
+    wl = inputs.Workload(name="fast", nx=160, ny=64, tau=0.8, nsteps=300,
+                         **inputs._bodies([[20.0, 30.0], [90.0, 14.0]], [6.0, 5.0], [1.5, 1.2],
+                                          vel=[[0.25, 0.05], [0.0, 0.0]], fixed=[1, 0]))
+    log_case(f"tile lists follow a fast disc, storage {storage}")
+    o = oracle_solver(wl)
+    g = gpu_solver(wl, storage=storage)
+    o.step(300)
+    g.step(300)
+    xo, uo, _ = o.get_particles()
+    xg, ug, _ = g.get_particles()
+    tol_x, tol_u = (1e-4, 1e-5) if storage == 0 else (1e-2, 2e-3)
+    assert _wrap(xg, xo, [wl.nx, wl.ny]).max() <= tol_x
+    _, uxo, uyo = o.get_fields()
+    _, uxg, uyg = g.get_fields()
+    e = velocity_rel_l2(uxg, uyg, uxo, uyo)
+    print(f"fast disc storage={storage}: u rel L2 {e:.3e}")
+    assert e <= tol_u
+    g.close()
