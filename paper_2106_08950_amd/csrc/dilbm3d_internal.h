@@ -37,6 +37,10 @@ constexpr int kMaxListCap3 = 1024;
 // Row pitch of the population planes (populations per row).
 inline int32_t row_pitch3(int32_t nx) { return (nx + 31) / 32 * 32; }
 
+// Tile lists are built with the reach R + support + kBinSkin3 and rebuilt once some sphere
+// has moved half that skin since its last binning.
+constexpr double kBinSkin3 = 2.0;
+
 // A multi-step call checks the sticky error flags every this many steps.
 constexpr int64_t kPollSteps3 = 32;
 
@@ -106,6 +110,11 @@ struct Desc3 {
   const double *bconst;
   SphereSnap *bsnap[2];
   double *acc[2];
+  // tile lists kept across steps (as in two dimensions): the list set the steps of parity
+  // p read, the per-parity rebin requests, and each sphere's position at its last binning
+  int32_t *lsel;
+  int32_t *rb_flag;
+  double *bin_ref;
   int32_t *err;
 };
 

@@ -133,7 +133,7 @@ struct dilbm3d_solver {
   int tile_x = 64;  // tile width of the current layout (64 or 256)
   Mem3 pops, body;
   uint64_t off_heads = 0, off_lists = 0, off_bstate = 0, off_bconst = 0, off_snap = 0,
-           off_acc = 0;
+           off_acc = 0, off_lsel = 0, off_bref = 0;
   Desc3 h{};
   Desc3 *d_desc = nullptr;
   int32_t *d_err = nullptr;
@@ -186,10 +186,11 @@ void body_layout3(dilbm3d_solver &s, int n) {
   const uint64_t T = (uint64_t)tiles_of(s.prm, s.tile_x);
   const int cap = s.prm.list_capacity > 0 ? s.prm.list_capacity : std::max(1, std::min(n, 128));
   const uint64_t nn = (uint64_t)std::max(n, 1);
-  uint64_t off[6], o = 0;
-  const uint64_t sizes[6] = {2 * T * 8, 2 * T * (uint64_t)cap * 4, 2 * 9 * nn * 8, 5 * nn * 8,
-                             2 * nn * sizeof(SphereSnap), 2 * 6 * (uint64_t)(n + 1) * 8};
-  for (int k = 0; k < 6; ++k) {
+  uint64_t off[8], o = 0;
+  const uint64_t sizes[8] = {2 * T * 8, 2 * T * (uint64_t)cap * 4, 2 * 9 * nn * 8, 5 * nn * 8,
+                             2 * nn * sizeof(SphereSnap), 2 * 6 * (uint64_t)(n + 1) * 8,
+                             4 * 4, 3 * nn * 8};
+  for (int k = 0; k < 8; ++k) {
     off[k] = o;
     o += up3(sizes[k]);
   }
@@ -203,6 +204,8 @@ void body_layout3(dilbm3d_solver &s, int n) {
   s.off_bconst = off[3];
   s.off_snap = off[4];
   s.off_acc = off[5];
+  s.off_lsel = off[6];  // lsel[2], then rb_flag[2]
+  s.off_bref = off[7];
 }
 
 void fill_desc3(dilbm3d_solver &s) {
@@ -268,6 +271,9 @@ void fill_desc3(dilbm3d_solver &s) {
   d.bsnap[0] = (SphereSnap *)(bb + s.off_snap);
   d.bsnap[1] = d.bsnap[0] + nn;
   d.acc[0] = (double *)(bb + s.off_acc);
+  d.lsel = (int32_t *)(bb + s.off_lsel);
+  d.rb_flag = d.lsel + 2;
+  d.bin_ref = (double *)(bb + s.off_bref);
   d.acc[1] = d.acc[0] + 6 * (uint64_t)(s.nb + 1);
   d.err = s.d_err;
 }

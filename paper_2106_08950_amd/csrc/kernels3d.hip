@@ -181,20 +181,24 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // the tile's head (sphere count and first list entry, one scalar load) and that
   // sphere's snapshot, in flight with the populations; the first entry is clamped into
   // range for the snapshot load and used only when the count lists it
-  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[p] + 2 * lt);
+  const int ls = *(const DILBM_CONST int32_t *)(d.lsel + p);  // the list set of this step
+  const uint64_t hv = *(const DILBM_CONST uint64_t *)(d.tile_head[ls] + 2 * lt);
   const int32_t raw0 = (int32_t)(hv >> 32);
   const int nb = min((int32_t)(uint32_t)hv, d.list_cap);
   const int nbs = d.nbodies;
   const DILBM_CONST int32_t *list =
-      (const DILBM_CONST int32_t *)(d.tile_list[p] + lt * d.list_cap);
+      (const DILBM_CONST int32_t *)(d.tile_list[ls] + lt * d.list_cap);
   const DILBM_CONST SphereSnap *snap = (const DILBM_CONST SphereSnap *)d.bsnap[p];
   SphereSnap s0{};
   if (nbs > 0) s0 = load_snap3(snap + min(raw0 & kListIndexMask, nbs - 1));
   if (MODE == kStep3) {
-    if (tid == 0) d.tile_head[p ^ 1][2 * lt] = 0;  // lists of the next step start empty
+    // the sphere step after this one rebins into the other set: it starts empty
+    if (tid == 0 && *(const DILBM_CONST int32_t *)(d.rb_flag + p) != 0)
+      d.tile_head[ls ^ 1][2 * lt] = 0;
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
       for (int i = tid; i < 6 * (nbs + 1); i += 256) a[i] = 0.0;
+      if (tid == 0) d.rb_flag[p ^ 1] = 0;  // read by the last sphere step, raised by the next
     }
   }
 
@@ -547,12 +551,12 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
     tile3<kFields3, TX, L>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
 }
 
-// One block per sphere.  BIN_ONLY: bin the spheres of the current state into the lists of
-// parity p (after set_particles); otherwise do the sphere step of parity p and bin the
-// moved spheres into the lists of parity p ^ 1.  Each of the four waves computes the same
-// update (the same instructions on the same data: bitwise the same result), thread 0
+// One block per sphere.  BIN_ONLY: bin the spheres of the current state into list set 0
+// (after set_particles); otherwise do the sphere step of parity p and, when a rebuild is
+// due, bin the moved spheres into the other list set.  Each of the four waves computes the
+// same update (the same instructions on the same data: bitwise the same result), thread 0
 // writes it, and the binning's candidate tiles are spread over all 256 threads: a sphere
-// of R = 8 has about 1 100 candidate rows, whose slot claims are most of the kernel's time.
+// of R = 8 has about 1 100 candidate rows, whose slot claims are most of a binning's time.
 template <bool BIN_ONLY, int TX>
 __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
   const Desc3 &d = *desc;
@@ -569,6 +573,11 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   const double m = d.bconst[2 * nb + b], I = d.bconst[3 * nb + b];
   const bool fixed = d.bconst[4 * nb + b] != 0.0;
   int q = p;
+  // tile lists: the set this step read, and whether this sphere step rebuilds them (into
+  // the other set; a fresh binning writes set 0 of a zeroed buffer)
+  const int ls = d.lsel[p];
+  const bool rebin = BIN_ONLY || d.rb_flag[p] != 0;
+  const int lnew = BIN_ONLY ? 0 : (rebin ? ls ^ 1 : ls);
   if (!BIN_ONLY) {
     // hydrodynamic force and torque of the step (read now: in flight with the pair loads)
     const double *acc = d.acc[p] + 6 * b;
@@ -642,6 +651,17 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
       X[a] = X[a] - N[a] * floor(X[a] / N[a]);
       if (X[a] >= N[a]) X[a] -= N[a];
     }
+    // moved more than half the skin since the lists were built: rebuild them next step
+    if (!rebin && threadIdx.x == 0) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double da = min_image(X[a] - d.bin_ref[3 * b + a], N[a]);
+        r2 += da * da;
+      }
+      if (!(r2 <= 0.25 * kBinSkin3 * kBinSkin3)) d.rb_flag[p ^ 1] = 1;
+    }
+    if (b == 0 && threadIdx.x == 0) d.lsel[p ^ 1] = lnew;  // the set the next step reads
     q = p ^ 1;
     if (threadIdx.x == 0) {
       double *sn = d.bstate[q];
@@ -673,8 +693,13 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
     if (lane == 0) atomicOr(d.err, (int32_t)kErrUnstable);
     return;
   }
-  // bin into the tile lists of parity q: every tile holding a node within R + support
-  const double H = R + d.support + 1e-3;
+  if (!rebin) return;  // the lists of the last rebuild still cover this sphere (uniform)
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.bin_ref[3 * b + a] = X[a];
+  }
+  // bin into list set lnew: every tile holding a node within R + support + skin
+  const double H = R + d.support + kBinSkin3 + 1e-3;
   const AxisTiles ax = axis_tiles(X[0], H, d.nx, d.tile_x, d.tiles_x);
   const AxisTiles ay = axis_tiles(X[1], H, d.ny, 256 / d.tile_x, d.tiles_y);
   const AxisTiles az = axis_tiles(X[2], H, d.nz, 1, d.nz);
@@ -682,8 +707,8 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
   const int na = na1 + max(0, ax.b1 - ax.b0 + 1);
   const int nbb = nb1 + max(0, ay.b1 - ay.b0 + 1);
   const int nc = nc1 + max(0, az.b1 - az.b0 + 1);
-  int32_t *hd = d.tile_head[q];
-  int32_t *lst = d.tile_list[q];
+  int32_t *hd = d.tile_head[lnew];
+  int32_t *lst = d.tile_list[lnew];
   // which of the tile's four waves (each 64 nodes of one row) hold a node within H of the
   // centre: per wave, each axis bounds the distance from below by the distance to the
   // middle of the wave's node range less half its extent (the periodic distance is
