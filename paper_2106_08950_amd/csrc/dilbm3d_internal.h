@@ -2,14 +2,17 @@
 // libdilbm (internal to the library).
 //
 // Memory layout of one 3-D solve in HBM:
-//   pop[2]        two population buffers, structure of arrays [q][nz][ny][nx] (q = 19 or
-//                 27) of FP32 g_i = S (f_i - w_i rho0), S = 36 or 216, stored in the moving
-//                 frame of ref_velocity3.  Pull scheme: node x at time t_n finds f_i in
+//   pop[2]        two population buffers, structure of arrays [q][nz][ny][pitch] (q = 19
+//                 or 27; pitch = row_pitch3(nx), whole 128-byte lines) of FP32
+//                 g_i = S (f_i - w_i rho0), S = 36 or 216, stored in the moving frame of
+//                 ref_velocity3.  Pull scheme: node x at time t_n finds f_i in
 //                 pop[p][i][x - c_i].
-//   tile_head[2]  per tile (64 x 4 x 1 or 256 x 1 x 1 nodes) two words: the number of
-//                 spheres whose phi support may touch it and the first list entry;
-//                 tile_list[2]: `list_cap` entries per tile (sphere index and four-wave
-//                 mask; entry 0 lives in the head)
+//   tile_head[2]  two list sets; per tile (64 x 4 x 1 or 256 x 1 x 1 nodes) two words:
+//                 the number of spheres whose phi support (plus the skin kBinSkin3) may
+//                 touch it and the first list entry; tile_list[2]: `list_cap` entries per
+//                 tile (sphere index and four-wave mask; entry 0 lives in the head).  The
+//                 lists are kept across steps: lsel[p] names the set the steps of parity p
+//                 read, and a rebuild fills the other set
 //   bstate[2]     sphere state SoA [9][nb]: x, y, z, u, v, w, omega_x, omega_y, omega_z
 //   bconst        sphere constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per sphere, what the collide kernel reads of it (SphereSnap, 64 B),
@@ -17,8 +20,8 @@
 //   acc[2]        FP64 accumulators [(nb + 1) * 6]: force (3) and torque (3) per sphere,
 //                 then the wall force in the last slot
 //   err           sticky error bits (kErrUnstable, kErrCapacity, kErrInternal)
-// Everything double-buffered is indexed by the step parity p: a step with parity p reads
-// slot p and writes slot 1 - p.
+// Everything else double-buffered is indexed by the step parity p: a step with parity p
+// reads slot p and writes slot 1 - p.
 #pragma once
 
 #include <stdint.h>

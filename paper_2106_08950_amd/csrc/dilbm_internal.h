@@ -1,7 +1,7 @@
 // dilbm_internal.h -- device-visible structures of libdilbm (internal to the library).
 //
 // Memory layout of one solve in HBM:
-//   pop[2]        two population buffers, structure of arrays [9][ny][nx] of shifted,
+//   pop[2]        two population buffers, structure of arrays [9][ny][pitch] of shifted,
 //                 scaled populations g_i = 36 (f_i - w_i rho0) in FP32 (or FP16 times
 //                 2^k); the factor 36 makes the D2Q9 weights exact integers.  What is
 //                 stored at step t is g_i - 3 K_i c_i.V_t (K_i = 36 w_i): the populations
@@ -9,12 +9,15 @@
 //                 velocity V_t drawn afresh every step (see ref_velocity), which keeps
 //                 FP32/FP16 rounding from accumulating a bias.  The pull scheme keeps
 //                 post-collision values: node x at time t_n finds f_i in
-//                 pop[p][i][x - c_i].
-//   tile_head[2]  per tile two words: the number of bodies whose phi support may touch
-//                 the tile, and the first of their list entries (one 8-byte scalar load
-//                 per tile, from a dense array)
+//                 pop[p][i][x - c_i].  Rows are `pitch` values apart (row_pitch: nx
+//                 rounded up to whole 128-byte lines); the padding is never touched.
+//   tile_head[2]  two list sets; per tile two words: the number of bodies whose phi
+//                 support (plus the skin kBinSkin) may touch the tile, and the first of
+//                 their list entries (one 8-byte scalar load per tile, from a dense array)
 //   tile_list[2]  per tile, `list_cap` entries: body index and four-wave mask (entry 0
-//                 lives in the tile's head; its slot here is unused)
+//                 lives in the tile's head; its slot here is unused).  The lists are kept
+//                 across steps: lsel[p] names the set the steps of parity p read, and a
+//                 rebuild fills the other set (see kBinSkin)
 //   bstate[2]     body state SoA [5][nb]: x, y, ux, uy, omega (FP64)
 //   bconst        body constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per body, what the collide kernel reads of it (BodySnap, 32 B): written
@@ -26,8 +29,8 @@
 //   acc[2]        FP64 force accumulators [(nb + 1) * 3]: Fx, Fy, T per body, then the
 //                 wall force in the last slot
 //   err           sticky error bits
-// Everything double-buffered is indexed by the step parity p: a step with parity p reads
-// slot p and writes slot 1 - p (bodies, lists) or both (populations).
+// Everything else double-buffered is indexed by the step parity p: a step with parity p
+// reads slot p and writes slot 1 - p (bodies, snapshots, force sums) or both (populations).
 #pragma once
 
 #include <stdint.h>
