@@ -1,7 +1,8 @@
 """Benchmark of the DI-LBM time step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs fp32,fp16,open_ends,suspension3d,suspension3d_q27,batched,served]
+                    [--legs fp32,fp16,open_ends,suspension3d,suspension3d_q27,
+                            suspension3d_fp16,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -34,6 +35,7 @@ Further legs, reported in the same JSON line:
 * suspension3d: the three-dimensional path, 256^3 D3Q19 nodes with 400 free spheres
   (seed 8), FP32 (152 B per node update);
 * suspension3d_q27: the same on the D3Q27 lattice (216 B per node update);
+* suspension3d_fp16: the D3Q19 suspension with FP16 storage (76 B per node update);
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -222,28 +224,31 @@ def single_solve(wl, storage, steps, warmup, tile, stream, bytes_per_node, traff
             "roofline": roofline(bytes_per_node, wl.nodes, ms, traffic, "k_collide", copy_gbs)}
 
 
-def suspension3d_leg(steps, warmup, stream, q=19):
-    """The three-dimensional path: 256^3 periodic nodes with 400 free spheres, FP32, on
-    D3Q19 (19 x 4 bytes read + 19 x 4 written = 152 B per node update) or D3Q27 (216 B)."""
+def suspension3d_leg(steps, warmup, stream, q=19, storage=0):
+    """The three-dimensional path: 256^3 periodic nodes with 400 free spheres, on D3Q19
+    (19 x 4 bytes read + 19 x 4 written = 152 B per node update in FP32, 76 B in FP16) or
+    D3Q27 (216 B in FP32)."""
     from paper_2106_08950_amd import dilbm3d, inputs3d
 
+    es = 2 if storage == 1 else 4
     w3 = inputs3d.suspension3d()
     s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w3, device=0, stream=stream.cuda_stream,
-                                                      lattice=q))
+                                                      lattice=q, storage=storage))
     s.set_particles(w3.pos, w3.radius, w3.density, w3.vel, w3.omega, w3.fixed)
-    copy_gbs = copy_bandwidth(stream, q * 4 * w3.nodes)
+    copy_gbs = copy_bandwidth(stream, q * es * w3.nodes)
     settle_steps(s.step, steps)
     s.step(warmup)
     runs = timed_runs(s.step, steps)
     ms = launch_pass(s, max(steps, 100))
     s.close()
     dt = statistics.median(runs)
-    counters = COUNTERS3 if q == 19 else COUNTERS3_27
-    return {"workload": w3.name, "lattice": f"D3Q{q}",
+    counters = None if storage == 1 else (COUNTERS3 if q == 19 else COUNTERS3_27)
+    return {"workload": w3.name, "lattice": f"D3Q{q}", "storage": "fp16" if storage else "fp32",
             "value": round(w3.nodes * steps / dt / 1e6, 1),
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
             "runs_ms_per_step": [round(r * 1e3 / steps, 4) for r in runs],
-            "roofline": roofline(8 * q, w3.nodes, ms, measured_traffic(counters, KERNEL3_FILES),
+            "roofline": roofline(2 * es * q, w3.nodes, ms,
+                                 measured_traffic(counters, KERNEL3_FILES) if counters else None,
                                  "k3_collide", copy_gbs)}
 
 
@@ -402,7 +407,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,suspension3d_q27,"
-                                      "batched,served")
+                                      "suspension3d_fp16,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--served-count", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -465,6 +470,10 @@ def main():
         log("suspension3d D3Q27")
         out["suspension3d_q27"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup,
                                                    stream, q=27)
+    if "suspension3d_fp16" in legs:
+        log("suspension3d FP16")
+        out["suspension3d_fp16"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup,
+                                                    stream, q=19, storage=1)
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

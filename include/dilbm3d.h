@@ -27,9 +27,11 @@
  *     27) and hold f_i - w_i * rho0 as FP64.  Per-sphere vectors are [n][3] (x, y, z).
  *   - Host pointers; the caller owns every array; status codes and handle poisoning
  *     as in dilbm.h (DILBM_EUNSTABLE and DILBM_ECAPACITY poison the handle).
- *   - Populations are stored on the device in FP32 as f_i - w_i rho0 (structure of
- *     arrays, one plane per direction); all arithmetic of the node update is FP32, the
- *     sphere forces, torques and motion are FP64.
+ *   - Populations are stored on the device in FP32 as f_i - w_i rho0, or in FP16 as
+ *     S (f_i - w_i rho0) 2^k with stochastic rounding in the step (storage =
+ *     DILBM_STORE_FP16, as in dilbm.h; structure of arrays, one plane per direction);
+ *     all arithmetic of the node update is FP32, the sphere forces, torques and motion
+ *     are FP64.
  *   - A sphere's mass is rho_s * 4/3 pi R^3 and its moment of inertia 2/5 m R^2; the
  *     spin update has no gyroscopic term (the inertia is isotropic).
  *   - Streaming is periodic on all three axes; walls are static diffuse slabs across
@@ -47,7 +49,7 @@
 extern "C" {
 #endif
 
-#define DILBM3D_ABI_VERSION 2u
+#define DILBM3D_ABI_VERSION 3u
 
 enum { DILBM3D_WALL_Y = 1u, DILBM3D_WALL_X = 2u, DILBM3D_WALL_Z = 4u };
 
@@ -55,7 +57,8 @@ typedef struct dilbm3d_solver dilbm3d_solver;
 
 typedef struct dilbm3d_params {
   uint32_t abi_version;        /* DILBM3D_ABI_VERSION, else DILBM_EABI */
-  int32_t nx, ny, nz;          /* >= 1 each; nx * ny * nz * q * 4 bytes per buffer < 4 GB */
+  int32_t nx, ny, nz;          /* >= 1 each; one population buffer (q planes of nz * ny
+                                  rows; a row nx values rounded up to 128 bytes) < 4 GB */
   double tau;                  /* BGK relaxation time, > 0.5 */
   double rho0;                 /* rest density, > 0 */
   double interface_width;      /* epsilon of Eq. (14), > 0 */
@@ -68,13 +71,16 @@ typedef struct dilbm3d_params {
   double coll_eps_p, coll_eps_p_overlap, coll_eps_w, coll_eps_w_overlap, coll_xi; /* (28)-(29) */
   int32_t list_capacity;       /* spheres listed per tile; 0 = min(n, 128); <= 1024 */
   int32_t lattice;             /* 19 (D3Q19; 0 also means 19) or 27 (D3Q27) */
+  int32_t storage;             /* DILBM_STORE_FP32 or DILBM_STORE_FP16, as in dilbm.h */
+  int32_t fp16_scale_log2;     /* FP16 storage keeps S (f - w rho0) * 2^k; k in [0, 24] */
   int32_t device;              /* HIP device ordinal */
   void *stream;                /* hipStream_t to run on, or NULL for a library-owned one */
 } dilbm3d_params;
 
 /* Fill *p with defaults: abi_version, rho0 = 1, interface_width = 2, phi_cutoff = 4,
- * wall_half_thickness = 4, collision constants 1e4 / 1e4 / 5e3 / 5e3 and xi = 1; the
- * caller sets nx, ny, nz and tau.  Returns DILBM_EINVAL for p == NULL. */
+ * wall_half_thickness = 4, collision constants 1e4 / 1e4 / 5e3 / 5e3 and xi = 1, FP32
+ * storage, fp16_scale_log2 = 10; the caller sets nx, ny, nz and tau.  Returns
+ * DILBM_EINVAL for p == NULL. */
 dilbm_status dilbm3d_params_init(dilbm3d_params *p);
 
 /* Create a solver with the fluid at rest (f = w rho0) and no spheres.  *out receives the
@@ -91,7 +97,8 @@ dilbm_status dilbm3d_set_particles(dilbm3d_solver *s, int32_t n, const double *p
                                    const uint8_t *fixed);
 
 /* Populations in and out, [q][nz][ny][nx] deviations f_i - w_i rho0 at the current step,
- * q = 19 or 27 (the lattice; stored as FP32: values are rounded on the way in). */
+ * q = 19 or 27 (the lattice; stored as FP32 or FP16: values are rounded to nearest on the
+ * way in). */
 dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev);
 dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev);
 

@@ -81,6 +81,37 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Counter-based 32-bit hash (Wellons' "lowbias32" integer finaliser) and one xorshift32
+// step (Marsaglia, 2003): random bits for stochastic rounding, keyed by node and step.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+typedef _Float16 F16x2 __attribute__((ext_vector_type(2)));
+
+// x rounded stochastically to FP16 with the gfx950 conversion v_cvt_sr_f16_f32, which adds
+// the top 13 bits of rnd to the 13 FP32 mantissa bits that FP16 drops and truncates
+// (normal range): with 13 uniform random bits the result rounds up with exactly its
+// distance from the lower neighbour.
+__device__ __forceinline__ uint16_t sr_half(float x, uint32_t rnd) {
+  // the conversion writes the low half of its destination; seeding that register with x
+  // itself costs no move (its high half is never stored)
+  F16x2 z = __builtin_bit_cast(F16x2, x);
+  z = __builtin_amdgcn_cvt_sr_f16_f32(z, x, rnd, false);
+  return __builtin_bit_cast(uint16_t, z.x);
+}
+
 __device__ __forceinline__ double min_image(double d, double n) {
   if (d >= 0.5 * n) return d - n;
   if (d < -0.5 * n) return d + n;

@@ -3,10 +3,11 @@
 //
 // Memory layout of one 3-D solve in HBM:
 //   pop[2]        two population buffers, structure of arrays [q][nz][ny][pitch] (q = 19
-//                 or 27; pitch = row_pitch3(nx), whole 128-byte lines) of FP32
+//                 or 27; pitch = row_pitch3, whole 128-byte lines) of FP32
 //                 g_i = S (f_i - w_i rho0), S = 36 or 216, stored in the moving frame of
-//                 ref_velocity3.  Pull scheme: node x at time t_n finds f_i in
-//                 pop[p][i][x - c_i].
+//                 ref_velocity3, or of FP16 g_i 2^k (no frame: the stochastic rounding of
+//                 the stores keeps FP16 free of drift).  Pull scheme: node x at time t_n
+//                 finds f_i in pop[p][i][x - c_i].
 //   tile_head[2]  two list sets; per tile (64 x 4 x 1 or 256 x 1 x 1 nodes) two words:
 //                 the number of spheres whose phi support (plus the skin kBinSkin3) may
 //                 touch it and the first list entry; tile_list[2]: `list_cap` entries per
@@ -37,8 +38,12 @@ constexpr int kQ3Max = 27;   // D3Q27
 #endif
 constexpr int kMaxListCap3 = 1024;
 
-// Row pitch of the population planes (populations per row).
-inline int32_t row_pitch3(int32_t nx) { return (nx + 31) / 32 * 32; }
+// Row pitch of the population planes (populations per row): whole 128-byte lines, 32 FP32
+// or 64 FP16 values.
+inline int32_t row_pitch3(int32_t nx, int32_t storage) {
+  const int32_t a = storage == 1 ? 64 : 32;
+  return (nx + a - 1) / a * a;
+}
 
 // Tile lists are built with the reach R + support + kBinSkin3 and rebuilt once some sphere
 // has moved half that skin since its last binning.
@@ -97,6 +102,8 @@ struct Desc3 {
   float wall_h;
   uint32_t wall_mask; // bit 0 y, bit 1 x, bit 2 z
   int32_t store_nt;   // population stores carry the non-temporal hint
+  int32_t storage;    // 0: FP32 populations; 1: FP16, g 2^k, stochastically rounded
+  float store_scale, store_inv;  // 2^k and 2^-k (1 for FP32)
   // nodes within h + cutoff*eps of a walled seam: [0, lo) and [hi, n) on each axis
   int32_t wall_lo[3], wall_hi[3];  // axis order x, y, z
   // FP64 sphere constants

@@ -66,6 +66,11 @@ dilbm_status guard3(std::string *err, F &&f) {
 
 // directions of the lattice: 19 (D3Q19, also for 0) or 27 (D3Q27)
 int q_of(const dilbm3d_params &p) { return p.lattice == 27 ? 27 : 19; }
+bool fp16_of(const dilbm3d_params &p) { return p.storage == DILBM_STORE_FP16; }
+// bytes of one population buffer: q planes of nz * ny rows of row_pitch3 values
+uint64_t pop_half_bytes3(const dilbm3d_params &p) {
+  return (uint64_t)q_of(p) * row_pitch3(p.nx, p.storage) * p.ny * p.nz * (fp16_of(p) ? 2 : 4);
+}
 
 void validate3(const dilbm3d_params *p) {
   if (!p) fail3(DILBM_EINVAL, "params is NULL");
@@ -73,9 +78,13 @@ void validate3(const dilbm3d_params *p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) fail3(DILBM_EINVAL, "nx, ny, nz must be >= 1");
   if (p->lattice != 0 && p->lattice != 19 && p->lattice != 27)
     fail3(DILBM_EINVAL, "lattice must be 19 (D3Q19) or 27 (D3Q27)");
-  const uint64_t cells = (uint64_t)row_pitch3(p->nx) * p->ny * p->nz;
-  if (cells * (uint64_t)q_of(*p) * 4ull >= (1ull << 32) - 256)
-    fail3(DILBM_EINVAL, "q * 4 bytes * nx * ny * nz (nx rounded up to 32) must stay under 4 GB");
+  if (p->storage != DILBM_STORE_FP32 && p->storage != DILBM_STORE_FP16)
+    fail3(DILBM_EINVAL, "storage must be DILBM_STORE_FP32 or DILBM_STORE_FP16");
+  if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)
+    fail3(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24]");
+  if (pop_half_bytes3(*p) >= (1ull << 32) - 256)
+    fail3(DILBM_EINVAL, "one population buffer (q planes, rows rounded up to 128 bytes) must "
+                        "stay under 4 GB");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) fail3(DILBM_EINVAL, "tau must be > 0.5");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) fail3(DILBM_EINVAL, "rho0 must be > 0");
   if (!(p->interface_width > 0.0) || !std::isfinite(p->interface_width))
@@ -171,7 +180,7 @@ void size_grid3(dilbm3d_solver &s) {
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_of(s.prm, 256), (int64_t)1 << 30));
     return;
   }
-  const int bpc = std::max(1, collide3_blocks_per_cu(q_of(s.prm), s.tile_x));
+  const int bpc = std::max(1, collide3_blocks_per_cu(q_of(s.prm), fp16_of(s.prm), s.tile_x));
   int cus = 0;
   HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
   const int64_t T = tiles_of(s.prm, s.tile_x), resident = (int64_t)cus * bpc;
@@ -215,7 +224,11 @@ void fill_desc3(dilbm3d_solver &s) {
   d.nx = p.nx;
   d.ny = p.ny;
   d.nz = p.nz;
-  d.pitch = row_pitch3(p.nx);
+  d.pitch = row_pitch3(p.nx, p.storage);
+  d.storage = fp16_of(p) ? 1 : 0;
+  const double sc = fp16_of(p) ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
+  d.store_scale = (float)sc;
+  d.store_inv = (float)(1.0 / sc);
   d.tile_x = s.tile_x;
   d.tiles_x = (p.nx + d.tile_x - 1) / d.tile_x;
   d.tiles_y = (p.ny + 256 / d.tile_x - 1) / (256 / d.tile_x);
@@ -234,7 +247,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.wall_h = (float)p.wall_half_thickness;
   d.wall_mask = p.wall_mask;
   // non-temporal population stores once the populations exceed the last-level cache
-  const uint64_t pops = 2ull * q_of(p) * 4ull * (uint64_t)row_pitch3(p.nx) * p.ny * p.nz;
+  const uint64_t pops = 2ull * pop_half_bytes3(p);
   d.store_nt = pops > kStoreNtMinBytes3 ? 1 : 0;
   const int n3[3] = {p.nx, p.ny, p.nz};
   const double reach = p.wall_half_thickness + p.phi_cutoff * p.interface_width;
@@ -256,7 +269,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.xi = p.coll_xi;
   d.wall_h_d = p.wall_half_thickness;
   d.support = p.phi_cutoff * p.interface_width;
-  const uint64_t half = (uint64_t)q_of(p) * row_pitch3(p.nx) * p.ny * p.nz * 4;
+  const uint64_t half = pop_half_bytes3(p);
   d.pop[0] = (float *)s.pops.ptr;
   d.pop[1] = (float *)((char *)s.pops.ptr + half);
   char *bb = (char *)s.body.ptr;
@@ -358,6 +371,7 @@ dilbm_status dilbm3d_params_init(dilbm3d_params *p) {
   p->coll_eps_w = 0.5e4;
   p->coll_eps_w_overlap = 0.5e4;
   p->coll_xi = 1.0;
+  p->fp16_scale_log2 = 10;
   return DILBM_OK;
 }
 
@@ -381,7 +395,7 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
       HIPCHK3(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
       s.own_stream = true;
     }
-    const uint64_t half = (uint64_t)q_of(*p) * row_pitch3(p->nx) * p->ny * p->nz * 4;
+    const uint64_t half = pop_half_bytes3(*p);
     s.pops = alloc3(2 * half);
     HIPCHK3(hipMalloc(&s.d_desc, sizeof(Desc3)));
     HIPCHK3(hipMalloc(&s.d_err, sizeof(int32_t)));
@@ -393,7 +407,7 @@ dilbm_status dilbm3d_create(const dilbm3d_params *p, dilbm3d_solver **out) {
     HIPCHK3(launch_zero_bytes(s.body.ptr, (int64_t)s.body.bytes, s.stream));
     HIPCHK3(launch_zero_bytes(s.d_err, sizeof(int32_t), s.stream));
     upload_desc3(s);
-    HIPCHK3(launch3_rest_pops(q_of(*p), (int64_t)q_of(*p) * p->nx * p->ny * p->nz, s.stream,
+    HIPCHK3(launch3_rest_pops(q_of(*p), fp16_of(*p), (int64_t)q_of(*p) * p->nx * p->ny * p->nz, s.stream,
                               s.d_desc, 0));
     size_grid3(s);
   });
@@ -475,7 +489,7 @@ dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev) {
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
     HIPCHK3(hipMemcpyAsync(tmp.p, f_dev, sizeof(double) * count, hipMemcpyHostToDevice,
                            s->stream));
-    HIPCHK3(launch3_set_pops(q_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps,
+    HIPCHK3(launch3_set_pops(q_of(s->prm), fp16_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps,
                              (const double *)tmp.p));
     HIPCHK3(hipStreamSynchronize(s->stream));
   });
@@ -488,7 +502,7 @@ dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev) {
     const int64_t count = (int64_t)q_of(s->prm) * s->prm.nx * s->prm.ny * s->prm.nz;
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * count));
-    HIPCHK3(launch3_get_pops(q_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps, (double *)tmp.p));
+    HIPCHK3(launch3_get_pops(q_of(s->prm), fp16_of(s->prm), count, s->stream, s->d_desc, s->parity, s->steps, (double *)tmp.p));
     HIPCHK3(hipMemcpyAsync(f_dev, tmp.p, sizeof(double) * count, hipMemcpyDeviceToHost,
                            s->stream));
     HIPCHK3(hipStreamSynchronize(s->stream));
@@ -520,13 +534,13 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
         HIPCHK3(hipEventCreate(&ev.first));
         HIPCHK3(hipEventCreate(&ev.second));
         HIPCHK3(hipEventRecord(ev.first, s->stream));
-        HIPCHK3(launch3_collide(q_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
                                 s->steps));
         HIPCHK3(hipEventRecord(ev.second, s->stream));
         s->events.push_back(ev);
         if (s->events.size() >= 4096) collect_timing3(*s);
       } else {
-        HIPCHK3(launch3_collide(q_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
                                 s->steps));
       }
       HIPCHK3(launch3_bodies(false, s->nb, s->tile_x, s->stream, s->d_desc, p));
@@ -547,7 +561,7 @@ dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, doub
     DevBuf tmp;
     HIPCHK3(hipMalloc(&tmp.p, sizeof(double) * 4 * n));
     double *t = (double *)tmp.p;
-    HIPCHK3(launch3_fields(q_of(s->prm), s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, s->steps,
+    HIPCHK3(launch3_fields(q_of(s->prm), fp16_of(s->prm), s->h.tile_x, s->h.ntiles, s->stream, s->d_desc, s->parity, s->steps,
                            t, t + n, t + 2 * n, t + 3 * n));
     double *outs[4] = {rho, ux, uy, uz};
     for (int k = 0; k < 4; ++k)

@@ -82,8 +82,6 @@ struct StoreF32 {
 // (values that are already representable, zero included, are stored exactly).  Host
 // conversions in and out round to nearest.  FP16 needs no moving frame: its storage
 // rounding dwarfs the FP32 arithmetic drift the frame removes.
-typedef _Float16 F16x2 __attribute__((ext_vector_type(2)));
-
 struct StoreF16 {
   static constexpr int kWaves = DILBM_COLLIDE_WAVES_F16;  // register budget, waves per SIMD
   using T = _Float16;
@@ -104,13 +102,7 @@ struct StoreF16 {
   // rotated by 13, so one word serves two populations with disjoint bits.
   static __device__ __forceinline__ uint16_t round_bits(float v, float scale, uint32_t h,
                                                         int k) {
-    const uint32_t rnd = (k & 1) ? __builtin_amdgcn_alignbit(h, h, 13) : h;
-    const float x = v * scale;
-    // the conversion writes the low half of its destination; seeding that register with
-    // x itself costs no move (its high half is never stored)
-    F16x2 z = __builtin_bit_cast(F16x2, x);
-    z = __builtin_amdgcn_cvt_sr_f16_f32(z, x, rnd, false);
-    return __builtin_bit_cast(uint16_t, z.x);
+    return sr_half(v * scale, (k & 1) ? __builtin_amdgcn_alignbit(h, h, 13) : h);
   }
   template <bool NT = false>
   static __device__ __forceinline__ void stb_bits(__amdgpu_buffer_rsrc_t r, uint32_t voff,
@@ -193,23 +185,6 @@ __device__ __forceinline__ float2 frame_velocity(int64_t t) {
     return ref_velocity<ST::kRefLog2>(t);
   else
     return make_float2(0.0f, 0.0f);
-}
-
-// Counter-based 32-bit hash (Wellons' "lowbias32" integer finaliser) and one xorshift32
-// step (Marsaglia, 2003): random bits for stochastic rounding, keyed by node and step.
-__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
-}
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
-  x ^= x << 13;
-  x ^= x >> 17;
-  x ^= x << 5;
-  return x;
 }
 
 // 3 K_i c_i.V: the frame offset of direction i

@@ -13,13 +13,13 @@ namespace dilbm {
 // one step's collide over all tiles of the solve (parity p); tile_x is the tile width
 // (64: tiles of 64 x 4 x 1 nodes, chunked persistent grid; 256: 256 x 1 x 1, one block
 // per tile)
-// q: the lattice, 19 (D3Q19) or 27 (D3Q27)
-hipError_t launch3_collide(int q, int tile_x, int grid, hipStream_t stream, const Desc3 *desc,
-                           int p, int64_t step);
+// q: the lattice, 19 (D3Q19) or 27 (D3Q27); h: FP16 population storage
+hipError_t launch3_collide(int q, bool h, int tile_x, int grid, hipStream_t stream,
+                           const Desc3 *desc, int p, int64_t step);
 // blocks of the collide kernel resident on one CU at once (0 on error)
-int collide3_blocks_per_cu(int q, int tile_x);
+int collide3_blocks_per_cu(int q, bool h, int tile_x);
 // rho and corrected u of parity p's state into [nz][ny][nx] device arrays
-hipError_t launch3_fields(int q, int tile_x, int64_t ntiles, hipStream_t stream,
+hipError_t launch3_fields(int q, bool h, int tile_x, int64_t ntiles, hipStream_t stream,
                           const Desc3 *desc, int p, int64_t step, double *rho, double *ux,
                           double *uy, double *uz);
 // the sphere step of parity p (or, bin_only, the binning of parity p's state) into the
@@ -27,12 +27,12 @@ hipError_t launch3_fields(int q, int tile_x, int64_t ntiles, hipStream_t stream,
 hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t stream,
                           const Desc3 *desc, int p);
 // populations in / out of parity p's buffer (count = q nx ny nz), device FP64 arrays
-hipError_t launch3_set_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            int64_t step, const double *fin);
-hipError_t launch3_get_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            int64_t step, double *fout);
+hipError_t launch3_set_pops(int q, bool h, int64_t count, hipStream_t stream,
+                            const Desc3 *desc, int p, int64_t step, const double *fin);
+hipError_t launch3_get_pops(int q, bool h, int64_t count, hipStream_t stream,
+                            const Desc3 *desc, int p, int64_t step, double *fout);
 // the fluid at rest in both buffers (count = q nx ny nz)
-hipError_t launch3_rest_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc,
-                             int64_t step);
+hipError_t launch3_rest_pops(int q, bool h, int64_t count, hipStream_t stream,
+                             const Desc3 *desc, int64_t step);
 
 }  // namespace dilbm

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "dilbm3d_internal.h"
@@ -128,7 +129,7 @@ constexpr int kStash3 = L == 27 ? DILBM3D27_STASH : L;
 
 // One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
-template <int MODE, int TX, int L>
+template <int MODE, int TX, int L, bool H>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
                                       const int64_t t, float (*red)[6][64], float *stash,
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
@@ -155,13 +156,17 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) ------------------------------
   // one buffer resource per population buffer; the row of every direction is
   // wave-uniform (scalar offset), the column is one of three per-lane offsets
+  // H: FP16 populations, g_i 2^k (raw: the moments are scaled back, the update is applied
+  // at the stored scale)
+  constexpr uint32_t es = H ? 2u : 4u;
+  const float inv = d.store_inv, sc = d.store_scale;
   const uint32_t plane = (uint32_t)pitch * (uint32_t)ny * (uint32_t)nz;
-  const uint32_t pb = plane * 4u;
+  const uint32_t pb = plane * es;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(L * pb), kBufferFlags);
-  const uint32_t vx0 = (uint32_t)xc * 4u;
-  const uint32_t vxm = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * 4u;  // source x - 1
-  const uint32_t vxp = (uint32_t)(xc + 1 == nx ? 0 : xc + 1) * 4u;  // source x + 1
+  const uint32_t vx0 = (uint32_t)xc * es;
+  const uint32_t vxm = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * es;  // source x - 1
+  const uint32_t vxp = (uint32_t)(xc + 1 == nx ? 0 : xc + 1) * es;  // source x + 1
   uint32_t row[3][3];  // row[dz + 1][dy + 1]: byte offset of row (y + dy, z + dz)
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
@@ -169,13 +174,16 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     for (int dy = -1; dy <= 1; ++dy)
       row[dz + 1][dy + 1] = __builtin_amdgcn_readfirstlane(
           ((uint32_t)wrapi(z + dz, nz) * (uint32_t)ny + (uint32_t)wrapi(yc + dy, ny)) *
-          (uint32_t)pitch * 4u);
+          (uint32_t)pitch * es);
   float g[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const uint32_t v = C3X[i] == 0 ? vx0 : (C3X[i] > 0 ? vxm : vxp);
     const uint32_t s = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
-    g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, s, 0));
+    if (H)
+      g[i] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, v, s, 0));
+    else
+      g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, s, 0));
   }
 
   // the tile's head (sphere count and first list entry, one scalar load) and that
@@ -210,8 +218,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   // across the whole tile.
   int64_t tc = t;
   asm volatile("" : "+s"(tc));
-  float3 Vf = ref_velocity3<L>(tc);
-  if (MODE == kStep3) {
+  float3 Vf = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(tc);  // FP16: no frame
+  if (MODE == kStep3 && !H) {
     const float3 Vt = Vf;
     Vf = ref_velocity3<L>(tc + 1);
     const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
@@ -232,6 +240,12 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     if (C3X[i]) Jx += C3X[i] > 0 ? g[i] : -g[i];
     if (C3Y[i]) Jy += C3Y[i] > 0 ? g[i] : -g[i];
     if (C3Z[i]) Jz += C3Z[i] > 0 ? g[i] : -g[i];
+  }
+  if (H) {  // back to g units (exact: a power of two)
+    D *= inv;
+    Jx *= inv;
+    Jy *= inv;
+    Jz *= inv;
   }
   const float R = S * d.rho0 + D;  // S rho
   const float rho = R * invS;
@@ -477,7 +491,11 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const float base = drho - 1.5f * rho * uu;            // even part shared by all i
   const float sbase = -3.0f * uG - 1.5f * trQ;          // even part of S shared by all i
   float out[L];
-  out[0] = g[0] + om * (kw3<L>(0) * base - g[0]) + kh * kw3<L>(0) * sbase;
+  // each output is g + (small update), applied once at the scale of g (FP16: g 2^k)
+  if (H)
+    out[0] = fmaf(sc, om * (kw3<L>(0) * base - inv * g[0]) + kh * kw3<L>(0) * sbase, g[0]);
+  else
+    out[0] = g[0] + om * (kw3<L>(0) * base - g[0]) + kh * kw3<L>(0) * sbase;
 #pragma unroll
   for (int i = 1; i < L; i += 2) {
     const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
@@ -492,32 +510,54 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     const float od = K * 3.0f * cm;                           // odd part of geq
     const float sev = K * (sbase + 9.0f * cu * cG + 4.5f * cQc);
     const float sod = K * 3.0f * (cG + cP);
-    out[i] = g[i] + om * (ev + od - g[i]) + kh * (sev + sod);
-    out[i + 1] = g[i + 1] + om * (ev - od - g[i + 1]) + kh * (sev - sod);
+    if (H) {
+      out[i] = fmaf(sc, om * (ev + od - inv * g[i]) + kh * (sev + sod), g[i]);
+      out[i + 1] = fmaf(sc, om * (ev - od - inv * g[i + 1]) + kh * (sev - sod), g[i + 1]);
+    } else {
+      out[i] = g[i] + om * (ev + od - g[i]) + kh * (sev + sod);
+      out[i + 1] = g[i + 1] + om * (ev - od - g[i + 1]) + kh * (sev - sod);
+    }
   }
 
   const float vv = ux * ux + uy * uy + uz * uz;
   if (__ballot(valid && !(rho > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
     atomicOr(d.err, (int32_t)kErrUnstable);
+  uint16_t hb[L];  // FP16: the stochastically rounded halves
+  if (H) {
+    // 13 random bits per population, from one hash of (node, step) and xorshifts, each
+    // 32-bit word serving two populations
+    const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
+    uint32_t hw = lowbias32((((uint32_t)z * (uint32_t)ny + (uint32_t)yc) * (uint32_t)nx +
+                            (uint32_t)xc) ^ tk);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      if (i > 0 && (i & 1) == 0) hw = xorshift32(hw);
+      hb[i] = sr_half(out[i], (i & 1) ? __builtin_amdgcn_alignbit(hw, hw, 13) : hw);
+    }
+  }
   if (valid) {
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
         (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
     const uint32_t s0r = row[1][1];
-    if (d.store_nt) {
+    auto put_all = [&](auto nt) {
+      constexpr int CP = decltype(nt)::value ? kStoreNT : 0;
 #pragma unroll
-      for (int i = 0; i < L; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
-                                              (uint32_t)i * pb + s0r, kStoreNT);
-    } else {
-#pragma unroll
-      for (int i = 0; i < L; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
-                                              (uint32_t)i * pb + s0r, 0);
-    }
+      for (int i = 0; i < L; ++i) {
+        if (H)
+          __builtin_amdgcn_raw_buffer_store_b16(hb[i], rd, vx0, (uint32_t)i * pb + s0r, CP);
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[i]), rd, vx0,
+                                                (uint32_t)i * pb + s0r, CP);
+      }
+    };
+    if (d.store_nt)
+      put_all(std::true_type{});
+    else
+      put_all(std::false_type{});
   }
 }
 
-template <int TX, int L>
+template <int TX, int L, bool H>
 __global__ __launch_bounds__(256, (L == 19 ? DILBM3D_COLLIDE_WAVES : DILBM3D27_COLLIDE_WAVES))
 void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
@@ -527,7 +567,7 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
     // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
     // XCDs at once
     for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-      tile3<kStep3, TX, L>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
+      tile3<kStep3, TX, L, H>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
     return;
   }
   const WorkSplit ws = xcd_split(d.ntiles);
@@ -536,11 +576,11 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX, L>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX, L, H>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
   }
 }
 
-template <int TX, int L>
+template <int TX, int L, bool H>
 __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
                                                  int64_t step, double *__restrict__ rho,
                                                  double *__restrict__ ux,
@@ -548,7 +588,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX, L>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
+    tile3<kFields3, TX, L, H>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
 }
 
 // One block per sphere.  BIN_ONLY: bin the spheres of the current state into list set 0
@@ -767,14 +807,15 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
 }
 
 // Populations in and out: fin / fout are [L][nz][ny][nx] FP64 deviations f_i - w_i rho0
-// of the current state; node x keeps f_i at x - c_i (pull layout), as g = S (f - w rho0).
-template <int L>
+// of the current state; node x keeps f_i at x - c_i (pull layout), as g = S (f - w rho0)
+// in FP32 in the storage frame, or as g 2^k in FP16 (rounded to nearest; no frame).
+template <int L, bool H>
 __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             const double *__restrict__ fin) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;      // the caller's dense planes
   const int64_t dplane = (int64_t)d.pitch * d.ny * d.nz;  // the stored planes
-  const float3 V = ref_velocity3<L>(step);
+  const float3 V = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
@@ -784,18 +825,22 @@ __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    d.pop[p][i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs] =
-        (float)((double)Lat3<L>::S * fin[e] - frame_offset3<L>(i, V));
+    const int64_t o = i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs;
+    const double g = (double)Lat3<L>::S * fin[e] - frame_offset3<L>(i, V);
+    if (H)
+      ((_Float16 *)d.pop[p])[o] = (_Float16)(float)(g * (double)d.store_scale);
+    else
+      d.pop[p][o] = (float)g;
   }
 }
 
-template <int L>
+template <int L, bool H>
 __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             double *__restrict__ fout) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.nx * d.ny * d.nz;      // the caller's dense planes
   const int64_t dplane = (int64_t)d.pitch * d.ny * d.nz;  // the stored planes
-  const float3 V = ref_velocity3<L>(step);
+  const float3 V = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / plane);
@@ -805,23 +850,29 @@ __global__ void k3_get_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
     const int y = (int)(r % d.ny), z = (int)(r / d.ny);
     const int xs = wrapi(x - C3X[i], d.nx), ys = wrapi(y - C3Y[i], d.ny);
     const int zs = wrapi(z - C3Z[i], d.nz);
-    fout[e] = ((double)d.pop[p][i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs] +
-               frame_offset3<L>(i, V)) /
-              (double)Lat3<L>::S;
+    const int64_t o = i * dplane + ((int64_t)zs * d.ny + ys) * d.pitch + xs;
+    const double g = H ? (double)((const _Float16 *)d.pop[p])[o] * (double)d.store_inv
+                       : (double)d.pop[p][o];
+    fout[e] = (g + frame_offset3<L>(i, V)) / (double)Lat3<L>::S;
   }
 }
 
 // The fluid at rest (every deviation zero) in the frame of step `step`, in both buffers.
-template <int L>
+template <int L, bool H>
 __global__ void k3_rest_pops(const Desc3 *__restrict__ desc, int64_t step) {
   const Desc3 &d = *desc;
   const int64_t plane = (int64_t)d.pitch * d.ny * d.nz;  // padding columns included
-  const float3 V = ref_velocity3<L>(step);
+  const float3 V = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(step);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < L * plane;
        e += (int64_t)gridDim.x * blockDim.x) {
     const float v = (float)(-frame_offset3<L>((int)(e / plane), V));  // exact
-    d.pop[0][e] = v;
-    d.pop[1][e] = v;
+    if (H) {
+      ((_Float16 *)d.pop[0])[e] = (_Float16)v;
+      ((_Float16 *)d.pop[1])[e] = (_Float16)v;
+    } else {
+      d.pop[0][e] = v;
+      d.pop[1][e] = v;
+    }
   }
 }
 
@@ -830,31 +881,41 @@ int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min
 }  // namespace
 
 using Collide3 = void (*)(const Desc3 *, int, int64_t);
-static Collide3 collide3_kernel(int q, int tile_x) {
-  if (q == 27) return tile_x == 256 ? &k3_collide<256, 27> : &k3_collide<64, 27>;
-  return tile_x == 256 ? &k3_collide<256, 19> : &k3_collide<64, 19>;
+template <bool H>
+static Collide3 collide3_kernel_of(int q, int tile_x) {
+  if (q == 27) return tile_x == 256 ? &k3_collide<256, 27, H> : &k3_collide<64, 27, H>;
+  return tile_x == 256 ? &k3_collide<256, 19, H> : &k3_collide<64, 19, H>;
+}
+static Collide3 collide3_kernel(int q, bool h, int tile_x) {
+  return h ? collide3_kernel_of<true>(q, tile_x) : collide3_kernel_of<false>(q, tile_x);
 }
 
-hipError_t launch3_collide(int q, int tile_x, int grid, hipStream_t stream, const Desc3 *desc,
-                           int p, int64_t step) {
-  hipLaunchKernelGGL(collide3_kernel(q, tile_x), dim3(grid), dim3(256), 0, stream, desc, p,
+hipError_t launch3_collide(int q, bool h, int tile_x, int grid, hipStream_t stream,
+                           const Desc3 *desc, int p, int64_t step) {
+  hipLaunchKernelGGL(collide3_kernel(q, h, tile_x), dim3(grid), dim3(256), 0, stream, desc, p,
                      step);
   return hipGetLastError();
 }
 
-int collide3_blocks_per_cu(int q, int tile_x) {
+int collide3_blocks_per_cu(int q, bool h, int tile_x) {
   int n = 0;
-  const void *f = reinterpret_cast<const void *>(collide3_kernel(q, tile_x));
+  const void *f = reinterpret_cast<const void *>(collide3_kernel(q, h, tile_x));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) return 0;
   return n;
 }
 
-hipError_t launch3_fields(int q, int tile_x, int64_t ntiles, hipStream_t stream,
+using Fields3 = void (*)(const Desc3 *, int, int64_t, double *, double *, double *, double *);
+template <bool H>
+static Fields3 fields3_kernel_of(int q, int tile_x) {
+  if (q == 27) return tile_x == 256 ? &k3_fields<256, 27, H> : &k3_fields<64, 27, H>;
+  return tile_x == 256 ? &k3_fields<256, 19, H> : &k3_fields<64, 19, H>;
+}
+
+hipError_t launch3_fields(int q, bool h, int tile_x, int64_t ntiles, hipStream_t stream,
                           const Desc3 *desc, int p, int64_t step, double *rho, double *ux,
                           double *uy, double *uz) {
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
-  auto k = q == 27 ? (tile_x == 256 ? &k3_fields<256, 27> : &k3_fields<64, 27>)
-                   : (tile_x == 256 ? &k3_fields<256, 19> : &k3_fields<64, 19>);
+  auto k = h ? fields3_kernel_of<true>(q, tile_x) : fields3_kernel_of<false>(q, tile_x);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux, uy, uz);
   return hipGetLastError();
 }
@@ -869,24 +930,29 @@ hipError_t launch3_bodies(bool bin_only, int nbodies, int tile_x, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch3_set_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            int64_t step, const double *fin) {
-  hipLaunchKernelGGL(q == 27 ? &k3_set_pops<27> : &k3_set_pops<19>,
-                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step, fin);
+hipError_t launch3_set_pops(int q, bool h, int64_t count, hipStream_t stream,
+                            const Desc3 *desc, int p, int64_t step, const double *fin) {
+  auto k = q == 27 ? (h ? &k3_set_pops<27, true> : &k3_set_pops<27, false>)
+                   : (h ? &k3_set_pops<19, true> : &k3_set_pops<19, false>);
+  hipLaunchKernelGGL(k, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step,
+                     fin);
   return hipGetLastError();
 }
 
-hipError_t launch3_get_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc, int p,
-                            int64_t step, double *fout) {
-  hipLaunchKernelGGL(q == 27 ? &k3_get_pops<27> : &k3_get_pops<19>,
-                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step, fout);
+hipError_t launch3_get_pops(int q, bool h, int64_t count, hipStream_t stream,
+                            const Desc3 *desc, int p, int64_t step, double *fout) {
+  auto k = q == 27 ? (h ? &k3_get_pops<27, true> : &k3_get_pops<27, false>)
+                   : (h ? &k3_get_pops<19, true> : &k3_get_pops<19, false>);
+  hipLaunchKernelGGL(k, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, p, step,
+                     fout);
   return hipGetLastError();
 }
 
-hipError_t launch3_rest_pops(int q, int64_t count, hipStream_t stream, const Desc3 *desc,
-                             int64_t step) {
-  hipLaunchKernelGGL(q == 27 ? &k3_rest_pops<27> : &k3_rest_pops<19>,
-                     dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, step);
+hipError_t launch3_rest_pops(int q, bool h, int64_t count, hipStream_t stream,
+                             const Desc3 *desc, int64_t step) {
+  auto k = q == 27 ? (h ? &k3_rest_pops<27, true> : &k3_rest_pops<27, false>)
+                   : (h ? &k3_rest_pops<19, true> : &k3_rest_pops<19, false>);
+  hipLaunchKernelGGL(k, dim3(grid_for(count, 1 << 16)), dim3(256), 0, stream, desc, step);
   return hipGetLastError();
 }
 

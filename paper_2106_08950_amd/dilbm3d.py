@@ -14,7 +14,7 @@ import numpy as np
 from . import dilbm
 
 Q = 19
-ABI_VERSION = 2
+ABI_VERSION = 3
 WALL_Y, WALL_X, WALL_Z = 1, 2, 4
 
 EXPORTED = [
@@ -38,7 +38,8 @@ class dilbm3d_params(C.Structure):
         ("coll_eps_p", C.c_double), ("coll_eps_p_overlap", C.c_double),
         ("coll_eps_w", C.c_double), ("coll_eps_w_overlap", C.c_double),
         ("coll_xi", C.c_double),
-        ("list_capacity", C.c_int32), ("lattice", C.c_int32),
+        ("list_capacity", C.c_int32), ("lattice", C.c_int32), ("storage", C.c_int32),
+        ("fp16_scale_log2", C.c_int32),
         ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -102,6 +103,8 @@ class Params3D:
     coll_xi: float = 1.0
     list_capacity: int = 0
     lattice: int = 19          # 19: D3Q19, 27: D3Q27
+    storage: int = 0           # 0: FP32 populations, 1: FP16 (dilbm.STORE_FP16)
+    fp16_scale_log2: int = 10
     device: int = 0
     stream: int = 0
     abi_version: int = ABI_VERSION
@@ -124,6 +127,8 @@ class Params3D:
         p.coll_xi = float(self.coll_xi)
         p.list_capacity = int(self.list_capacity)
         p.lattice = int(self.lattice)
+        p.storage = int(self.storage)
+        p.fp16_scale_log2 = int(self.fp16_scale_log2)
         p.device = int(self.device)
         p.stream = int(self.stream) or None
         return p

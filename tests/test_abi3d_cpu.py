@@ -36,6 +36,7 @@ def test_params_defaults():
     assert (p.coll_eps_p, p.coll_eps_p_overlap, p.coll_eps_w, p.coll_eps_w_overlap, p.coll_xi) == (
         1.0e4, 1.0e4, 0.5e4, 0.5e4, 1.0)
     assert (p.list_capacity, p.device, p.wall_mask) == (0, 0, 0)
+    assert (p.storage, p.fp16_scale_log2) == (dilbm.STORE_FP32, 10)
     assert p.stream is None
     assert lib.dilbm3d_params_init(None) == dilbm.EINVAL
 
@@ -44,7 +45,8 @@ def test_params_defaults():
     dict(nx=0), dict(ny=-1), dict(nz=0), dict(nx=400, ny=400, nz=400), dict(tau=0.5),
     dict(tau=float("nan")), dict(rho0=0.0), dict(interface_width=0.0), dict(phi_cutoff=-1.0),
     dict(wall_mask=8), dict(wall_mask=4, wall_half_thickness=0.0), dict(force_mode=2),
-    dict(list_capacity=5000), dict(coll_xi=-1.0), dict(coll_eps_p=0.0),
+    dict(list_capacity=5000), dict(coll_xi=-1.0), dict(coll_eps_p=0.0), dict(storage=2),
+    dict(fp16_scale_log2=30), dict(fp16_scale_log2=-1),
     dict(body_force=(0.0, float("inf"), 0.0)), dict(gravity=(0.0, 0.0, float("nan"))),
 ])
 def test_create_rejects_bad_params_before_device(bad):
