@@ -31,6 +31,15 @@ namespace dilbm {
 
 constexpr int kQ3 = 19;      // D3Q19
 constexpr int kQ3Max = 27;   // D3Q27
+
+// Directions: rest, the six axis directions, the twelve edge directions (D3Q19), then the
+// eight corner directions (D3Q27); opposite directions are neighbours (i, i + 1) for odd i.
+constexpr int C3X[kQ3Max] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                             1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int C3Y[kQ3Max] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                             1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int C3Z[kQ3Max] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                             1, -1, -1, 1, 1, -1, 1, -1};
 // Tiles are tile_x x (256 / tile_x) x 1 nodes, 256 threads: tile_x = 256 (a whole row of
 // up to 256 nodes per block) when nx >= DILBM3D_WIDE_MIN, else 64 (64 x 4 x 1).
 #ifndef DILBM3D_WIDE_MIN
@@ -96,6 +105,7 @@ struct Desc3 {
   float khalf;        // 1 - 1/(2 tau)
   float rho0;
   float Gx, Gy, Gz;
+  float cg[kQ3Max / 2];  // c_i.G for the direction pairs (2k + 1, 2k + 2)
   float kappa;        // force scale of Eq. (18): 1 or 1 - 1/(2 tau)
   float lcut;         // -cutoff * eps
   float phi_k;        // 4 / eps * log2(e)

@@ -241,6 +241,10 @@ void fill_desc3(dilbm3d_solver &s) {
   d.Gx = (float)p.body_force[0];
   d.Gy = (float)p.body_force[1];
   d.Gz = (float)p.body_force[2];
+  for (int k = 0; k < kQ3Max / 2; ++k) {
+    const int i = 2 * k + 1;
+    d.cg[k] = (float)C3X[i] * d.Gx + (float)C3Y[i] * d.Gy + (float)C3Z[i] * d.Gz;
+  }
   d.kappa = p.force_mode == DILBM_FORCE_PAPER_LITERAL ? (float)(1.0 - 0.5 / p.tau) : 1.0f;
   d.lcut = (float)(-p.phi_cutoff * p.interface_width);
   d.phi_k = (float)(4.0 / p.interface_width * 1.4426950408889634);

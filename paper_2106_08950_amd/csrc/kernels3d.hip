@@ -33,15 +33,6 @@ namespace dilbm {
 
 namespace {
 
-// Directions: rest, the six axis directions, the twelve edge directions (D3Q19), then the
-// eight corner directions (D3Q27); opposite directions are neighbours (i, i + 1) for odd i.
-constexpr int C3X[kQ3Max] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
-                             1, -1, 1, -1, 1, -1, -1, 1};
-constexpr int C3Y[kQ3Max] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
-                             1, -1, 1, -1, -1, 1, 1, -1};
-constexpr int C3Z[kQ3Max] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
-                             1, -1, -1, 1, 1, -1, 1, -1};
-
 // The population scale S and the integer weights K_i = S w_i of lattice L.
 template <int L>
 struct Lat3;
@@ -501,7 +492,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
     const float cu = cx * ux + cy * uy + cz * uz;
     const float cm = cx * mx + cy * my + cz * mz;
-    const float cG = cx * Gx + cy * Gy + cz * Gz;
+    const float cG = d.cg[i >> 1];  // c.G of the pair, from the descriptor
     const float cP = cx * Px + cy * Py + cz * Pz;
     const float cQc = cx * cx * Qxx + cy * cy * Qyy + cz * cz * Qzz +
                       2.0f * (cx * cy * Qxy + cx * cz * Qxz + cy * cz * Qyz);
