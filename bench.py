@@ -67,6 +67,7 @@ COUNTERS16 = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp1
 COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm_counters.txt")
 COUNTERS3_27 = os.path.join(ROOT, "profiles",
                             "k3_collide_suspension3d_256_d3q27_fp32_hbm_counters.txt")
+COUNTERS3_16 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp16_hbm_counters.txt")
 TIMED_RUNS = 5
 
 
@@ -242,7 +243,7 @@ def suspension3d_leg(steps, warmup, stream, q=19, storage=0):
     ms = launch_pass(s, max(steps, 100))
     s.close()
     dt = statistics.median(runs)
-    counters = None if storage == 1 else (COUNTERS3 if q == 19 else COUNTERS3_27)
+    counters = {(19, 0): COUNTERS3, (27, 0): COUNTERS3_27, (19, 1): COUNTERS3_16}.get((q, storage))
     return {"workload": w3.name, "lattice": f"D3Q{q}", "storage": "fp16" if storage else "fp32",
             "value": round(w3.nodes * steps / dt / 1e6, 1),
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
