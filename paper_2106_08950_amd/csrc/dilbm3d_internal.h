@@ -73,6 +73,14 @@ constexpr uint64_t kStoreNtMinBytes3 = 256ull << 20;
 #ifndef DILBM3D27_COLLIDE_WAVES
 #define DILBM3D27_COLLIDE_WAVES 5
 #endif
+// the same for FP16 populations on either lattice.  The LDS of a block (the population
+// stash and the force rows) allows six per SIMD.  Measured on the 256^3 suspension: six
+// against five, D3Q19 FP16 393 -> 372 us per launch (79 VGPRs, no spills), D3Q27 FP16
+// 464 -> 454 us (80 VGPRs, 12 bytes of spills in the sphere loop); the FP32 instances
+// spill at six and lose 3% (D3Q19) and 8% (D3Q27).
+#ifndef DILBM3D_COLLIDE_WAVES_F16
+#define DILBM3D_COLLIDE_WAVES_F16 6
+#endif
 
 // Chunk of tiles each collide block sweeps (the grid never drops below one resident
 // wave while tiles last).  On the 256^3 suspension: 2 tiles 546 us, 3 549 us, 4 (one row

@@ -549,7 +549,9 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
 }
 
 template <int TX, int L, bool H>
-__global__ __launch_bounds__(256, (L == 19 ? DILBM3D_COLLIDE_WAVES : DILBM3D27_COLLIDE_WAVES))
+__global__ __launch_bounds__(256, (H ? DILBM3D_COLLIDE_WAVES_F16
+                                     : (L == 19 ? DILBM3D_COLLIDE_WAVES
+                                                : DILBM3D27_COLLIDE_WAVES)))
 void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   __shared__ float stash[kStash3<L> * 256];  // populations of the block's lanes
