@@ -33,6 +33,9 @@ class _Params(C.Structure):
         ("eps_p", C.c_double), ("eps_p1", C.c_double), ("eps_w", C.c_double),
         ("eps_w1", C.c_double), ("xi", C.c_double),
         ("lattice", C.c_int32),
+        ("x_boundary", C.c_int32), ("inlet_kind", C.c_int32), ("inlet_profile", C.c_int32),
+        ("outlet_kind", C.c_int32), ("u_in", C.c_double * 3), ("rho_in", C.c_double),
+        ("rho_out", C.c_double),
     ]
 
 
@@ -60,6 +63,10 @@ def _L():
         lib.ora3q_guo_term.argtypes = [C.c_int32, C.c_double, _dp, _dp, _dp]
         lib.ora3q_collide_node.argtypes = [C.c_int32] + lib.ora3_collide_node.argtypes
         lib.ora3q_collide_node.restype = C.c_int32
+        lib.ora3q_nee_node.argtypes = [C.c_int32, C.c_double, C.c_double, _dp, _dp, C.c_int32,
+                                       C.c_double, C.c_int32, _dp, _dp, _dp, _dp]
+        lib.ora3_inlet_shape.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32]
+        lib.ora3_inlet_shape.restype = C.c_double
         lib.ora3_pp_force.argtypes = [_dp] + [C.c_double] * 5 + [_dp]
         lib.ora3_pw_force.argtypes = [_dp] + [C.c_double] * 4 + [_dp]
         lib.ora3_body_update.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -139,6 +146,26 @@ def collide_node(tau, rho0, f_dev, phis=(), us=(), G=(0.0, 0.0, 0.0), force_mode
     return int(st), fp, float(rho[0]), u, ust, fb[: 3 * nb].reshape(nb, 3)
 
 
+def nee_node(tau, rho0, f_nb_dev, G=(0.0, 0.0, 0.0), rho_set=None, u_set=None, q=Q):
+    """Non-equilibrium extrapolation at one boundary node from its neighbour's populations:
+    rho_set / u_set prescribe the boundary state, None takes the neighbour's.
+    Returns (fpost_dev, rho_b, u_b)."""
+    fp = np.zeros(q)
+    rb = np.zeros(1)
+    ub = np.zeros(3)
+    us = _f64(u_set if u_set is not None else (0.0, 0.0, 0.0), (3,))
+    _L().ora3q_nee_node(q, tau, rho0, _ptr(_f64(f_nb_dev, (q,))), _ptr(_f64(G, (3,))),
+                        int(rho_set is None), float(rho_set or 0.0), int(u_set is None),
+                        _ptr(us), _ptr(fp), _ptr(rb), _ptr(ub))
+    return fp, float(rb[0]), ub
+
+
+def inlet_shape(params, j, k):
+    """The inlet profile factor of the inlet node (j, k)."""
+    cp = params._c()
+    return float(_L().ora3_inlet_shape(C.byref(cp), int(j), int(k)))
+
+
 def pp_force(d, ri, rj, xi, eps_p, eps_p1):
     out = np.zeros(3)
     _L().ora3_pp_force(_ptr(_f64(d, (3,))), ri, rj, xi, eps_p, eps_p1, _ptr(out))
@@ -178,6 +205,13 @@ class Oracle3Params:
     eps_w1: float = 0.5e4
     xi: float = 1.0
     lattice: int = 19          # 19: D3Q19, 27: D3Q27
+    x_boundary: int = 0        # 1: inlet column x = 0, outlet column x = nx - 1
+    inlet_kind: int = 0        # 0: velocity u_in; 1: density rho_in
+    inlet_profile: int = 0     # 0 uniform; 1 parabolic across y; 2 across y and z
+    outlet_kind: int = 0       # 0: density rho_out; 1: zero gradient
+    u_in: tuple = (0.0, 0.0, 0.0)
+    rho_in: float = 1.0
+    rho_out: float = 1.0
 
     def _c(self):
         p = _Params()
@@ -192,6 +226,11 @@ class Oracle3Params:
         p.eps_p, p.eps_p1, p.eps_w, p.eps_w1, p.xi = (self.eps_p, self.eps_p1, self.eps_w,
                                                       self.eps_w1, self.xi)
         p.lattice = int(self.lattice)
+        p.x_boundary, p.inlet_kind = int(self.x_boundary), int(self.inlet_kind)
+        p.inlet_profile, p.outlet_kind = int(self.inlet_profile), int(self.outlet_kind)
+        for a in range(3):
+            p.u_in[a] = self.u_in[a]
+        p.rho_in, p.rho_out = self.rho_in, self.rho_out
         return p
 
 

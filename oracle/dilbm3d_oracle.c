@@ -17,7 +17,9 @@
  *   term;  Eqs. (16)-(17) velocities;  Eqs. (18)-(19) force and torque (r x F, a
  *   vector);  Eqs. (22)-(24) particle motion (sphere: m = 4/3 pi R^3 rho_s,
  *   I = 2/5 m R^2, isotropic, so the spin update has no gyroscopic term);
- *   Eqs. (28)-(29) repulsion (the same scalar laws along the 3-D centre line).
+ *   Eqs. (28)-(29) repulsion (the same scalar laws along the 3-D centre line); optional
+ *   open ends in x by non-equilibrium extrapolation (Guo, Zheng & Shi 2002), the
+ *   treatment the paper gives its physical boundaries (Section 3).
  * The readings of the two-dimensional oracle carry over: minimum images, the phi cutoff
  * at l = -cutoff*eps, w_b = phi_b min(1, 1/sum phi), solid velocity U + omega x r,
  * Guo-Zheng-Shi forcing for the uniform body force with u* carrying half of it, static
@@ -394,7 +396,62 @@ static int valid_params(const ora3_params *p) {
   if (p->wall_mask && !(p->wall_h > 0.0)) return 0;
   if (p->force_mode != 0 && p->force_mode != 1) return 0;
   if (p->lattice != 0 && !valid_q(p->lattice)) return 0;
+  if (p->x_boundary != 0 && p->x_boundary != 1) return 0;
+  if (p->x_boundary) {
+    if (p->nx < 3 || (p->wall_mask & 2u)) return 0;
+    if ((p->inlet_kind != 0 && p->inlet_kind != 1) || (p->outlet_kind != 0 && p->outlet_kind != 1))
+      return 0;
+    if (p->inlet_profile < 0 || p->inlet_profile > 2) return 0;
+    if (p->inlet_kind == 1 && !(p->rho_in > 0.0)) return 0;
+    if (p->outlet_kind == 0 && !(p->rho_out > 0.0)) return 0;
+  }
   return 1;
+}
+
+/* Non-equilibrium extrapolation (Guo, Zheng & Shi 2002), the treatment the paper gives its
+ * physical boundaries (Section 3): the boundary node takes the equilibrium of its boundary
+ * state plus its neighbour's non-equilibrium part relaxed as in Eq. (13); the neighbour's
+ * velocity carries half the body force, as in its own collision (Eq. (16)). */
+void ora3q_nee_node(int32_t q, double tau, double rho0, const double *f_nb_dev,
+                    const double *G, int32_t rho_from_nb, double rho_set, int32_t u_from_nb,
+                    const double *u_set, double *fpost_dev, double *rho_b, double *u_b) {
+  const int Q = q;
+  double f[QMAX];
+  for (int i = 0; i < Q; ++i) f[i] = f_nb_dev[i] + weight(q, i) * rho0;
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    j[0] += CX[i] * f[i];
+    j[1] += CY[i] * f[i];
+    j[2] += CZ[i] * f[i];
+  }
+  double u_nb[3], ub[3];
+  for (int a = 0; a < 3; ++a) u_nb[a] = (j[a] + 0.5 * G[a]) / rho;
+  const double rb = rho_from_nb ? rho : rho_set;
+  for (int a = 0; a < 3; ++a) ub[a] = u_from_nb ? u_nb[a] : u_set[a];
+  double feq_nb[QMAX], feq_b[QMAX];
+  ora3q_feq(q, rho, u_nb, feq_nb);
+  ora3q_feq(q, rb, ub, feq_b);
+  for (int i = 0; i < Q; ++i)
+    fpost_dev[i] = feq_b[i] + (1.0 - 1.0 / tau) * (f[i] - feq_nb[i]) - weight(q, i) * rho0;
+  if (rho_b) *rho_b = rb;
+  if (u_b)
+    for (int a = 0; a < 3; ++a) u_b[a] = ub[a];
+}
+
+/* parabola 4 s (1 - s) over [a, b) at cell centre c + 1/2, zero outside */
+static double parabola(int32_t c, double a, double b) {
+  const double sv = ((double)c + 0.5 - a) / (b - a);
+  return (sv > 0.0 && sv < 1.0) ? 4.0 * sv * (1.0 - sv) : 0.0;
+}
+
+double ora3_inlet_shape(const ora3_params *p, int32_t j, int32_t k) {
+  if (!p->inlet_profile) return 1.0;
+  const int wy = (p->wall_mask & 1u) != 0, wz = (p->wall_mask & 4u) != 0;
+  double sh = parabola(j, wy ? p->wall_h : 0.0, wy ? p->ny - p->wall_h : (double)p->ny);
+  if (p->inlet_profile == 2)
+    sh *= parabola(k, wz ? p->wall_h : 0.0, wz ? p->nz - p->wall_h : (double)p->nz);
+  return sh;
 }
 
 int32_t ora3_create(const ora3_params *p, ora3_solver **out) {
@@ -515,10 +572,36 @@ static int node_pass(ora3_solver *s, double *fout, double *rho_o, double *ux_o, 
         for (int q = 0; q < Q; ++q) fd[q] = s->f[q * n + node];
         const int64_t e0 = s->off[node];
         const int32_t nb = (int32_t)(s->off[node + 1] - e0);
-        const int st =
+        int st =
             ora3q_collide_node(Q, p->tau, p->rho0, fd, nb, nb ? s->e_phi + e0 : NULL,
                                nb ? s->e_us + 3 * e0 : NULL, p->G, p->force_mode, fp, &rho, u,
                                NULL, nb ? s->e_F + 3 * e0 : NULL);
+        if (p->x_boundary && (i == 0 || i == nx - 1)) {
+          /* inlet / outlet column: its post-collision state comes from the neighbour */
+          const int32_t in = (i == 0);
+          const int64_t nbn = ((int64_t)k * ny + j) * nx + (in ? 1 : nx - 2);
+          double fnb[QMAX], uset[3] = {0.0, 0.0, 0.0};
+          for (int q = 0; q < Q; ++q) fnb[q] = s->f[q * n + nbn];
+          int32_t rho_nb, u_nb;
+          double rset;
+          if (in) {
+            rho_nb = p->inlet_kind == 0;
+            u_nb = p->inlet_kind == 1;
+            rset = p->rho_in;
+            const double sh = ora3_inlet_shape(p, j, k);
+            for (int a = 0; a < 3; ++a) uset[a] = sh * p->u_in[a];
+          } else {
+            rho_nb = p->outlet_kind == 1;
+            u_nb = 1;
+            rset = p->rho_out;
+          }
+          ora3q_nee_node(Q, p->tau, p->rho0, fnb, p->G, rho_nb, rset, u_nb, uset, fp, &rho, u);
+          for (int64_t e = 0; e < 3 * (int64_t)nb; ++e) s->e_F[3 * e0 + e] = 0.0;  /* no force */
+          st = (rho > 0.0 && u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 0.25) ? ORA_OK
+                                                                                : ORA_EUNSTABLE;
+          for (int q = 0; q < Q; ++q)
+            if (!isfinite(fp[q])) st = ORA_EUNSTABLE;
+        }
         if (st != ORA_OK) bad = 1;
         if (rho_o) rho_o[node] = rho;
         if (ux_o) ux_o[node] = u[0];

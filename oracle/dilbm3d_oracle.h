@@ -42,6 +42,16 @@ typedef struct ora3_params {
   int32_t force_mode;      /* 0: momentum-exchange scale; 1: Eq. (18) taken literally */
   double eps_p, eps_p1, eps_w, eps_w1, xi;   /* Eqs. (28)-(29) */
   int32_t lattice;         /* 19 (D3Q19, also 0) or 27 (D3Q27) */
+  /* open ends in x: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) replaces the
+   * post-collision state of the columns x = 0 (inlet) and x = nx - 1 (outlet) */
+  int32_t x_boundary;      /* 0: periodic in x; 1: inlet and outlet columns */
+  int32_t inlet_kind;      /* 0: velocity u_in (rho from the neighbour); 1: density rho_in */
+  int32_t inlet_profile;   /* velocity inlet: 0 uniform; 1 parabolic 4 s (1 - s) across y
+                              (between the y wall slabs, else the full height); 2 the
+                              product of that and the same across z */
+  int32_t outlet_kind;     /* 0: density rho_out (u from the neighbour); 1: zero gradient */
+  double u_in[3];
+  double rho_in, rho_out;
 } ora3_params;
 
 typedef struct ora3_solver ora3_solver;
@@ -69,6 +79,15 @@ int32_t ora3_collide_node(double tau, double rho0, const double *f_dev, int32_t 
                           const double *phi_b, const double *us, const double *G,
                           int32_t force_mode, double *fpost_dev, double *rho_out,
                           double *u_out, double *ustar_out, double *force_b);
+/* Non-equilibrium extrapolation at one boundary node from its neighbour's populations
+ * f_nb_dev (deviations): f*_b = f^eq(rho_b, u_b) + (1 - 1/tau) (f_nb - f^eq(rho_nb, u_nb)),
+ * u_nb = (j_nb + G/2) / rho_nb.  rho_b = rho_nb if rho_from_nb, else rho_set; u_b = u_nb
+ * if u_from_nb, else u_set.  Outputs f*_b - w rho0 and the boundary state. */
+void   ora3q_nee_node(int32_t q, double tau, double rho0, const double *f_nb_dev,
+                      const double *G, int32_t rho_from_nb, double rho_set, int32_t u_from_nb,
+                      const double *u_set, double *fpost_dev, double *rho_b, double *u_b);
+/* the inlet profile factor of node (j, k) (1 for a uniform inlet) */
+double ora3_inlet_shape(const ora3_params *p, int32_t j, int32_t k);
 void   ora3_pp_force(const double *d, double ri, double rj, double xi, double eps_p,
                      double eps_p1, double *F);
 void   ora3_pw_force(const double *d, double r, double xi, double eps_w, double eps_w1,

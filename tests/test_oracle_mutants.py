@@ -23,7 +23,7 @@ SRC3 = os.path.join(ORA, "dilbm3d_oracle.c")
 PINS2 = ["tests/test_oracle_pointwise.py", "tests/test_oracle_solver.py",
          "tests/test_oracle_bodies.py", "tests/test_oracle_boundaries.py"]
 BODIES = ["tests/test_oracle_bodies.py"]
-PINS3 = ["tests/test_oracle3d.py", "tests/test_oracle3d_q27.py"]
+PINS3 = ["tests/test_oracle3d.py", "tests/test_oracle3d_q27.py", "tests/test_oracle3d_open.py"]
 
 # (name, source, text, replacement, pin files that must catch it)
 MUTANTS = [
@@ -98,6 +98,17 @@ MUTANTS = [
      "(n == 2 ? 1.0 / 54.0 : 1.0 / 108.0)", PINS3),
     ("D3Q27 edge and corner weights swapped", SRC3, "(n == 2 ? 1.0 / 54.0 : 1.0 / 216.0)",
      "(n == 2 ? 1.0 / 216.0 : 1.0 / 54.0)", PINS3),
+    ("3-D extrapolation without the relaxation factor", SRC3,
+     "(1.0 - 1.0 / tau) * (f[i] - feq_nb[i]) - weight(q, i) * rho0;",
+     "(f[i] - feq_nb[i]) - weight(q, i) * rho0;", PINS3),
+    ("3-D neighbour velocity without half the body force", SRC3,
+     "u_nb[a] = (j[a] + 0.5 * G[a]) / rho;", "u_nb[a] = j[a] / rho;", PINS3),
+    ("3-D outlet extrapolated from itself", SRC3, "(in ? 1 : nx - 2)", "(in ? 1 : nx - 1)",
+     PINS3),
+    ("3-D duct profile without the z factor", SRC3, "if (p->inlet_profile == 2)",
+     "if (p->inlet_profile == 3)", PINS3),
+    ("3-D inlet takes the neighbour's velocity", SRC3, "u_nb = p->inlet_kind == 1;",
+     "u_nb = 1;", PINS3),
     ("D3Q27 corner direction flipped in z", SRC3,
      "                                 1, -1, -1, 1, 1, -1, 1, -1};",
      "                                 -1, -1, -1, 1, 1, -1, 1, -1};", PINS3),
