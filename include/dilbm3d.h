@@ -35,8 +35,15 @@
  *   - A sphere's mass is rho_s * 4/3 pi R^3 and its moment of inertia 2/5 m R^2; the
  *     spin update has no gyroscopic term (the inertia is isotropic).
  *   - Streaming is periodic on all three axes; walls are static diffuse slabs across
- *     the periodic seams, as in two dimensions.  Open inlet/outlet ends are not
- *     available in three dimensions.
+ *     the periodic seams, as in two dimensions.
+ *   - Open ends in x (x_boundary = DILBM_XBC_INLET_OUTLET, the constants of dilbm.h):
+ *     non-equilibrium extrapolation (Guo, Zheng & Shi 2002), the treatment the paper
+ *     gives its physical boundaries (Section 3), as in two dimensions.  After each
+ *     collision the inlet plane x = 0 and the outlet plane x = nx - 1 take f^eq of their
+ *     boundary state plus (1 - 1/tau) times the non-equilibrium part of the neighbouring
+ *     plane (x = 1, x = nx - 2) at the same step; the neighbour's velocity includes half
+ *     the body force.  The boundary planes exert no force on spheres or walls: keep the
+ *     spheres' supports off the two outermost planes on each side.
  */
 #ifndef DILBM3D_H
 #define DILBM3D_H
@@ -49,7 +56,7 @@
 extern "C" {
 #endif
 
-#define DILBM3D_ABI_VERSION 3u
+#define DILBM3D_ABI_VERSION 4u
 
 enum { DILBM3D_WALL_Y = 1u, DILBM3D_WALL_X = 2u, DILBM3D_WALL_Z = 4u };
 
@@ -73,14 +80,27 @@ typedef struct dilbm3d_params {
   int32_t lattice;             /* 19 (D3Q19; 0 also means 19) or 27 (D3Q27) */
   int32_t storage;             /* DILBM_STORE_FP32 or DILBM_STORE_FP16, as in dilbm.h */
   int32_t fp16_scale_log2;     /* FP16 storage keeps S (f - w rho0) * 2^k; k in [0, 24] */
+  int32_t x_boundary;          /* DILBM_XBC_*; INLET_OUTLET needs nx >= 3, no DILBM3D_WALL_X */
+  int32_t inlet_kind;          /* DILBM_INLET_VELOCITY (inlet_velocity prescribed, rho from
+                                  the neighbour) or DILBM_INLET_PRESSURE (inlet_density
+                                  prescribed, u from the neighbour) */
+  int32_t inlet_profile;       /* velocity inlet: 0 uniform; 1 parabolic 4 s (1 - s) across
+                                  y (between the y wall slabs, else the full height), uniform
+                                  in z; 2 the product of that and the same across z (a duct);
+                                  peak inlet_velocity */
+  int32_t outlet_kind;         /* DILBM_OUTLET_PRESSURE (outlet_density prescribed, u from
+                                  the neighbour) or DILBM_OUTLET_ZERO_GRADIENT (both) */
+  double inlet_velocity[3];
+  double inlet_density;        /* > 0 when used */
+  double outlet_density;       /* > 0 when used */
   int32_t device;              /* HIP device ordinal */
   void *stream;                /* hipStream_t to run on, or NULL for a library-owned one */
 } dilbm3d_params;
 
 /* Fill *p with defaults: abi_version, rho0 = 1, interface_width = 2, phi_cutoff = 4,
  * wall_half_thickness = 4, collision constants 1e4 / 1e4 / 5e3 / 5e3 and xi = 1, FP32
- * storage, fp16_scale_log2 = 10; the caller sets nx, ny, nz and tau.  Returns
- * DILBM_EINVAL for p == NULL. */
+ * storage, fp16_scale_log2 = 10, periodic in x (inlet and outlet densities 1); the
+ * caller sets nx, ny, nz and tau.  Returns DILBM_EINVAL for p == NULL. */
 dilbm_status dilbm3d_params_init(dilbm3d_params *p);
 
 /* Create a solver with the fluid at rest (f = w rho0) and no spheres.  *out receives the
@@ -103,7 +123,7 @@ dilbm_status dilbm3d_set_populations(dilbm3d_solver *s, const double *f_dev);
 dilbm_status dilbm3d_get_populations(dilbm3d_solver *s, double *f_dev);
 
 /* Advance nsteps >= 0 steps (the procedure of Section 2.3 per step: Eqs. (13)-(19) on the
- * fluid, Eqs. (22)-(24) and (28)-(29) on the spheres); synchronous.  The sticky error
+ * fluid, the open ends if any, Eqs. (22)-(24) and (28)-(29) on the spheres); synchronous.  The sticky error
  * flags are checked every 32 steps while later steps run: a solve that becomes unstable
  * (rho <= 0, |u| > 0.5 or a non-finite value) or overflows a tile sphere list stops
  * within 64 steps of the failure, the call returns the error, and the solver refuses
@@ -113,8 +133,8 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps);
 /* Steps taken so far (including those a failed call ran before it stopped). */
 dilbm_status dilbm3d_get_step_count(dilbm3d_solver *s, int64_t *steps);
 
-/* rho and the corrected velocity of Eq. (17) at every node, [nz][ny][nx] each; any
- * pointer may be NULL. */
+/* rho and the corrected velocity of Eq. (17) at every node (the boundary state on the
+ * inlet and outlet planes), [nz][ny][nx] each; any pointer may be NULL. */
 dilbm_status dilbm3d_get_fields(dilbm3d_solver *s, double *rho, double *ux, double *uy,
                                 double *uz);
 

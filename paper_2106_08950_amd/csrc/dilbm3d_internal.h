@@ -124,6 +124,12 @@ struct Desc3 {
   float store_scale, store_inv;  // 2^k and 2^-k (1 for FP32)
   // nodes within h + cutoff*eps of a walled seam: [0, lo) and [hi, n) on each axis
   int32_t wall_lo[3], wall_hi[3];  // axis order x, y, z
+  // open ends in x (non-equilibrium extrapolation at the planes x = 0 and x = nx - 1)
+  int32_t xbc, inlet_kind, inlet_profile, outlet_kind;
+  float u_in[3];      // prescribed inlet velocity (peak of a parabolic profile)
+  float drho_in, drho_out;  // prescribed inlet / outlet density minus rho0
+  // parabolic inlet: s = (c + 1/2 - c0) * inv_h across y (and z for a duct)
+  float prof_y0, prof_inv_hy, prof_z0, prof_inv_hz;
   // FP64 sphere constants
   double rho0_d;
   double gx, gy, gz;

@@ -67,6 +67,7 @@ dilbm_status guard3(std::string *err, F &&f) {
 // directions of the lattice: 19 (D3Q19, also for 0) or 27 (D3Q27)
 int q_of(const dilbm3d_params &p) { return p.lattice == 27 ? 27 : 19; }
 bool fp16_of(const dilbm3d_params &p) { return p.storage == DILBM_STORE_FP16; }
+bool open_of(const dilbm3d_params &p) { return p.x_boundary == DILBM_XBC_INLET_OUTLET; }
 // bytes of one population buffer: q planes of nz * ny rows of row_pitch3 values
 uint64_t pop_half_bytes3(const dilbm3d_params &p) {
   return (uint64_t)q_of(p) * row_pitch3(p.nx, p.storage) * p.ny * p.nz * (fp16_of(p) ? 2 : 4);
@@ -104,6 +105,26 @@ void validate3(const dilbm3d_params *p) {
     fail3(DILBM_EINVAL, "collision constants must be > 0 (xi >= 0)");
   if (p->list_capacity < 0 || p->list_capacity > kMaxListCap3)
     fail3(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
+  if (p->x_boundary != DILBM_XBC_PERIODIC && p->x_boundary != DILBM_XBC_INLET_OUTLET)
+    fail3(DILBM_EINVAL, "unknown x_boundary");
+  if (p->x_boundary == DILBM_XBC_INLET_OUTLET) {
+    if (p->nx < 3) fail3(DILBM_EINVAL, "an inlet and an outlet need nx >= 3");
+    if (p->wall_mask & DILBM3D_WALL_X) fail3(DILBM_EINVAL, "x_boundary excludes DILBM3D_WALL_X");
+    if (p->inlet_kind != DILBM_INLET_VELOCITY && p->inlet_kind != DILBM_INLET_PRESSURE)
+      fail3(DILBM_EINVAL, "unknown inlet_kind");
+    if (p->outlet_kind != DILBM_OUTLET_PRESSURE && p->outlet_kind != DILBM_OUTLET_ZERO_GRADIENT)
+      fail3(DILBM_EINVAL, "unknown outlet_kind");
+    if (p->inlet_profile < 0 || p->inlet_profile > 2) fail3(DILBM_EINVAL, "unknown inlet_profile");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->inlet_velocity[a]))
+        fail3(DILBM_EINVAL, "inlet_velocity must be finite");
+    if (p->inlet_kind == DILBM_INLET_PRESSURE &&
+        !(p->inlet_density > 0.0 && std::isfinite(p->inlet_density)))
+      fail3(DILBM_EINVAL, "inlet_density must be > 0");
+    if (p->outlet_kind == DILBM_OUTLET_PRESSURE &&
+        !(p->outlet_density > 0.0 && std::isfinite(p->outlet_density)))
+      fail3(DILBM_EINVAL, "outlet_density must be > 0");
+  }
 }
 
 struct Mem3 {
@@ -180,7 +201,7 @@ void size_grid3(dilbm3d_solver &s) {
     s.grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_of(s.prm, 256), (int64_t)1 << 30));
     return;
   }
-  const int bpc = std::max(1, collide3_blocks_per_cu(q_of(s.prm), fp16_of(s.prm), s.tile_x));
+  const int bpc = std::max(1, collide3_blocks_per_cu(q_of(s.prm), fp16_of(s.prm), open_of(s.prm), s.tile_x));
   int cus = 0;
   HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device));
   const int64_t T = tiles_of(s.prm, s.tile_x), resident = (int64_t)cus * bpc;
@@ -261,6 +282,24 @@ void fill_desc3(dilbm3d_solver &s) {
     int hi = (int)std::max<double>(0.0, (double)n3[a] - (std::ceil(reach - 0.5) + 1.0));
     d.wall_lo[a] = std::max(0, lo);
     d.wall_hi[a] = std::min(n3[a], hi);
+  }
+  d.xbc = p.x_boundary == DILBM_XBC_INLET_OUTLET ? 1 : 0;
+  d.inlet_kind = p.inlet_kind;
+  d.inlet_profile = p.inlet_profile;
+  d.outlet_kind = p.outlet_kind;
+  for (int a = 0; a < 3; ++a) d.u_in[a] = (float)p.inlet_velocity[a];
+  d.drho_in = (float)(p.inlet_density - p.rho0);
+  d.drho_out = (float)(p.outlet_density - p.rho0);
+  {
+    // parabolic inlet: across the fluid between the wall slabs of an axis, else all of it
+    const bool wy = p.wall_mask & DILBM3D_WALL_Y, wz = p.wall_mask & DILBM3D_WALL_Z;
+    const double h = p.wall_half_thickness;
+    const double y0 = wy ? h : 0.0, y1 = wy ? p.ny - h : (double)p.ny;
+    const double z0 = wz ? h : 0.0, z1 = wz ? p.nz - h : (double)p.nz;
+    d.prof_y0 = (float)y0;
+    d.prof_inv_hy = (float)(1.0 / (y1 - y0));
+    d.prof_z0 = (float)z0;
+    d.prof_inv_hz = (float)(1.0 / (z1 - z0));
   }
   d.rho0_d = p.rho0;
   d.gx = p.gravity[0];
@@ -376,6 +415,9 @@ dilbm_status dilbm3d_params_init(dilbm3d_params *p) {
   p->coll_eps_w_overlap = 0.5e4;
   p->coll_xi = 1.0;
   p->fp16_scale_log2 = 10;
+  p->x_boundary = DILBM_XBC_PERIODIC;
+  p->inlet_density = 1.0;
+  p->outlet_density = 1.0;
   return DILBM_OK;
 }
 
@@ -538,13 +580,13 @@ dilbm_status dilbm3d_step(dilbm3d_solver *s, int64_t nsteps) {
         HIPCHK3(hipEventCreate(&ev.first));
         HIPCHK3(hipEventCreate(&ev.second));
         HIPCHK3(hipEventRecord(ev.first, s->stream));
-        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), open_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
                                 s->steps));
         HIPCHK3(hipEventRecord(ev.second, s->stream));
         s->events.push_back(ev);
         if (s->events.size() >= 4096) collect_timing3(*s);
       } else {
-        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
+        HIPCHK3(launch3_collide(q_of(s->prm), fp16_of(s->prm), open_of(s->prm), s->h.tile_x, s->grid, s->stream, s->d_desc, p,
                                 s->steps));
       }
       HIPCHK3(launch3_bodies(false, s->nb, s->tile_x, s->stream, s->d_desc, p));

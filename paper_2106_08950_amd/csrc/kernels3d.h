@@ -13,12 +13,14 @@ namespace dilbm {
 // one step's collide over all tiles of the solve (parity p); tile_x is the tile width
 // (64: tiles of 64 x 4 x 1 nodes, chunked persistent grid; 256: 256 x 1 x 1, one block
 // per tile)
-// q: the lattice, 19 (D3Q19) or 27 (D3Q27); h: FP16 population storage
-hipError_t launch3_collide(int q, bool h, int tile_x, int grid, hipStream_t stream,
+// q: the lattice, 19 (D3Q19) or 27 (D3Q27); h: FP16 population storage; open: the
+// instance with open ends in x (desc->xbc)
+hipError_t launch3_collide(int q, bool h, bool open, int tile_x, int grid, hipStream_t stream,
                            const Desc3 *desc, int p, int64_t step);
 // blocks of the collide kernel resident on one CU at once (0 on error)
-int collide3_blocks_per_cu(int q, bool h, int tile_x);
-// rho and corrected u of parity p's state into [nz][ny][nx] device arrays
+int collide3_blocks_per_cu(int q, bool h, bool open, int tile_x);
+// rho and corrected u of parity p's state into [nz][ny][nx] device arrays (the boundary
+// state on the planes of open ends)
 hipError_t launch3_fields(int q, bool h, int tile_x, int64_t ntiles, hipStream_t stream,
                           const Desc3 *desc, int p, int64_t step, double *rho, double *ux,
                           double *uy, double *uz);

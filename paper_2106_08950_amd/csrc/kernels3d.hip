@@ -118,9 +118,131 @@ enum Mode3 { kStep3 = 0, kFields3 = 1 };
 template <int L>
 constexpr int kStash3 = L == 27 ? DILBM3D27_STASH : L;
 
+// Non-equilibrium extrapolation (Guo, Zheng & Shi 2002; the treatment the paper gives its
+// physical boundaries, Section 3) at a node of the inlet plane x = 0 or the outlet plane
+// x = nx - 1: the neighbour on the plane x = 1 or nx - 2 is pulled as in its own step
+// (its sources x - c_i stay inside [0, nx)), its rho and u (with half the body force, as
+// in its collision) give its equilibrium, and the boundary state (prescribed or the
+// neighbour's) gives the boundary node's; OUT: the boundary node's post-collision
+// populations g_i* = geq_i(boundary) + (1 - 1/tau) (g_i(neighbour) - geq_i(neighbour)),
+// in g units and the frame Vf (FP16: at the stored scale, rounded stochastically with the
+// node's own random bits), are stored to the other buffer (rd) here, each as it is formed.
+// The frame constants cancel in the non-equilibrium part.  Called after the tile's own
+// stores, so the collision's outputs are no longer held in registers.
+template <int L, bool H, bool OUT>
+__device__ __forceinline__ void nee3(const Desc3 &d, const __amdgpu_buffer_rsrc_t rs,
+                                     const __amdgpu_buffer_rsrc_t rd,
+                                     const uint32_t (&row)[3][3], const uint32_t pb,
+                                     const int xc, const int yc, const int z, const int64_t t,
+                                     const float3 Vt, const float3 Vf, float &rho_b, float &ubx,
+                                     float &uby, float &ubz) {
+  constexpr uint32_t es = H ? 2u : 4u;
+  const bool inlet = xc == 0;
+  const int xn = inlet ? 1 : d.nx - 2;
+  const uint32_t v0 = (uint32_t)xn * es, vm = (uint32_t)(xn - 1) * es;
+  const uint32_t vp = (uint32_t)(xn + 1) * es;
+  float g[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const uint32_t v = C3X[i] == 0 ? v0 : (C3X[i] > 0 ? vm : vp);
+    const uint32_t so = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
+    if (H)
+      g[i] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, v, so, 0)) *
+             d.store_inv;
+    else
+      g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, so, 0));
+  }
+  if (!H) {  // to the frame of the outputs
+    const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
+#pragma unroll
+    for (int i = 1; i < L; ++i)
+      g[i] -= (3.0f * kw3<L>(i)) *
+              ((float)C3X[i] * dvx + (float)C3Y[i] * dvy + (float)C3Z[i] * dvz);
+  }
+  constexpr float S = Lat3<L>::S, invS = 1.0f / S, halfS = 0.5f * S;
+  float D = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    D += g[i];
+    if (C3X[i]) Jx += C3X[i] > 0 ? g[i] : -g[i];
+    if (C3Y[i]) Jy += C3Y[i] > 0 ? g[i] : -g[i];
+    if (C3Z[i]) Jz += C3Z[i] > 0 ? g[i] : -g[i];
+  }
+  const float R = S * d.rho0 + D;
+  const float rho_n = R * invS, drho_n = D * invS;
+  float Rinv = __builtin_amdgcn_rcpf(R);
+  Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
+  // S rho u_nb = S (j + G/2), in the fixed frame
+  const float V36x = S * Vf.x, V36y = S * Vf.y, V36z = S * Vf.z;
+  const float Jgx = Jx + (V36x + halfS * d.Gx), Jgy = Jy + (V36y + halfS * d.Gy);
+  const float Jgz = Jz + (V36z + halfS * d.Gz);
+  const float unx = Jgx * Rinv, uny = Jgy * Rinv, unz = Jgz * Rinv;
+  float drho_b = drho_n;
+  ubx = unx;
+  uby = uny;
+  ubz = unz;
+  if (inlet) {
+    if (d.inlet_kind == 0) {  // velocity inlet: rho from the neighbour
+      float sh = 1.0f;
+      if (d.inlet_profile >= 1) {
+        const float sy = ((float)yc + 0.5f - d.prof_y0) * d.prof_inv_hy;
+        sh = (sy > 0.0f && sy < 1.0f) ? 4.0f * sy * (1.0f - sy) : 0.0f;
+        if (d.inlet_profile == 2) {
+          const float sz = ((float)z + 0.5f - d.prof_z0) * d.prof_inv_hz;
+          sh *= (sz > 0.0f && sz < 1.0f) ? 4.0f * sz * (1.0f - sz) : 0.0f;
+        }
+      }
+      ubx = sh * d.u_in[0];
+      uby = sh * d.u_in[1];
+      ubz = sh * d.u_in[2];
+    } else {
+      drho_b = d.drho_in;
+    }
+  } else if (d.outlet_kind == 0) {
+    drho_b = d.drho_out;
+  }
+  rho_b = d.rho0 + drho_b;
+  if (!OUT) return;
+  // rho u - V for the neighbour (rho u_nb = j + G/2) and for the boundary state
+  const float mnx = (Jgx - V36x) * invS, mny = (Jgy - V36y) * invS, mnz = (Jgz - V36z) * invS;
+  const float mbx = rho_b * ubx - Vf.x, mby = rho_b * uby - Vf.y, mbz = rho_b * ubz - Vf.z;
+  const float uun = unx * unx + uny * uny + unz * unz, uub = ubx * ubx + uby * uby + ubz * ubz;
+  const float keep = 1.0f - d.omega;  // 1 - 1/tau
+  const float scale = H ? d.store_scale : 1.0f;
+  // FP16: the random words of the node's own stochastic rounding (as in tile3)
+  uint32_t hw = 0;
+  if (H) {
+    const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
+    hw = lowbias32((((uint32_t)z * (uint32_t)d.ny + (uint32_t)yc) * (uint32_t)d.nx +
+                    (uint32_t)xc) ^ tk);
+  }
+  const uint32_t vo = (uint32_t)xc * es, so0 = row[1][1];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
+    const float K = kw3<L>(i);
+    const float cun = cx * unx + cy * uny + cz * unz, cub = cx * ubx + cy * uby + cz * ubz;
+    const float eqn = K * (drho_n + 3.0f * (cx * mnx + cy * mny + cz * mnz) +
+                           rho_n * (4.5f * cun * cun - 1.5f * uun));
+    const float eqb = K * (drho_b + 3.0f * (cx * mbx + cy * mby + cz * mbz) +
+                           rho_b * (4.5f * cub * cub - 1.5f * uub));
+    const float o = scale * (eqb + keep * (g[i] - eqn));
+    const uint32_t so = (uint32_t)i * pb + so0;
+    if (H) {
+      if (i > 0 && (i & 1) == 0) hw = xorshift32(hw);
+      __builtin_amdgcn_raw_buffer_store_b16(
+          sr_half(o, (i & 1) ? __builtin_amdgcn_alignbit(hw, hw, 13) : hw), rd, vo, so, 0);
+    } else {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), rd, vo, so, 0);
+    }
+  }
+}
+
 // One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
-template <int MODE, int TX, int L, bool H>
+// OPEN: the instance handles open ends in x (d.xbc; the lanes of the two boundary planes
+// take non-equilibrium extrapolation, nee3, and contribute no solid-field force).
+template <int MODE, int TX, int L, bool H, bool OPEN>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
                                       const int64_t t, float (*red)[6][64], float *stash,
                                       double *__restrict__ out_rho, double *__restrict__ out_ux,
@@ -143,6 +265,9 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const int y = __builtin_amdgcn_readfirstlane(y0 + tid / TX);  // a wave is part of one row
   const bool valid = x < nx && y < ny;
   const int xc = min(x, nx - 1), yc = min(y, ny - 1);
+  // a node of the inlet or outlet plane: its state comes from its neighbour (nee3)
+  const bool bnd = OPEN && d.xbc && valid && (x == 0 || x == nx - 1);
+  const bool own = valid && !bnd;  // a node whose solid field this tile computes
 
   // ---- pull streaming: f_i(x, t) = f_i*(x - c_i, t - 1) ------------------------------
   // one buffer resource per population buffer; the row of every direction is
@@ -210,8 +335,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   int64_t tc = t;
   asm volatile("" : "+s"(tc));
   float3 Vf = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(tc);  // FP16: no frame
+  const float3 Vt = Vf;
   if (MODE == kStep3 && !H) {
-    const float3 Vt = Vf;
     Vf = ref_velocity3<L>(tc + 1);
     const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
 #pragma unroll
@@ -310,7 +435,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     float S = 0.f;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      if (valid && lw[a] >= lcut) S += phi_of(lw[a], phik);
+      if (own && lw[a] >= lcut) S += phi_of(lw[a], phik);
     // the wave's six sums of one sphere's force and torque, by a transpose through its own
     // LDS rows: each lane stores its six values, lanes 8k..8k+7 add the 64 values of
     // component k (eight each, in FP64), three DPP steps combine the eight, and one atomic
@@ -346,7 +471,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       const float rz = (float)min_image(zn - sj.z, dnz);
       const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
       float fx = 0.f, fy = 0.f, fz = 0.f;
-      if (valid && l >= lcut) {
+      if (own && l >= lcut) {
         const float w = phi_of(l, phik);
         S += w;
         // rigid-body velocity of the solid at the node: U + omega x r
@@ -384,7 +509,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     Mxz *= scale;
     Myz *= scale;
     // where S > 1 the forces above took phi_b for w_b: add (scale - 1) times them
-    if (MODE == kStep3 && __ballot(valid && S > 1.0f) != 0) {
+    if (MODE == kStep3 && __ballot(own && S > 1.0f) != 0) {
       const float c = scale - 1.0f;  // 0 where S <= 1
       for (int j = 0; j < nb; ++j) {
         int e;
@@ -395,7 +520,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         const float rz = (float)min_image(zn - sj.z, dnz);
         const float l = sj.r - __builtin_amdgcn_sqrtf(rx * rx + ry * ry + rz * rz);
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        if (valid && c != 0.0f && l >= lcut) {
+        if (own && c != 0.0f && l >= lcut) {
           const float w = phi_of(l, phik);
           const float vx = sj.u + (sj.oy * rz - sj.oz * ry);
           const float vy = sj.v + (sj.oz * rx - sj.ox * rz);
@@ -413,7 +538,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       float fx = 0.f, fy = 0.f, fz = 0.f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (valid && lw[a] >= lcut) {
+        if (own && lw[a] >= lcut) {
           const float w = scale * phi_of(lw[a], phik);
           Phi += w;
           const float k = kap * w * rho;
@@ -447,12 +572,14 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const float ux = Mx * Rinv, uy = My * Rinv, uz = Mz * Rinv;
 
   if (MODE == kFields3) {
+    float ro = rho, vx = ux, vy = uy, vz = uz;
+    if (OPEN && bnd) nee3<L, H, false>(d, rs, rs, row, pb, xc, yc, z, t, Vt, Vf, ro, vx, vy, vz);
     if (valid) {
       const int64_t o = ((int64_t)z * ny + y) * nx + x;
-      out_rho[o] = (double)rho;
-      out_ux[o] = (double)ux;
-      out_uy[o] = (double)uy;
-      out_uz[o] = (double)uz;
+      out_rho[o] = (double)ro;
+      out_ux[o] = (double)vx;
+      out_uy[o] = (double)vy;
+      out_uz[o] = (double)vz;
     }
     return;
   }
@@ -511,7 +638,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   }
 
   const float vv = ux * ux + uy * uy + uz * uz;
-  if (__ballot(valid && !(rho > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
+  if (__ballot(own && !(rho > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
     atomicOr(d.err, (int32_t)kErrUnstable);
   uint16_t hb[L];  // FP16: the stochastically rounded halves
   if (H) {
@@ -526,7 +653,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       hb[i] = sr_half(out[i], (i & 1) ? __builtin_amdgcn_alignbit(hw, hw, 13) : hw);
     }
   }
-  if (valid) {
+  if (own) {
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
         (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
     const uint32_t s0r = row[1][1];
@@ -546,9 +673,19 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     else
       put_all(std::false_type{});
   }
+  if constexpr (OPEN) {
+    if (bnd) {  // the lanes of the inlet and outlet planes
+      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
+      float rb, bx, by, bz;
+      nee3<L, H, true>(d, rs, rd, row, pb, xc, yc, z, t, Vt, Vf, rb, bx, by, bz);
+      if (!(rb > 0.0f && bx * bx + by * by + bz * bz <= 0.25f))
+        atomicOr(d.err, (int32_t)kErrUnstable);
+    }
+  }
 }
 
-template <int TX, int L, bool H>
+template <int TX, int L, bool H, bool OPEN>
 __global__ __launch_bounds__(256, (H ? DILBM3D_COLLIDE_WAVES_F16
                                      : (L == 19 ? DILBM3D_COLLIDE_WAVES
                                                 : DILBM3D27_COLLIDE_WAVES)))
@@ -560,7 +697,8 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
     // whole-row tiles: tile b to block b, so neighbouring row segments run on the eight
     // XCDs at once
     for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-      tile3<kStep3, TX, L, H>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
+      tile3<kStep3, TX, L, H, OPEN>(d, t, p, step, red, stash, nullptr, nullptr, nullptr,
+                                    nullptr);
     return;
   }
   const WorkSplit ws = xcd_split(d.ntiles);
@@ -569,7 +707,8 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   const bool rev = (blockIdx.x >> 3) & 1;
   for (int64_t i = ws.begin; i < ws.end; ++i) {
     const int64_t t = rev ? ws.end - 1 - (i - ws.begin) : i;
-    tile3<kStep3, TX, L, H>(d, t, p, step, red, stash, nullptr, nullptr, nullptr, nullptr);
+    tile3<kStep3, TX, L, H, OPEN>(d, t, p, step, red, stash, nullptr, nullptr, nullptr,
+                                  nullptr);
   }
 }
 
@@ -581,7 +720,7 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
                                                  double *__restrict__ uz) {
   const Desc3 &d = *desc;
   for (int64_t t = blockIdx.x; t < d.ntiles; t += gridDim.x)
-    tile3<kFields3, TX, L, H>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
+    tile3<kFields3, TX, L, H, true>(d, t, p, step, nullptr, nullptr, rho, ux, uy, uz);
 }
 
 // One block per sphere.  BIN_ONLY: bin the spheres of the current state into list set 0
@@ -874,25 +1013,27 @@ int grid_for(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min
 }  // namespace
 
 using Collide3 = void (*)(const Desc3 *, int, int64_t);
-template <bool H>
+template <bool H, bool O>
 static Collide3 collide3_kernel_of(int q, int tile_x) {
-  if (q == 27) return tile_x == 256 ? &k3_collide<256, 27, H> : &k3_collide<64, 27, H>;
-  return tile_x == 256 ? &k3_collide<256, 19, H> : &k3_collide<64, 19, H>;
+  if (q == 27) return tile_x == 256 ? &k3_collide<256, 27, H, O> : &k3_collide<64, 27, H, O>;
+  return tile_x == 256 ? &k3_collide<256, 19, H, O> : &k3_collide<64, 19, H, O>;
 }
-static Collide3 collide3_kernel(int q, bool h, int tile_x) {
-  return h ? collide3_kernel_of<true>(q, tile_x) : collide3_kernel_of<false>(q, tile_x);
+static Collide3 collide3_kernel(int q, bool h, int tile_x, bool open) {
+  if (open)
+    return h ? collide3_kernel_of<true, true>(q, tile_x) : collide3_kernel_of<false, true>(q, tile_x);
+  return h ? collide3_kernel_of<true, false>(q, tile_x) : collide3_kernel_of<false, false>(q, tile_x);
 }
 
-hipError_t launch3_collide(int q, bool h, int tile_x, int grid, hipStream_t stream,
+hipError_t launch3_collide(int q, bool h, bool open, int tile_x, int grid, hipStream_t stream,
                            const Desc3 *desc, int p, int64_t step) {
-  hipLaunchKernelGGL(collide3_kernel(q, h, tile_x), dim3(grid), dim3(256), 0, stream, desc, p,
-                     step);
+  hipLaunchKernelGGL(collide3_kernel(q, h, tile_x, open), dim3(grid), dim3(256), 0, stream,
+                     desc, p, step);
   return hipGetLastError();
 }
 
-int collide3_blocks_per_cu(int q, bool h, int tile_x) {
+int collide3_blocks_per_cu(int q, bool h, bool open, int tile_x) {
   int n = 0;
-  const void *f = reinterpret_cast<const void *>(collide3_kernel(q, h, tile_x));
+  const void *f = reinterpret_cast<const void *>(collide3_kernel(q, h, tile_x, open));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) return 0;
   return n;
 }

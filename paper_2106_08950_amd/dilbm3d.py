@@ -14,7 +14,7 @@ import numpy as np
 from . import dilbm
 
 Q = 19
-ABI_VERSION = 3
+ABI_VERSION = 4
 WALL_Y, WALL_X, WALL_Z = 1, 2, 4
 
 EXPORTED = [
@@ -40,6 +40,9 @@ class dilbm3d_params(C.Structure):
         ("coll_xi", C.c_double),
         ("list_capacity", C.c_int32), ("lattice", C.c_int32), ("storage", C.c_int32),
         ("fp16_scale_log2", C.c_int32),
+        ("x_boundary", C.c_int32), ("inlet_kind", C.c_int32), ("inlet_profile", C.c_int32),
+        ("outlet_kind", C.c_int32), ("inlet_velocity", C.c_double * 3),
+        ("inlet_density", C.c_double), ("outlet_density", C.c_double),
         ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -105,6 +108,13 @@ class Params3D:
     lattice: int = 19          # 19: D3Q19, 27: D3Q27
     storage: int = 0           # 0: FP32 populations, 1: FP16 (dilbm.STORE_FP16)
     fp16_scale_log2: int = 10
+    x_boundary: int = 0        # dilbm.XBC_*: 1 = inlet plane x = 0, outlet plane x = nx - 1
+    inlet_kind: int = 0        # dilbm.INLET_VELOCITY or dilbm.INLET_PRESSURE
+    inlet_profile: int = 0     # 0 uniform; 1 parabolic across y; 2 across y and z
+    outlet_kind: int = 0       # dilbm.OUTLET_PRESSURE or dilbm.OUTLET_ZERO_GRADIENT
+    inlet_velocity: tuple = (0.0, 0.0, 0.0)
+    inlet_density: float = 1.0
+    outlet_density: float = 1.0
     device: int = 0
     stream: int = 0
     abi_version: int = ABI_VERSION
@@ -129,6 +139,11 @@ class Params3D:
         p.lattice = int(self.lattice)
         p.storage = int(self.storage)
         p.fp16_scale_log2 = int(self.fp16_scale_log2)
+        p.x_boundary, p.inlet_kind = int(self.x_boundary), int(self.inlet_kind)
+        p.inlet_profile, p.outlet_kind = int(self.inlet_profile), int(self.outlet_kind)
+        for a in range(3):
+            p.inlet_velocity[a] = float(self.inlet_velocity[a])
+        p.inlet_density, p.outlet_density = float(self.inlet_density), float(self.outlet_density)
         p.device = int(self.device)
         p.stream = int(self.stream) or None
         return p

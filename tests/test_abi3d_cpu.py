@@ -37,6 +37,7 @@ def test_params_defaults():
         1.0e4, 1.0e4, 0.5e4, 0.5e4, 1.0)
     assert (p.list_capacity, p.device, p.wall_mask) == (0, 0, 0)
     assert (p.storage, p.fp16_scale_log2) == (dilbm.STORE_FP32, 10)
+    assert (p.x_boundary, p.inlet_density, p.outlet_density) == (dilbm.XBC_PERIODIC, 1.0, 1.0)
     assert p.stream is None
     assert lib.dilbm3d_params_init(None) == dilbm.EINVAL
 
@@ -48,6 +49,13 @@ def test_params_defaults():
     dict(list_capacity=5000), dict(coll_xi=-1.0), dict(coll_eps_p=0.0), dict(storage=2),
     dict(fp16_scale_log2=30), dict(fp16_scale_log2=-1),
     dict(body_force=(0.0, float("inf"), 0.0)), dict(gravity=(0.0, 0.0, float("nan"))),
+    # open ends in x
+    dict(x_boundary=2), dict(x_boundary=1, nx=2), dict(x_boundary=1, wall_mask=2),
+    dict(x_boundary=1, inlet_kind=2), dict(x_boundary=1, outlet_kind=2),
+    dict(x_boundary=1, inlet_profile=3), dict(x_boundary=1, inlet_profile=-1),
+    dict(x_boundary=1, inlet_velocity=(float("nan"), 0.0, 0.0)),
+    dict(x_boundary=1, inlet_kind=1, inlet_density=0.0),
+    dict(x_boundary=1, outlet_density=-1.0),
 ])
 def test_create_rejects_bad_params_before_device(bad):
     kw = dict(nx=32, ny=32, nz=32, tau=0.8)
