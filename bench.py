@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--legs fp32,fp16,open_ends,suspension3d,suspension3d_q27,
-                            suspension3d_fp16,batched,served]
+                            suspension3d_fp16,open_ends3d,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -36,6 +36,8 @@ Further legs, reported in the same JSON line:
   (seed 8), FP32 (152 B per node update);
 * suspension3d_q27: the same on the D3Q27 lattice (216 B per node update);
 * suspension3d_fp16: the D3Q19 suspension with FP16 storage (76 B per node update);
+* open_ends3d: a 256^3 D3Q19 duct (diffuse walls in y and z) with a parabolic velocity
+  inlet and a density outlet, past 200 fixed spheres, FP32;
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -225,14 +227,15 @@ def single_solve(wl, storage, steps, warmup, tile, stream, bytes_per_node, traff
             "roofline": roofline(bytes_per_node, wl.nodes, ms, traffic, "k_collide", copy_gbs)}
 
 
-def suspension3d_leg(steps, warmup, stream, q=19, storage=0):
-    """The three-dimensional path: 256^3 periodic nodes with 400 free spheres, on D3Q19
-    (19 x 4 bytes read + 19 x 4 written = 152 B per node update in FP32, 76 B in FP16) or
-    D3Q27 (216 B in FP32)."""
+def suspension3d_leg(steps, warmup, stream, q=19, storage=0, w3=None):
+    """The three-dimensional path: 256^3 periodic nodes with 400 free spheres (or w3), on
+    D3Q19 (19 x 4 bytes read + 19 x 4 written = 152 B per node update in FP32, 76 B in
+    FP16) or D3Q27 (216 B in FP32)."""
     from paper_2106_08950_amd import dilbm3d, inputs3d
 
     es = 2 if storage == 1 else 4
-    w3 = inputs3d.suspension3d()
+    periodic = w3 is None
+    w3 = inputs3d.suspension3d() if periodic else w3
     s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w3, device=0, stream=stream.cuda_stream,
                                                       lattice=q, storage=storage))
     s.set_particles(w3.pos, w3.radius, w3.density, w3.vel, w3.omega, w3.fixed)
@@ -243,7 +246,8 @@ def suspension3d_leg(steps, warmup, stream, q=19, storage=0):
     ms = launch_pass(s, max(steps, 100))
     s.close()
     dt = statistics.median(runs)
-    counters = {(19, 0): COUNTERS3, (27, 0): COUNTERS3_27, (19, 1): COUNTERS3_16}.get((q, storage))
+    counters = {(19, 0): COUNTERS3, (27, 0): COUNTERS3_27,
+                (19, 1): COUNTERS3_16}.get((q, storage)) if periodic else None
     return {"workload": w3.name, "lattice": f"D3Q{q}", "storage": "fp16" if storage else "fp32",
             "value": round(w3.nodes * steps / dt / 1e6, 1),
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
@@ -408,7 +412,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,suspension3d_q27,"
-                                      "suspension3d_fp16,batched,served")
+                                      "suspension3d_fp16,open_ends3d,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--served-count", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -475,6 +479,12 @@ def main():
         log("suspension3d FP16")
         out["suspension3d_fp16"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup,
                                                     stream, q=19, storage=1)
+    if "open_ends3d" in legs:
+        log("open ends 3-D")
+        from paper_2106_08950_amd import inputs3d
+
+        out["open_ends3d"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup, stream,
+                                              w3=inputs3d.inflow_duct3d())
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

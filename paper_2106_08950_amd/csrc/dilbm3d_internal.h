@@ -18,7 +18,7 @@
 //   bconst        sphere constants SoA [5][nb]: radius, rho_s, mass, inertia, fixed
 //   bsnap[2]      per sphere, what the collide kernel reads of it (SphereSnap, 64 B),
 //                 written with every sphere update
-//   acc[2]        FP64 accumulators [(nb + 1) * 6]: force (3) and torque (3) per sphere,
+//   acc[2]        FP64 accumulators [acc_words(nb, 6)]: force (3) and torque (3) per sphere,
 //                 then the wall force in the last slot
 //   err           sticky error bits (kErrUnstable, kErrCapacity, kErrInternal)
 // Everything else double-buffered is indexed by the step parity p: a step with parity p
@@ -111,6 +111,7 @@ struct Desc3 {
   // FP32 node-update constants
   float omega;        // 1 / tau
   float khalf;        // 1 - 1/(2 tau)
+  float inv_khalf;    // 1 / khalf
   float rho0;
   float Gx, Gy, Gz;
   float cg[kQ3Max / 2];  // c_i.G for the direction pairs (2k + 1, 2k + 2)

@@ -26,8 +26,8 @@
 //   bxy[2]        per body, (x, y) rounded to FP32, written with the snapshot: the pair
 //                 search reads 8 bytes per partner and takes the FP64 state only for
 //                 partners within reach
-//   acc[2]        FP64 force accumulators [(nb + 1) * 3]: Fx, Fy, T per body, then the
-//                 wall force in the last slot
+//   acc[2]        FP64 force accumulators: Fx, Fy, T per body ([nb * 3]), then the wall
+//                 force in kWallSlots slots of one 128-byte line each (acc_words)
 //   err           sticky error bits
 // Everything else double-buffered is indexed by the step parity p: a step with parity p
 // reads slot p and writes slot 1 - p (bodies, snapshots, force sums) or both (populations).
@@ -102,6 +102,21 @@ constexpr double kNbrSkin = 2.0;
 // per step, so until the rebuild every node within R + support of it lies in a listed
 // tile.
 constexpr double kBinSkin = 2.0;
+
+// The force on the walls is summed over kWallSlots accumulators, one 128-byte line each,
+// chosen by the block index: with a single accumulator every wave of a walled solve adds
+// to one address and the atomics serialize (a 256^3 duct with walls across y and z took
+// 1450 us per collide launch instead of 450).  wall_base(w): the first word of the slots
+// after w per-body words; acc_words(nb, k): one accumulator buffer for nb bodies of k
+// words each.
+constexpr int kWallSlots = 64;
+constexpr int kWallSlotWords = 16;
+__host__ __device__ constexpr int64_t wall_base(int64_t body_words) {
+  return (body_words + kWallSlotWords - 1) / kWallSlotWords * kWallSlotWords;
+}
+__host__ __device__ constexpr int64_t acc_words(int64_t nb, int k) {
+  return wall_base(nb * k) + (int64_t)kWallSlots * kWallSlotWords;
+}
 
 // One body as the collide kernel sees it at a step: position (FP64, so that node - centre
 // differences keep FP64 accuracy before they are rounded), rigid velocity, spin and radius.

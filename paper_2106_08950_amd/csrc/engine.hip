@@ -243,7 +243,7 @@ BodyLayout body_layout(const dilbm_params &p, int nb) {
   L.bxy = o;
   o += align_up(2 * 2 * (uint64_t)std::max(nb, 1) * 4);
   L.acc = o;
-  o += align_up(2 * 3 * (uint64_t)(nb + 1) * 8);
+  o += align_up(2 * (uint64_t)acc_words(nb, 3) * 8);
   L.nbr_cnt = o;
   o += align_up(4 * (uint64_t)std::max(nb, 1));
   L.nbr_list = o;
@@ -394,7 +394,7 @@ void fill_desc(Solve &s) {
   d.bxy[0] = (float *)(bb + s.L.bxy);
   d.bxy[1] = d.bxy[0] + 2 * nbs;
   d.acc[0] = (double *)(bb + s.L.acc);
-  d.acc[1] = d.acc[0] + 3 * (uint64_t)(s.nb + 1);
+  d.acc[1] = d.acc[0] + acc_words(s.nb, 3);
   d.nbr_cnt = (int32_t *)(bb + s.L.nbr_cnt);
   d.nbr_list = (int32_t *)(bb + s.L.nbr_list);
   d.nbr_ref = (double *)(bb + s.L.nbr_ref);
@@ -1002,7 +1002,7 @@ void upload_bodies(Solve &s, hipStream_t st, const double *pos, const double *ve
     HIPCHK(hipMemcpyAsync((void *)s.desc.bconst, cst.data(), sizeof(double) * 5 * nb,
                           hipMemcpyHostToDevice, st));
   }
-  HIPCHK(launch_fill_f64(s.desc.acc[0], 2 * 3 * (int64_t)(nb + 1), 0.0, st));
+  HIPCHK(launch_fill_f64(s.desc.acc[0], 2 * acc_words(nb, 3), 0.0, st));
   HIPCHK(hipStreamSynchronize(st));  // the host vectors die here
 }
 
@@ -1039,9 +1039,9 @@ void get_particles_of(Solve &s, hipStream_t st, double *pos, double *vel, double
 
 void get_forces_of(Solve &s, hipStream_t st, double *force, double *torque, double *wall) {
   const int nb = s.nb;
-  std::vector<double> h(3 * (size_t)(nb + 1), 0.0);
+  std::vector<double> h((size_t)acc_words(nb, 3), 0.0);
   if (s.forces_valid && s.steps_done > 0)
-    d2h(h.data(), s.desc.acc[(s.steps_done - 1) & 1], sizeof(double) * 3 * (nb + 1), st);
+    d2h(h.data(), s.desc.acc[(s.steps_done - 1) & 1], sizeof(double) * h.size(), st);
   for (int b = 0; b < nb; ++b) {
     if (force) {
       force[2 * b] = h[3 * b];
@@ -1049,9 +1049,12 @@ void get_forces_of(Solve &s, hipStream_t st, double *force, double *torque, doub
     }
     if (torque) torque[b] = h[3 * b + 2];
   }
-  if (wall) {
-    wall[0] = h[3 * nb];
-    wall[1] = h[3 * nb + 1];
+  if (wall) {  // the sum of the wall slots
+    wall[0] = wall[1] = 0.0;
+    for (int k = 0; k < kWallSlots; ++k) {
+      wall[0] += h[wall_base(3 * nb) + k * kWallSlotWords];
+      wall[1] += h[wall_base(3 * nb) + k * kWallSlotWords + 1];
+    }
   }
 }
 

@@ -218,7 +218,7 @@ void body_layout3(dilbm3d_solver &s, int n) {
   const uint64_t nn = (uint64_t)std::max(n, 1);
   uint64_t off[8], o = 0;
   const uint64_t sizes[8] = {2 * T * 8, 2 * T * (uint64_t)cap * 4, 2 * 9 * nn * 8, 5 * nn * 8,
-                             2 * nn * sizeof(SphereSnap), 2 * 6 * (uint64_t)(n + 1) * 8,
+                             2 * nn * sizeof(SphereSnap), 2 * (uint64_t)acc_words(n, 6) * 8,
                              4 * 4, 3 * nn * 8};
   for (int k = 0; k < 8; ++k) {
     off[k] = o;
@@ -258,6 +258,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.list_cap = s.cap;
   d.omega = (float)(1.0 / p.tau);
   d.khalf = (float)(1.0 - 0.5 / p.tau);
+  d.inv_khalf = (float)(1.0 / (1.0 - 0.5 / p.tau));
   d.rho0 = (float)p.rho0;
   d.Gx = (float)p.body_force[0];
   d.Gy = (float)p.body_force[1];
@@ -330,7 +331,7 @@ void fill_desc3(dilbm3d_solver &s) {
   d.lsel = (int32_t *)(bb + s.off_lsel);
   d.rb_flag = d.lsel + 2;
   d.bin_ref = (double *)(bb + s.off_bref);
-  d.acc[1] = d.acc[0] + 6 * (uint64_t)(s.nb + 1);
+  d.acc[1] = d.acc[0] + acc_words(s.nb, 6);
   d.err = s.d_err;
 }
 
@@ -667,10 +668,13 @@ dilbm_status dilbm3d_get_wall_force(dilbm3d_solver *s, double *force) {
   return guard3(&s->last_error, [&] {
     HIPCHK3(hipSetDevice(s->device));
     double a[3] = {0.0, 0.0, 0.0};
-    if (s->steps) {
-      HIPCHK3(hipMemcpyAsync(a, s->h.acc[s->parity ^ 1] + 6 * (size_t)s->nb, sizeof(a),
-                             hipMemcpyDeviceToHost, s->stream));
+    if (s->steps) {  // the sum of the wall slots
+      std::vector<double> w((size_t)kWallSlots * kWallSlotWords);
+      HIPCHK3(hipMemcpyAsync(w.data(), s->h.acc[s->parity ^ 1] + wall_base(6 * s->nb),
+                             sizeof(double) * w.size(), hipMemcpyDeviceToHost, s->stream));
       HIPCHK3(hipStreamSynchronize(s->stream));
+      for (int k = 0; k < kWallSlots; ++k)
+        for (int c = 0; c < 3; ++c) a[c] += w[(size_t)k * kWallSlotWords + c];
     }
     for (int c = 0; c < 3; ++c) force[c] = a[c];
   });

@@ -486,7 +486,7 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
       d.tile_head[ls ^ 1][2 * (int64_t)lt] = 0;
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
-      for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+      for (int i = tid, na = (int)acc_words(d.nbodies, 3); i < na; i += kBlockThreads) a[i] = 0.0;
       if (tid == 0) {  // read by the last body step, raised by the next
         d.nl_flag[p ^ 1] = 0;
         d.rb_flag[p ^ 1] = 0;
@@ -684,8 +684,9 @@ __device__ __forceinline__ void process_tile(const SolveDesc &d, const int lt, c
         const double sx = wave_sum((double)fx);
         const double sy = wave_sum((double)fy);
         if (lane == 0) {
-          unsafeAtomicAdd(&acc[3 * nbs], sx);
-          unsafeAtomicAdd(&acc[3 * nbs + 1], sy);
+          double *wa = acc + wall_base(3 * nbs) + (blockIdx.x % kWallSlots) * kWallSlotWords;
+          unsafeAtomicAdd(wa, sx);
+          unsafeAtomicAdd(wa + 1, sy);
         }
       }
     }
@@ -932,7 +933,7 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
     d.tile_head[ls ^ 1][2 * (int64_t)lt] = 0;
   if (lt == 0) {
     double *a = d.acc[p ^ 1];
-    for (int i = tid; i < 3 * (d.nbodies + 1); i += kBlockThreads) a[i] = 0.0;
+    for (int i = tid, na = (int)acc_words(d.nbodies, 3); i < na; i += kBlockThreads) a[i] = 0.0;
     if (tid == 0) {  // read by the last body step, raised by the next
       d.nl_flag[p ^ 1] = 0;
       d.rb_flag[p ^ 1] = 0;
@@ -1128,8 +1129,9 @@ __device__ __forceinline__ void process_tile_x2(const SolveDesc &d, const int lt
         const double sx = wave_sum((double)fx);
         const double sy = wave_sum((double)fy);
         if (lane == 0) {
-          unsafeAtomicAdd(&acc[3 * nbs], sx);
-          unsafeAtomicAdd(&acc[3 * nbs + 1], sy);
+          double *wa = acc + wall_base(3 * nbs) + (blockIdx.x % kWallSlots) * kWallSlotWords;
+          unsafeAtomicAdd(wa, sx);
+          unsafeAtomicAdd(wa + 1, sy);
         }
       }
     }

@@ -118,130 +118,20 @@ enum Mode3 { kStep3 = 0, kFields3 = 1 };
 template <int L>
 constexpr int kStash3 = L == 27 ? DILBM3D27_STASH : L;
 
-// Non-equilibrium extrapolation (Guo, Zheng & Shi 2002; the treatment the paper gives its
-// physical boundaries, Section 3) at a node of the inlet plane x = 0 or the outlet plane
-// x = nx - 1: the neighbour on the plane x = 1 or nx - 2 is pulled as in its own step
-// (its sources x - c_i stay inside [0, nx)), its rho and u (with half the body force, as
-// in its collision) give its equilibrium, and the boundary state (prescribed or the
-// neighbour's) gives the boundary node's; OUT: the boundary node's post-collision
-// populations g_i* = geq_i(boundary) + (1 - 1/tau) (g_i(neighbour) - geq_i(neighbour)),
-// in g units and the frame Vf (FP16: at the stored scale, rounded stochastically with the
-// node's own random bits), are stored to the other buffer (rd) here, each as it is formed.
-// The frame constants cancel in the non-equilibrium part.  Called after the tile's own
-// stores, so the collision's outputs are no longer held in registers.
-template <int L, bool H, bool OUT>
-__device__ __forceinline__ void nee3(const Desc3 &d, const __amdgpu_buffer_rsrc_t rs,
-                                     const __amdgpu_buffer_rsrc_t rd,
-                                     const uint32_t (&row)[3][3], const uint32_t pb,
-                                     const int xc, const int yc, const int z, const int64_t t,
-                                     const float3 Vt, const float3 Vf, float &rho_b, float &ubx,
-                                     float &uby, float &ubz) {
-  constexpr uint32_t es = H ? 2u : 4u;
-  const bool inlet = xc == 0;
-  const int xn = inlet ? 1 : d.nx - 2;
-  const uint32_t v0 = (uint32_t)xn * es, vm = (uint32_t)(xn - 1) * es;
-  const uint32_t vp = (uint32_t)(xn + 1) * es;
-  float g[L];
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const uint32_t v = C3X[i] == 0 ? v0 : (C3X[i] > 0 ? vm : vp);
-    const uint32_t so = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
-    if (H)
-      g[i] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, v, so, 0)) *
-             d.store_inv;
-    else
-      g[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, v, so, 0));
-  }
-  if (!H) {  // to the frame of the outputs
-    const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
-#pragma unroll
-    for (int i = 1; i < L; ++i)
-      g[i] -= (3.0f * kw3<L>(i)) *
-              ((float)C3X[i] * dvx + (float)C3Y[i] * dvy + (float)C3Z[i] * dvz);
-  }
-  constexpr float S = Lat3<L>::S, invS = 1.0f / S, halfS = 0.5f * S;
-  float D = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    D += g[i];
-    if (C3X[i]) Jx += C3X[i] > 0 ? g[i] : -g[i];
-    if (C3Y[i]) Jy += C3Y[i] > 0 ? g[i] : -g[i];
-    if (C3Z[i]) Jz += C3Z[i] > 0 ? g[i] : -g[i];
-  }
-  const float R = S * d.rho0 + D;
-  const float rho_n = R * invS, drho_n = D * invS;
-  float Rinv = __builtin_amdgcn_rcpf(R);
-  Rinv = fmaf(fmaf(-R, Rinv, 1.0f), Rinv, Rinv);
-  // S rho u_nb = S (j + G/2), in the fixed frame
-  const float V36x = S * Vf.x, V36y = S * Vf.y, V36z = S * Vf.z;
-  const float Jgx = Jx + (V36x + halfS * d.Gx), Jgy = Jy + (V36y + halfS * d.Gy);
-  const float Jgz = Jz + (V36z + halfS * d.Gz);
-  const float unx = Jgx * Rinv, uny = Jgy * Rinv, unz = Jgz * Rinv;
-  float drho_b = drho_n;
-  ubx = unx;
-  uby = uny;
-  ubz = unz;
-  if (inlet) {
-    if (d.inlet_kind == 0) {  // velocity inlet: rho from the neighbour
-      float sh = 1.0f;
-      if (d.inlet_profile >= 1) {
-        const float sy = ((float)yc + 0.5f - d.prof_y0) * d.prof_inv_hy;
-        sh = (sy > 0.0f && sy < 1.0f) ? 4.0f * sy * (1.0f - sy) : 0.0f;
-        if (d.inlet_profile == 2) {
-          const float sz = ((float)z + 0.5f - d.prof_z0) * d.prof_inv_hz;
-          sh *= (sz > 0.0f && sz < 1.0f) ? 4.0f * sz * (1.0f - sz) : 0.0f;
-        }
-      }
-      ubx = sh * d.u_in[0];
-      uby = sh * d.u_in[1];
-      ubz = sh * d.u_in[2];
-    } else {
-      drho_b = d.drho_in;
-    }
-  } else if (d.outlet_kind == 0) {
-    drho_b = d.drho_out;
-  }
-  rho_b = d.rho0 + drho_b;
-  if (!OUT) return;
-  // rho u - V for the neighbour (rho u_nb = j + G/2) and for the boundary state
-  const float mnx = (Jgx - V36x) * invS, mny = (Jgy - V36y) * invS, mnz = (Jgz - V36z) * invS;
-  const float mbx = rho_b * ubx - Vf.x, mby = rho_b * uby - Vf.y, mbz = rho_b * ubz - Vf.z;
-  const float uun = unx * unx + uny * uny + unz * unz, uub = ubx * ubx + uby * uby + ubz * ubz;
-  const float keep = 1.0f - d.omega;  // 1 - 1/tau
-  const float scale = H ? d.store_scale : 1.0f;
-  // FP16: the random words of the node's own stochastic rounding (as in tile3)
-  uint32_t hw = 0;
-  if (H) {
-    const uint32_t tk = lowbias32((uint32_t)t ^ lowbias32((uint32_t)((uint64_t)t >> 32)));
-    hw = lowbias32((((uint32_t)z * (uint32_t)d.ny + (uint32_t)yc) * (uint32_t)d.nx +
-                    (uint32_t)xc) ^ tk);
-  }
-  const uint32_t vo = (uint32_t)xc * es, so0 = row[1][1];
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
-    const float K = kw3<L>(i);
-    const float cun = cx * unx + cy * uny + cz * unz, cub = cx * ubx + cy * uby + cz * ubz;
-    const float eqn = K * (drho_n + 3.0f * (cx * mnx + cy * mny + cz * mnz) +
-                           rho_n * (4.5f * cun * cun - 1.5f * uun));
-    const float eqb = K * (drho_b + 3.0f * (cx * mbx + cy * mby + cz * mbz) +
-                           rho_b * (4.5f * cub * cub - 1.5f * uub));
-    const float o = scale * (eqb + keep * (g[i] - eqn));
-    const uint32_t so = (uint32_t)i * pb + so0;
-    if (H) {
-      if (i > 0 && (i & 1) == 0) hw = xorshift32(hw);
-      __builtin_amdgcn_raw_buffer_store_b16(
-          sr_half(o, (i & 1) ? __builtin_amdgcn_alignbit(hw, hw, 13) : hw), rd, vo, so, 0);
-    } else {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), rd, vo, so, 0);
-    }
-  }
-}
-
 // One tile of TX x (256 / TX) x 1 nodes (TX = 64 or 256: a wave is part of one row).
 // MODE kStep3: the full step; kFields3: rho and u of the current state.
-// OPEN: the instance handles open ends in x (d.xbc; the lanes of the two boundary planes
-// take non-equilibrium extrapolation, nee3, and contribute no solid-field force).
+// OPEN: the instance for open ends in x (d.xbc).  A node of the inlet plane x = 0 or the
+// outlet plane x = nx - 1 takes non-equilibrium extrapolation (Guo, Zheng & Shi 2002; the
+// treatment the paper gives its physical boundaries, Section 3): its lane pulls the
+// populations of its neighbour on the plane x = 1 or nx - 2 instead of its own (the
+// neighbour's sources x - c_i stay inside [0, nx), and the lines are those its wave reads
+// anyway), so the moments below are the neighbour's, u* carries half the body force as in
+// the neighbour's collision, and the lane takes no solid field.  Its output is
+//   g_i* = geq_i(boundary) + (1 - 1/tau) (g_i - geq_i(neighbour))
+//        = g_i + omega (geq_i(neighbour) - g_i) + [geq_i(boundary) - geq_i(neighbour)],
+// the regular update with the bracket in place of the forcing term (the forcing term's
+// inputs are set to produce it); the boundary state is prescribed or the neighbour's.  The
+// frame constants cancel in the bracket's difference and in the non-equilibrium part.
 template <int MODE, int TX, int L, bool H, bool OPEN>
 __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const int p,
                                       const int64_t t, float (*red)[6][64], float *stash,
@@ -265,7 +155,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const int y = __builtin_amdgcn_readfirstlane(y0 + tid / TX);  // a wave is part of one row
   const bool valid = x < nx && y < ny;
   const int xc = min(x, nx - 1), yc = min(y, ny - 1);
-  // a node of the inlet or outlet plane: its state comes from its neighbour (nee3)
+  // a node of the inlet or outlet plane (see OPEN above)
   const bool bnd = OPEN && d.xbc && valid && (x == 0 || x == nx - 1);
   const bool own = valid && !bnd;  // a node whose solid field this tile computes
 
@@ -280,9 +170,12 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const uint32_t pb = plane * es;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)d.pop[p], (short)0, (int)(L * pb), kBufferFlags);
-  const uint32_t vx0 = (uint32_t)xc * es;
-  const uint32_t vxm = (uint32_t)(xc == 0 ? nx - 1 : xc - 1) * es;  // source x - 1
-  const uint32_t vxp = (uint32_t)(xc + 1 == nx ? 0 : xc + 1) * es;  // source x + 1
+  const uint32_t vx0 = (uint32_t)xc * es;  // the node's own column (stores)
+  // the column whose populations the lane pulls: its own, or a boundary node's neighbour
+  const int xl = OPEN && bnd ? (x == 0 ? 1 : nx - 2) : xc;
+  const uint32_t vxl = (uint32_t)xl * es;
+  const uint32_t vxm = (uint32_t)(xl == 0 ? nx - 1 : xl - 1) * es;  // source x - 1
+  const uint32_t vxp = (uint32_t)(xl + 1 == nx ? 0 : xl + 1) * es;  // source x + 1
   uint32_t row[3][3];  // row[dz + 1][dy + 1]: byte offset of row (y + dy, z + dz)
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
@@ -294,7 +187,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   float g[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const uint32_t v = C3X[i] == 0 ? vx0 : (C3X[i] > 0 ? vxm : vxp);
+    const uint32_t v = C3X[i] == 0 ? vxl : (C3X[i] > 0 ? vxm : vxp);
     const uint32_t s = (uint32_t)i * pb + row[1 - C3Z[i]][1 - C3Y[i]];
     if (H)
       g[i] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, v, s, 0));
@@ -321,7 +214,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       d.tile_head[ls ^ 1][2 * lt] = 0;
     if (lt == 0) {
       double *a = d.acc[p ^ 1];
-      for (int i = tid; i < 6 * (nbs + 1); i += 256) a[i] = 0.0;
+      const int na = (int)acc_words(nbs, 6);
+      for (int i = tid; i < na; i += 256) a[i] = 0.0;
       if (tid == 0) d.rb_flag[p ^ 1] = 0;  // read by the last sphere step, raised by the next
     }
   }
@@ -335,8 +229,8 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   int64_t tc = t;
   asm volatile("" : "+s"(tc));
   float3 Vf = H ? make_float3(0.0f, 0.0f, 0.0f) : ref_velocity3<L>(tc);  // FP16: no frame
-  const float3 Vt = Vf;
   if (MODE == kStep3 && !H) {
+    const float3 Vt = Vf;
     Vf = ref_velocity3<L>(tc + 1);
     const float dvx = Vf.x - Vt.x, dvy = Vf.y - Vt.y, dvz = Vf.z - Vt.z;
 #pragma unroll
@@ -551,7 +445,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
         const double sx = wave_sum((double)fx), sy = wave_sum((double)fy);
         const double sz = wave_sum((double)fz);
         if (lane == 0) {
-          double *a = acc + 6 * nbs;
+          double *a = acc + wall_base(6 * nbs) + (blockIdx.x % kWallSlots) * kWallSlotWords;
           unsafeAtomicAdd(a + 0, sx);
           unsafeAtomicAdd(a + 1, sy);
           unsafeAtomicAdd(a + 2, sz);
@@ -571,15 +465,41 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   const float Mx = fmaf(halfS, Px, Jgx), My = fmaf(halfS, Py, Jgy), Mz = fmaf(halfS, Pz, Jgz);
   const float ux = Mx * Rinv, uy = My * Rinv, uz = Mz * Rinv;
 
+  // ---- open ends: the boundary state of an inlet or outlet node (the moments above are
+  // its neighbour's): prescribed, or the neighbour's ----------------------------------
+  float drho_b = drho, ubx = ux, uby = uy, ubz = uz;
+  if (OPEN && bnd) {
+    if (x == 0) {
+      if (d.inlet_kind == 0) {  // velocity inlet, rho from the neighbour
+        float sh = 1.0f;
+        if (d.inlet_profile >= 1) {
+          const float sy = ((float)yc + 0.5f - d.prof_y0) * d.prof_inv_hy;
+          sh = (sy > 0.0f && sy < 1.0f) ? 4.0f * sy * (1.0f - sy) : 0.0f;
+          if (d.inlet_profile == 2) {
+            const float sz = ((float)z + 0.5f - d.prof_z0) * d.prof_inv_hz;
+            sh *= (sz > 0.0f && sz < 1.0f) ? 4.0f * sz * (1.0f - sz) : 0.0f;
+          }
+        }
+        ubx = sh * d.u_in[0];
+        uby = sh * d.u_in[1];
+        ubz = sh * d.u_in[2];
+      } else {
+        drho_b = d.drho_in;
+      }
+    } else if (d.outlet_kind == 0) {
+      drho_b = d.drho_out;
+    }
+  }
+  const float rho_b = d.rho0 + drho_b;
+
   if (MODE == kFields3) {
-    float ro = rho, vx = ux, vy = uy, vz = uz;
-    if (OPEN && bnd) nee3<L, H, false>(d, rs, rs, row, pb, xc, yc, z, t, Vt, Vf, ro, vx, vy, vz);
     if (valid) {
+      const bool b = OPEN && bnd;
       const int64_t o = ((int64_t)z * ny + y) * nx + x;
-      out_rho[o] = (double)ro;
-      out_ux[o] = (double)vx;
-      out_uy[o] = (double)vy;
-      out_uz[o] = (double)vz;
+      out_rho[o] = (double)(b ? rho_b : rho);
+      out_ux[o] = (double)(b ? ubx : ux);
+      out_uy[o] = (double)(b ? uby : uy);
+      out_uz[o] = (double)(b ? ubz : uz);
     }
     return;
   }
@@ -606,21 +526,38 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
     trQ = Qxx + Qyy + Qzz;
   }
   const float om = d.omega, kh = d.khalf;
+  // the forcing term's inputs: P, Q and the body force; for an inlet or outlet node (OPEN
+  // above) they are set so that khalf K_i S_i is the bracket geq_i(boundary) -
+  // geq_i(neighbour): P = (m_b - m) / khalf, Q = (rho_b u_b u_b - rho u u) / khalf, the
+  // scalar (drho_b - drho) / khalf and no body force (m = rho u - V, m_b = rho_b u_b - V)
+  float sPx = Px, sPy = Py, sPz = Pz, sg = -3.0f * uG, gk = 1.0f;
+  if (OPEN && bnd) {
+    const float ik = d.inv_khalf;
+    sPx = (rho_b * ubx - Vf.x - mx) * ik;
+    sPy = (rho_b * uby - Vf.y - my) * ik;
+    sPz = (rho_b * ubz - Vf.z - mz) * ik;
+    Qxx = (rho_b * ubx * ubx - rho * ux * ux) * ik;
+    Qyy = (rho_b * uby * uby - rho * uy * uy) * ik;
+    Qzz = (rho_b * ubz * ubz - rho * uz * uz) * ik;
+    Qxy = (rho_b * ubx * uby - rho * ux * uy) * ik;
+    Qxz = (rho_b * ubx * ubz - rho * ux * uz) * ik;
+    Qyz = (rho_b * uby * ubz - rho * uy * uz) * ik;
+    trQ = Qxx + Qyy + Qzz;
+    sg = (drho_b - drho) * ik;
+    gk = 0.0f;
+  }
   const float base = drho - 1.5f * rho * uu;            // even part shared by all i
-  const float sbase = -3.0f * uG - 1.5f * trQ;          // even part of S shared by all i
+  const float sbase = sg - 1.5f * trQ;                  // even part of S shared by all i
   float out[L];
   // each output is g + (small update), applied once at the scale of g (FP16: g 2^k)
-  if (H)
-    out[0] = fmaf(sc, om * (kw3<L>(0) * base - inv * g[0]) + kh * kw3<L>(0) * sbase, g[0]);
-  else
-    out[0] = g[0] + om * (kw3<L>(0) * base - g[0]) + kh * kw3<L>(0) * sbase;
 #pragma unroll
   for (int i = 1; i < L; i += 2) {
     const float cx = (float)C3X[i], cy = (float)C3Y[i], cz = (float)C3Z[i];
     const float cu = cx * ux + cy * uy + cz * uz;
     const float cm = cx * mx + cy * my + cz * mz;
-    const float cG = d.cg[i >> 1];  // c.G of the pair, from the descriptor
-    const float cP = cx * Px + cy * Py + cz * Pz;
+    // c.G of the pair, from the descriptor (0 for an inlet or outlet node)
+    const float cG = OPEN ? d.cg[i >> 1] * gk : d.cg[i >> 1];
+    const float cP = cx * sPx + cy * sPy + cz * sPz;
     const float cQc = cx * cx * Qxx + cy * cy * Qyy + cz * cz * Qzz +
                       2.0f * (cx * cy * Qxy + cx * cz * Qxz + cy * cz * Qyz);
     const float K = kw3<L>(i);
@@ -636,9 +573,15 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       out[i + 1] = g[i + 1] + om * (ev - od - g[i + 1]) + kh * (sev - sod);
     }
   }
+  if (H)
+    out[0] = fmaf(sc, om * (kw3<L>(0) * base - inv * g[0]) + kh * kw3<L>(0) * sbase, g[0]);
+  else
+    out[0] = g[0] + om * (kw3<L>(0) * base - g[0]) + kh * kw3<L>(0) * sbase;
 
-  const float vv = ux * ux + uy * uy + uz * uz;
-  if (__ballot(own && !(rho > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
+  const bool b = OPEN && bnd;
+  const float rc = b ? rho_b : rho;
+  const float vv = b ? ubx * ubx + uby * uby + ubz * ubz : ux * ux + uy * uy + uz * uz;
+  if (__ballot(valid && !(rc > 0.0f && vv <= 0.25f)) != 0 && lane == 0)
     atomicOr(d.err, (int32_t)kErrUnstable);
   uint16_t hb[L];  // FP16: the stochastically rounded halves
   if (H) {
@@ -653,7 +596,7 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       hb[i] = sr_half(out[i], (i & 1) ? __builtin_amdgcn_alignbit(hw, hw, 13) : hw);
     }
   }
-  if (own) {
+  if (valid) {
     const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
         (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
     const uint32_t s0r = row[1][1];
@@ -672,16 +615,6 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
       put_all(std::true_type{});
     else
       put_all(std::false_type{});
-  }
-  if constexpr (OPEN) {
-    if (bnd) {  // the lanes of the inlet and outlet planes
-      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-          (void *)d.pop[p ^ 1], (short)0, (int)(L * pb), kBufferFlags);
-      float rb, bx, by, bz;
-      nee3<L, H, true>(d, rs, rd, row, pb, xc, yc, z, t, Vt, Vf, rb, bx, by, bz);
-      if (!(rb > 0.0f && bx * bx + by * by + bz * bz <= 0.25f))
-        atomicOr(d.err, (int32_t)kErrUnstable);
-    }
   }
 }
 

@@ -155,7 +155,11 @@ def params_from_workload(wl, **kw) -> Params3D:
                  interface_width=wl.eps, phi_cutoff=wl.cutoff, body_force=tuple(wl.G),
                  gravity=tuple(wl.g), wall_mask=wl.wall_mask, wall_half_thickness=wl.wall_h,
                  force_mode=wl.force_mode, coll_eps_p=wl.eps_p, coll_eps_p_overlap=wl.eps_p1,
-                 coll_eps_w=wl.eps_w, coll_eps_w_overlap=wl.eps_w1, coll_xi=wl.xi)
+                 coll_eps_w=wl.eps_w, coll_eps_w_overlap=wl.eps_w1, coll_xi=wl.xi,
+                 x_boundary=wl.x_boundary, inlet_kind=wl.inlet_kind,
+                 inlet_profile=wl.inlet_profile, outlet_kind=wl.outlet_kind,
+                 inlet_velocity=tuple(wl.u_in), inlet_density=wl.rho_in,
+                 outlet_density=wl.rho_out)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -52,6 +52,14 @@ class Workload3D:
     eps_w: float = 0.5e4
     eps_w1: float = 0.5e4
     xi: float = 1.0
+    # open ends in x (non-equilibrium extrapolation; 0 = periodic)
+    x_boundary: int = 0
+    inlet_kind: int = 0
+    inlet_profile: int = 0
+    outlet_kind: int = 0
+    u_in: tuple = (0.0, 0.0, 0.0)
+    rho_in: float = 1.0
+    rho_out: float = 1.0
     pos: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     omega: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
@@ -118,6 +126,22 @@ def suspension3d(n=256, count=400, seed=8) -> Workload3D:
     return Workload3D(name=f"suspension3d_{n}^3_{len(rad)}spheres", nx=n, ny=n, nz=n,
                       tau=0.6, nsteps=2000, G=(1.0e-6, 0.0, 0.0),
                       **spheres(pos, rad, np.full(len(rad), 1.2)))
+
+
+def inflow_duct3d(n=256, count=200, seed=9) -> Workload3D:
+    """A square duct (diffuse walls across the y and z seams) with a parabolic velocity
+    inlet at x = 0 and a density outlet at x = nx - 1, past fixed spheres of radius 8
+    whose supports stay 12 planes or more from the two ends."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    margin = 8.0 + 8.0 + 12.0
+    pos, rad = place_spheres(rng, (n - 2 * margin, n, n), count, lambda r: 8.0,
+                             wall_mask=WALL_Y | WALL_Z, wall_h=4.0)
+    pos[:, 0] += margin
+    return Workload3D(name=f"inflow_duct3d_{n}^3_{len(rad)}spheres", nx=n, ny=n, nz=n,
+                      tau=0.6, nsteps=2000, wall_mask=WALL_Y | WALL_Z, wall_h=4.0,
+                      x_boundary=1, inlet_kind=0, inlet_profile=2, outlet_kind=0,
+                      u_in=(0.03, 0.0, 0.0), rho_in=1.0, rho_out=1.0,
+                      **spheres(pos, rad, np.full(len(rad), 1.2), fixed=np.ones(len(rad))))
 
 
 def channel3d() -> Workload3D:
