@@ -70,6 +70,7 @@ COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm
 COUNTERS3_27 = os.path.join(ROOT, "profiles",
                             "k3_collide_suspension3d_256_d3q27_fp32_hbm_counters.txt")
 COUNTERS3_16 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp16_hbm_counters.txt")
+COUNTERS3_OPEN = os.path.join(ROOT, "profiles", "k3_collide_inflow_duct3d_256_fp32_hbm_counters.txt")
 TIMED_RUNS = 5
 
 
@@ -246,8 +247,8 @@ def suspension3d_leg(steps, warmup, stream, q=19, storage=0, w3=None):
     ms = launch_pass(s, max(steps, 100))
     s.close()
     dt = statistics.median(runs)
-    counters = {(19, 0): COUNTERS3, (27, 0): COUNTERS3_27,
-                (19, 1): COUNTERS3_16}.get((q, storage)) if periodic else None
+    counters = ({(19, 0): COUNTERS3, (27, 0): COUNTERS3_27, (19, 1): COUNTERS3_16}.get((q, storage))
+                if periodic else (COUNTERS3_OPEN if (q, storage) == (19, 0) else None))
     return {"workload": w3.name, "lattice": f"D3Q{q}", "storage": "fp16" if storage else "fp32",
             "value": round(w3.nodes * steps / dt / 1e6, 1),
             "unit": "MLUPS", "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
