@@ -7,7 +7,9 @@ Tolerances, fixed before measuring (the bars of the periodic 3-D path):
   largest deviation, sphere forces within 1e-4 of the largest, rho within 1e-6 and the
   velocity field (boundary planes included) within 1e-5 relative L2;
 * 400 steps of an inflow channel or duct with a fixed sphere: velocity relative L2 <= 1e-5
-  and drag within 1e-4 relative (FP32); 2e-3 and 2e-2 with FP16 storage.
+  and drag within 1e-4 relative (FP32); 2e-3 and 2e-2 with FP16 storage;
+* FP16 one step: populations within 2^-8 of the largest deviation (the FP16 bound of the
+  periodic one-step tests).
 """
 import numpy as np
 import pytest
@@ -84,6 +86,33 @@ def test_open_ends_one_step_matches_oracle(seed, dims, walls, kinds, q):
     for a in range(3):
         assert np.abs(ug[a][:, :, 0] - uo[a][:, :, 0]).max() < 1e-6
         assert np.abs(ug[a][:, :, -1] - uo[a][:, :, -1]).max() < 1e-6
+    g.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_fp16_open_ends_one_step_matches_oracle(q):
+    """FP16 storage: one step from a random state on whole-row tiles, a duct-profile
+    inlet and a density outlet; the populations within the FP16 one-step bound of the
+    periodic FP16 tests (2^-8 of the largest deviation: storage rounding dominates)."""
+    nx, ny, nz = 260, 10, 8
+    sp = inputs3d.spheres([[130.0, 5.0, 4.0]], [2.5], [1.2], fixed=[1])
+    wl = inputs3d.Workload3D(name="open16", nx=nx, ny=ny, nz=nz, tau=0.7, nsteps=1,
+                             G=(1e-5, 0.0, 0.0), wall_mask=inputs3d.WALL_Y | inputs3d.WALL_Z,
+                             wall_h=2.0, eps=1.0, cutoff=3.0, **sp)
+    ends = dict(OPEN, inlet_profile=2)
+    f0 = np.random.Generator(np.random.PCG64(7)).uniform(-1e-3, 1e-3, size=(q, nz, ny, nx))
+    log_case(f"3d FP16 open ends one step D3Q{q}")
+    o, g = _pair(wl, q, storage=dilbm.STORE_FP16, **ends)
+    o.set_populations(f0)
+    g.set_populations(f0)
+    o.step(1)
+    g.step(1)
+    fo, fg = o.get_populations(), g.get_populations()
+    err = np.abs(fg - fo).max() / np.abs(fo).max()
+    assert err <= 2.0**-8, err
+    _, *uo = o.get_fields()
+    _, *ug = g.get_fields()
+    assert rel_l2(np.stack(ug), np.stack(uo)) < 2e-3
     g.close()
 
 
