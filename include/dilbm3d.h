@@ -162,6 +162,34 @@ dilbm_status dilbm3d_get_kernel_launch_times(dilbm3d_solver *s, double *ms, int6
 /* Release the handle and its device memory; NULL is a no-op. */
 void dilbm3d_destroy(dilbm3d_solver *s);
 
+/* Batches: several solves advanced together, one collide launch over all members' tiles
+ * and one sphere launch over all their spheres per step (the Section 2.3 step of each
+ * member, with the arithmetic of dilbm3d_step).  Members must share the device, the
+ * lattice, the population storage and the tile width (all with rows of 256 nodes or
+ * more, or all shorter); they run on the first member's stream.  The batch refers to its
+ * members and owns none of them: destroy the batch before any member.  Members may still
+ * be stepped, read or given new spheres on their own between batch calls; each call
+ * takes their current state.  *out receives the handle (NULL on failure); DILBM_EINVAL
+ * for n < 1, a NULL or repeated member or members that differ as above, DILBM_ESTATE
+ * for a poisoned member. */
+typedef struct dilbm3d_batch dilbm3d_batch;
+dilbm_status dilbm3d_batch_create(dilbm3d_solver *const *members, int32_t n,
+                                  dilbm3d_batch **out);
+
+/* Advance every member nsteps >= 0 steps (< 2^31); synchronous.  The members' error
+ * words are read every 32 steps while later steps run: when a member fails, the call
+ * stops within 64 steps, every member has advanced the same number of steps
+ * (dilbm3d_get_step_count), the failing member is poisoned as by dilbm3d_step and the
+ * call returns its error. */
+dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps);
+
+/* Release the batch (not its members); NULL is a no-op. */
+void dilbm3d_batch_destroy(dilbm3d_batch *b);
+
+/* Message of the batch's last failure ("" if none); for b == NULL, the calling thread's
+ * last failure of a dilbm3d_* call. */
+const char *dilbm3d_batch_last_error(const dilbm3d_batch *b);
+
 /* Message of the handle's last failure ("" if none); for s == NULL, the calling
  * thread's last failure of a dilbm3d_* call. */
 const char *dilbm3d_last_error(const dilbm3d_solver *s);

@@ -106,6 +106,12 @@ struct Desc3 {
   int32_t tile_x;     // 64 or 256
   int32_t tiles_x, tiles_y;
   int64_t ntiles;
+  // a member of a batch (dilbm3d_batch_*): its first tile and first sphere in the batch's
+  // concatenation, and the parity and step count of its state when the batch call began
+  int64_t tile_base;
+  int32_t body_base;
+  int32_t parity0;
+  int64_t step0;
   int32_t nbodies;
   int32_t list_cap;
   // FP32 node-update constants

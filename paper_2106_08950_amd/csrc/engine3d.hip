@@ -1,10 +1,11 @@
 // engine3d.hip -- host runtime and C ABI of the three-dimensional DI-LBM path of libdilbm.
 //
-// A dilbm3d_solver owns the device state of one 3-D problem: two FP32 population buffers,
-// the per-tile sphere lists, the FP64 sphere state, snapshots and force accumulators,
-// and a small device descriptor.  A step is one k3_collide launch over every tile and
-// one k3_bodies launch over the spheres; dilbm3d_step polls the sticky error word once
-// after the last step.
+// A dilbm3d_solver owns the device state of one 3-D problem: two population buffers (FP32
+// or FP16), the per-tile sphere lists, the FP64 sphere state, snapshots and force
+// accumulators, and a small device descriptor.  A step is one k3_collide launch over
+// every tile (the open-ends instance when x_boundary asks for it) and one k3_bodies launch
+// over the spheres; dilbm3d_step reads the sticky error word every kPollSteps3 steps while
+// later steps run, and once more after the last.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -739,3 +740,202 @@ const char *dilbm3d_last_error(const dilbm3d_solver *s) {
 }
 
 }  // extern "C"
+
+// ---- batches: several solves advanced in one collide and one sphere launch per step ----
+
+struct dilbm3d_batch {
+  std::vector<dilbm3d_solver *> m;
+  int device = 0;
+  hipStream_t stream = nullptr;   // the first member's stream
+  int q = 19, tile_x = 64;
+  bool h = false, open = false;
+  Desc3 *d_descs = nullptr;       // the members' descriptors, refreshed at every call
+  int32_t *d_tile_solve = nullptr, *d_body_solve = nullptr;
+  int64_t tile_cap = 0, body_cap = 0;
+  int32_t *h_flags = nullptr;     // pinned copies of the members' error words
+  hipEvent_t flag_ev = nullptr;
+  std::string last_error;
+};
+
+dilbm_status dilbm3d_batch_create(dilbm3d_solver *const *members, int32_t n,
+                                  dilbm3d_batch **out) {
+  if (!out) return DILBM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<dilbm3d_batch> b(new (std::nothrow) dilbm3d_batch);
+  if (!b) return DILBM_ENOMEM;
+  dilbm_status st = guard3(nullptr, [&] {
+    if (!members || n < 1) fail3(DILBM_EINVAL, "a batch needs n >= 1 members");
+    for (int32_t i = 0; i < n; ++i) {
+      dilbm3d_solver *s = members[i];
+      if (!s) fail3(DILBM_EINVAL, "NULL member");
+      for (int32_t j = 0; j < i; ++j)
+        if (members[j] == s) fail3(DILBM_EINVAL, "a solver appears twice in the batch");
+      check_usable3(s);
+      const dilbm3d_solver *f = members[0];
+      if (s->device != f->device || q_of(s->prm) != q_of(f->prm) ||
+          fp16_of(s->prm) != fp16_of(f->prm) || s->tile_x != f->tile_x)
+        fail3(DILBM_EINVAL,
+              "batch members must share the device, the lattice, the population storage and "
+              "the tile width (rows of 256 nodes or more, or all shorter)");
+      b->open = b->open || open_of(s->prm);
+      b->m.push_back(s);
+    }
+    b->device = members[0]->device;
+    b->stream = members[0]->stream;
+    b->q = q_of(members[0]->prm);
+    b->h = fp16_of(members[0]->prm);
+    b->tile_x = members[0]->tile_x;
+    HIPCHK3(hipSetDevice(b->device));
+    HIPCHK3(hipMalloc(&b->d_descs, sizeof(Desc3) * (size_t)n));
+    HIPCHK3(hipHostMalloc(&b->h_flags, sizeof(int32_t) * (size_t)n));
+    HIPCHK3(hipEventCreateWithFlags(&b->flag_ev, hipEventDisableTiming));
+  });
+  if (st != DILBM_OK) {
+    dilbm3d_batch_destroy(b.release());
+    return st;
+  }
+  *out = b.release();
+  return DILBM_OK;
+}
+
+namespace dilbm {
+namespace {
+
+// The members' descriptors with their places in the concatenation and their current state,
+// and the tile and sphere tables (rebuilt at every call: members may have new spheres).
+int64_t batch_tables3(dilbm3d_batch &b, int64_t *total_bodies) {
+  std::vector<Desc3> descs(b.m.size());
+  int64_t T = 0, B = 0;
+  for (size_t i = 0; i < b.m.size(); ++i) {
+    dilbm3d_solver &s = *b.m[i];
+    descs[i] = s.h;
+    descs[i].tile_base = T;
+    descs[i].body_base = (int32_t)B;
+    descs[i].parity0 = s.parity;
+    descs[i].step0 = s.steps;
+    T += s.h.ntiles;
+    B += s.nb;
+  }
+  if (T >= (int64_t)1 << 31 || B >= (int64_t)1 << 31)
+    fail3(DILBM_EINVAL, "a batch holds at most 2^31 - 1 tiles and spheres");
+  if (T > b.tile_cap) {
+    if (b.d_tile_solve) (void)hipFree(b.d_tile_solve);
+    b.d_tile_solve = nullptr;
+    HIPCHK3(hipMalloc(&b.d_tile_solve, sizeof(int32_t) * (size_t)T));
+    b.tile_cap = T;
+  }
+  if (B > b.body_cap) {
+    if (b.d_body_solve) (void)hipFree(b.d_body_solve);
+    b.d_body_solve = nullptr;
+    HIPCHK3(hipMalloc(&b.d_body_solve, sizeof(int32_t) * (size_t)B));
+    b.body_cap = B;
+  }
+  std::vector<int32_t> ts((size_t)T), bs((size_t)std::max<int64_t>(B, 1));
+  for (size_t i = 0; i < b.m.size(); ++i) {
+    std::fill(ts.begin() + descs[i].tile_base, ts.begin() + descs[i].tile_base + b.m[i]->h.ntiles,
+              (int32_t)i);
+    std::fill(bs.begin() + descs[i].body_base, bs.begin() + descs[i].body_base + b.m[i]->nb,
+              (int32_t)i);
+  }
+  HIPCHK3(hipMemcpyAsync(b.d_descs, descs.data(), sizeof(Desc3) * descs.size(),
+                         hipMemcpyHostToDevice, b.stream));
+  HIPCHK3(hipMemcpyAsync(b.d_tile_solve, ts.data(), sizeof(int32_t) * (size_t)T,
+                         hipMemcpyHostToDevice, b.stream));
+  if (B > 0)
+    HIPCHK3(hipMemcpyAsync(b.d_body_solve, bs.data(), sizeof(int32_t) * (size_t)B,
+                           hipMemcpyHostToDevice, b.stream));
+  HIPCHK3(hipStreamSynchronize(b.stream));  // the host tables go out of scope
+  *total_bodies = B;
+  return T;
+}
+
+void batch_flags_async3(dilbm3d_batch &b) {
+  for (size_t i = 0; i < b.m.size(); ++i)
+    HIPCHK3(hipMemcpyAsync(b.h_flags + i, b.m[i]->d_err, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, b.stream));
+  HIPCHK3(hipEventRecord(b.flag_ev, b.stream));
+}
+
+}  // namespace
+}  // namespace dilbm
+
+dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps) {
+  if (!b) return DILBM_EINVAL;
+  return guard3(&b->last_error, [&] {
+    if (nsteps < 0) fail3(DILBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps >= ((int64_t)1 << 31)) fail3(DILBM_EINVAL, "nsteps must be < 2^31 per call");
+    for (dilbm3d_solver *s : b->m) check_usable3(s);
+    HIPCHK3(hipSetDevice(b->device));
+    // members' own work on other streams finishes first
+    for (dilbm3d_solver *s : b->m)
+      if (s->stream != b->stream) HIPCHK3(hipStreamSynchronize(s->stream));
+    int64_t nbodies = 0;
+    const int64_t T = batch_tables3(*b, &nbodies);
+    int grid;
+    if (b->tile_x == 256) {
+      grid = (int)std::max<int64_t>(1, std::min<int64_t>(T, (int64_t)1 << 30));
+    } else {
+      const int bpc = std::max(1, collide3_batch_blocks_per_cu(b->q, b->h, b->open, b->tile_x));
+      int cus = 0;
+      HIPCHK3(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+      int64_t g = std::max(std::min(T, (int64_t)cus * bpc), (T + DILBM3D_CHUNK - 1) / DILBM3D_CHUNK);
+      g = std::min<int64_t>(g, (int64_t)1 << 30);
+      grid = (int)std::max<int64_t>(8, (g + 7) / 8 * 8);
+    }
+    bool pending = false;
+    int64_t k = 0;
+    for (; k < nsteps; ++k) {
+      // every kPollSteps3 steps: the flags as of the previous poll (a failed member stops
+      // the call one chunk later), then a copy of the current ones
+      if (k > 0 && k % kPollSteps3 == 0) {
+        if (pending) {
+          HIPCHK3(hipEventSynchronize(b->flag_ev));
+          bool bad = false;
+          for (size_t i = 0; i < b->m.size(); ++i) bad = bad || b->h_flags[i] != 0;
+          if (bad) break;
+        }
+        batch_flags_async3(*b);
+        pending = true;
+      }
+      HIPCHK3(launch3_collide_batch(b->q, b->h, b->open, b->tile_x, grid, b->stream,
+                                    b->d_descs, b->d_tile_solve, T, (int)k));
+      HIPCHK3(launch3_bodies_batch((int)nbodies, b->tile_x, b->stream, b->d_descs,
+                                   b->d_body_solve, (int)k));
+    }
+    HIPCHK3(hipStreamSynchronize(b->stream));
+    for (dilbm3d_solver *s : b->m) {
+      s->parity ^= (int)(k & 1);
+      s->steps += k;
+    }
+    // every member's error word; the first failing member is poisoned and named
+    for (size_t i = 0; i < b->m.size(); ++i) {
+      dilbm3d_solver *s = b->m[i];
+      int32_t e = 0;
+      HIPCHK3(hipMemcpy(&e, s->d_err, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (e) {
+        try {
+          raise_errors3(*s, e);
+        } catch (const Fail3 &f) {
+          s->last_error = f.msg;
+          fail3(f.st, "member " + std::to_string(i) + ": " + f.msg);
+        }
+      }
+    }
+  });
+}
+
+void dilbm3d_batch_destroy(dilbm3d_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_tile_solve) (void)hipFree(b->d_tile_solve);
+  if (b->d_body_solve) (void)hipFree(b->d_body_solve);
+  if (b->h_flags) (void)hipHostFree(b->h_flags);
+  if (b->flag_ev) (void)hipEventDestroy(b->flag_ev);
+  delete b;
+}
+
+const char *dilbm3d_batch_last_error(const dilbm3d_batch *b) {
+  return b ? b->last_error.c_str() : g_thread_error3.c_str();
+}

@@ -19,6 +19,15 @@ hipError_t launch3_collide(int q, bool h, bool open, int tile_x, int grid, hipSt
                            const Desc3 *desc, int p, int64_t step);
 // blocks of the collide kernel resident on one CU at once (0 on error)
 int collide3_blocks_per_cu(int q, bool h, bool open, int tile_x);
+// a batch's collide: members' descriptors descs[], tile_solve[t] the member of
+// concatenated tile t, k steps since the batch call began (tile_x and the instance shared)
+hipError_t launch3_collide_batch(int q, bool h, bool open, int tile_x, int grid,
+                                 hipStream_t stream, const Desc3 *descs,
+                                 const int32_t *tile_solve, int64_t total_tiles, int k);
+int collide3_batch_blocks_per_cu(int q, bool h, bool open, int tile_x);
+// a batch's sphere step: body_solve[g] the member of concatenated sphere g
+hipError_t launch3_bodies_batch(int total_bodies, int tile_x, hipStream_t stream,
+                                const Desc3 *descs, const int32_t *body_solve, int k);
 // rho and corrected u of parity p's state into [nz][ny][nx] device arrays (the boundary
 // state on the planes of open ends)
 hipError_t launch3_fields(int q, bool h, int tile_x, int64_t ntiles, hipStream_t stream,

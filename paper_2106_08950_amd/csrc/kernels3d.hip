@@ -6,19 +6,21 @@
 //
 //   k3_collide  one launch per step over all tiles (whole rows of 256 nodes, or 64 x 4 x 1
 //               nodes for short rows; 256 threads, one node per lane): pull streaming of
-//               the 19 populations, moments, the solid field of the listed spheres and
-//               walls, Eq. (17), the Eq. (13) collision, write-back, and the per-sphere
-//               FP64 force and torque sums.
+//               the 19 or 27 populations, moments, the solid field of the listed spheres
+//               and walls, Eq. (17), the Eq. (13) collision (or, on the planes of open
+//               ends, non-equilibrium extrapolation), write-back, and the per-sphere FP64
+//               force and torque sums.
 //   k3_bodies   one block per sphere: Eq. (28) pair forces, Eq. (29) wall images, the
 //               Eqs. (22)-(24) update in FP64 and binning into the next step's tile lists
 //               (each entry carries which of the tile's four waves the support reaches).
 //   k3_fields   rho and the corrected velocity of Eq. (17) (output only).
 //
-// Populations are kept as g_i = S (f_i - w_i rho0) in FP32, with S making the weights exact
-// integers K_i = S w_i: D3Q19 S = 36 (weights 1/3, 1/18, 1/36 -> K = 12, 2, 1), D3Q27
-// S = 216 (8/27, 2/27, 1/54, 1/216 -> K = 64, 16, 4, 1).  Every constant on the mass and
-// momentum path is then exact in binary and what remains is unbiased round-to-nearest.
-// Kernels are instantiated per lattice L (19 or 27 directions).
+// Populations are kept as g_i = S (f_i - w_i rho0) in FP32 (or FP16 times 2^k), with S
+// making the weights exact integers K_i = S w_i: D3Q19 S = 36 (weights 1/3, 1/18, 1/36 ->
+// K = 12, 2, 1), D3Q27 S = 216 (8/27, 2/27, 1/54, 1/216 -> K = 64, 16, 4, 1).  Every
+// constant on the mass and momentum path is then exact in binary and what remains is
+// unbiased round-to-nearest.  Kernels are instantiated per lattice L (19 or 27
+// directions), population storage H (FP16) and, for the collide, open ends in x.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -618,10 +620,14 @@ __device__ __forceinline__ void tile3(const Desc3 &d, const int64_t lt, const in
   }
 }
 
+// Register budget of the collide kernels (waves per SIMD)
+template <int L, bool H>
+constexpr int collide3_waves() {
+  return H ? DILBM3D_COLLIDE_WAVES_F16 : (L == 19 ? DILBM3D_COLLIDE_WAVES : DILBM3D27_COLLIDE_WAVES);
+}
+
 template <int TX, int L, bool H, bool OPEN>
-__global__ __launch_bounds__(256, (H ? DILBM3D_COLLIDE_WAVES_F16
-                                     : (L == 19 ? DILBM3D_COLLIDE_WAVES
-                                                : DILBM3D27_COLLIDE_WAVES)))
+__global__ __launch_bounds__(256, (collide3_waves<L, H>()))
 void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   __shared__ float red[4][6][64];  // per wave: the force and torque of its lanes
   __shared__ float stash[kStash3<L> * 256];  // populations of the block's lanes
@@ -645,6 +651,31 @@ void k3_collide(const Desc3 *__restrict__ desc, int p, int64_t step) {
   }
 }
 
+// The collide of a batch of solves in one launch: tile t of the concatenated tiles belongs
+// to member tile_solve[t]; member s steps from its own state (parity (parity0 + k) & 1,
+// step step0 + k), as in its own k3_collide.  Whole-row tiles go tile b to block b;
+// 64-wide tiles sweep chunks of each XCD's eighth.
+template <int TX, int L, bool H, bool OPEN>
+__global__ __launch_bounds__(256, (collide3_waves<L, H>()))
+void k3_collide_batch(const Desc3 *__restrict__ descs, const int32_t *__restrict__ tile_solve,
+                      int64_t total_tiles, int k) {
+  __shared__ float red[4][6][64];
+  __shared__ float stash[kStash3<L> * 256];
+  auto run = [&](const int64_t t) {
+    const int s = __builtin_amdgcn_readfirstlane(tile_solve[t]);
+    const Desc3 &d = descs[s];
+    tile3<kStep3, TX, L, H, OPEN>(d, t - d.tile_base, (d.parity0 + k) & 1, d.step0 + k, red,
+                                  stash, nullptr, nullptr, nullptr, nullptr);
+  };
+  if (TX == 256) {
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) run(t);
+    return;
+  }
+  const WorkSplit ws = xcd_split(total_tiles);
+  const bool rev = (blockIdx.x >> 3) & 1;
+  for (int64_t i = ws.begin; i < ws.end; ++i) run(rev ? ws.end - 1 - (i - ws.begin) : i);
+}
+
 template <int TX, int L, bool H>
 __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc, int p,
                                                  int64_t step, double *__restrict__ rho,
@@ -663,11 +694,9 @@ __global__ __launch_bounds__(256) void k3_fields(const Desc3 *__restrict__ desc,
 // writes it, and the binning's candidate tiles are spread over all 256 threads: a sphere
 // of R = 8 has about 1 100 candidate rows, whose slot claims are most of a binning's time.
 template <bool BIN_ONLY, int TX>
-__global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
-  const Desc3 &d = *desc;
+__device__ __forceinline__ void bodies3(const Desc3 &d, const int b, const int p) {
   const int lane = threadIdx.x & 63;
   const int nb = d.nbodies;
-  const int b = blockIdx.x;
   if (b >= nb) return;  // block-uniform
   const double *st = d.bstate[p];
   const double N[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
@@ -874,6 +903,22 @@ __global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc,
 // Populations in and out: fin / fout are [L][nz][ny][nx] FP64 deviations f_i - w_i rho0
 // of the current state; node x keeps f_i at x - c_i (pull layout), as g = S (f - w rho0)
 // in FP32 in the storage frame, or as g 2^k in FP16 (rounded to nearest; no frame).
+template <bool BIN_ONLY, int TX>
+__global__ __launch_bounds__(256) void k3_bodies(const Desc3 *__restrict__ desc, int p) {
+  bodies3<BIN_ONLY, TX>(*desc, blockIdx.x, p);
+}
+
+// The sphere steps of a batch of solves in one launch: block g is sphere
+// g - descs[s].body_base of member s = body_solve[g].
+template <int TX>
+__global__ __launch_bounds__(256) void k3_bodies_batch(const Desc3 *__restrict__ descs,
+                                                       const int32_t *__restrict__ body_solve,
+                                                       int k) {
+  const int s = __builtin_amdgcn_readfirstlane(body_solve[blockIdx.x]);
+  const Desc3 &d = descs[s];
+  bodies3<false, TX>(d, (int)blockIdx.x - d.body_base, (d.parity0 + k) & 1);
+}
+
 template <int L, bool H>
 __global__ void k3_set_pops(const Desc3 *__restrict__ desc, int p, int64_t step,
                             const double *__restrict__ fin) {
@@ -971,6 +1016,7 @@ int collide3_blocks_per_cu(int q, bool h, bool open, int tile_x) {
   return n;
 }
 
+using Collide3B = void (*)(const Desc3 *, const int32_t *, int64_t, int);
 using Fields3 = void (*)(const Desc3 *, int, int64_t, double *, double *, double *, double *);
 template <bool H>
 static Fields3 fields3_kernel_of(int q, int tile_x) {
@@ -984,6 +1030,41 @@ hipError_t launch3_fields(int q, bool h, int tile_x, int64_t ntiles, hipStream_t
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, 1 << 20));
   auto k = h ? fields3_kernel_of<true>(q, tile_x) : fields3_kernel_of<false>(q, tile_x);
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, desc, p, step, rho, ux, uy, uz);
+  return hipGetLastError();
+}
+
+template <bool H, bool O>
+static Collide3B collide3_batch_of(int q, int tile_x) {
+  if (q == 27)
+    return tile_x == 256 ? &k3_collide_batch<256, 27, H, O> : &k3_collide_batch<64, 27, H, O>;
+  return tile_x == 256 ? &k3_collide_batch<256, 19, H, O> : &k3_collide_batch<64, 19, H, O>;
+}
+static Collide3B collide3_batch(int q, bool h, int tile_x, bool open) {
+  if (open)
+    return h ? collide3_batch_of<true, true>(q, tile_x) : collide3_batch_of<false, true>(q, tile_x);
+  return h ? collide3_batch_of<true, false>(q, tile_x) : collide3_batch_of<false, false>(q, tile_x);
+}
+
+hipError_t launch3_collide_batch(int q, bool h, bool open, int tile_x, int grid,
+                                 hipStream_t stream, const Desc3 *descs,
+                                 const int32_t *tile_solve, int64_t total_tiles, int k) {
+  hipLaunchKernelGGL(collide3_batch(q, h, tile_x, open), dim3(grid), dim3(256), 0, stream,
+                     descs, tile_solve, total_tiles, k);
+  return hipGetLastError();
+}
+
+int collide3_batch_blocks_per_cu(int q, bool h, bool open, int tile_x) {
+  int n = 0;
+  const void *f = reinterpret_cast<const void *>(collide3_batch(q, h, tile_x, open));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) return 0;
+  return n;
+}
+
+hipError_t launch3_bodies_batch(int total_bodies, int tile_x, hipStream_t stream,
+                                const Desc3 *descs, const int32_t *body_solve, int k) {
+  if (total_bodies <= 0) return hipSuccess;
+  auto kf = tile_x == 256 ? k3_bodies_batch<256> : k3_bodies_batch<64>;
+  hipLaunchKernelGGL(kf, dim3(total_bodies), dim3(256), 0, stream, descs, body_solve, k);
   return hipGetLastError();
 }
 

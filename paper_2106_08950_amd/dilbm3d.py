@@ -1,5 +1,6 @@
 """Thin ctypes binding of the three-dimensional DI-LBM calls of libdilbm.so (the C ABI
-declared in include/dilbm3d.h: D3Q19 lattice, spherical particles).
+declared in include/dilbm3d.h: D3Q19 or D3Q27 lattice, spherical particles, FP32 or FP16
+population storage, optional open ends in x).
 
 Argument marshalling only: every step of the method runs in the library's HIP kernels.
 Loading fails loudly when the library has not been built -- there is no fallback.
@@ -23,6 +24,7 @@ EXPORTED = [
     "dilbm3d_get_fields", "dilbm3d_get_particle_forces", "dilbm3d_get_particles",
     "dilbm3d_get_wall_force", "dilbm3d_get_step_count", "dilbm3d_set_kernel_timing",
     "dilbm3d_get_kernel_timing", "dilbm3d_get_kernel_launch_times", "dilbm3d_destroy", "dilbm3d_last_error",
+    "dilbm3d_batch_create", "dilbm3d_batch_step", "dilbm3d_batch_destroy", "dilbm3d_batch_last_error",
 ]
 
 
@@ -76,6 +78,10 @@ def load():
         "dilbm3d_get_kernel_launch_times": (I32, [V, _dp, I64, C.POINTER(I64)]),
         "dilbm3d_destroy": (None, [V]),
         "dilbm3d_last_error": (C.c_char_p, [V]),
+        "dilbm3d_batch_create": (I32, [C.POINTER(V), I32, C.POINTER(V)]),
+        "dilbm3d_batch_step": (I32, [V, I64]),
+        "dilbm3d_batch_destroy": (None, [V]),
+        "dilbm3d_batch_last_error": (C.c_char_p, [V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -295,3 +301,41 @@ class Solver3D:
                                                            C.byref(n)),
                     "dilbm3d_get_kernel_launch_times")
         return out[: int(n.value)]
+
+
+class Batch3D:
+    """Several Solver3D advanced together (dilbm3d_batch_*): one collide launch and one
+    sphere launch per step over all members.  The batch keeps references to its members;
+    close the batch before closing a member."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        lib = load()
+        arr = (C.c_void_p * len(self.members))(*[m._h.value if m._h else None
+                                                 for m in self.members])
+        h = C.c_void_p()
+        st = lib.dilbm3d_batch_create(arr, len(self.members), C.byref(h))
+        if st != 0:
+            raise dilbm.DilbmError(st, "dilbm3d_batch_create",
+                                   lib.dilbm3d_batch_last_error(None).decode())
+        self._h = h
+
+    def step(self, n=1):
+        st = load().dilbm3d_batch_step(self._h, int(n))
+        if st != 0:
+            raise dilbm.DilbmError(st, "dilbm3d_batch_step",
+                                   load().dilbm3d_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dilbm3d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -83,3 +83,15 @@ def test_null_handles_are_rejected():
     assert lib.dilbm3d_get_wall_force(None, None) == dilbm.EINVAL
     lib.dilbm3d_destroy(None)
     assert lib.dilbm3d_create(None, None) == dilbm.EINVAL
+
+
+def test_batch_rejects_bad_arguments_before_device():
+    lib = dilbm3d.load()
+    h = C.c_void_p()
+    assert lib.dilbm3d_batch_create(None, 0, C.byref(h)) == dilbm.EINVAL and not h.value
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.dilbm3d_batch_create(arr, 2, C.byref(h)) == dilbm.EINVAL and not h.value
+    assert lib.dilbm3d_batch_last_error(None) == b"NULL member"
+    assert lib.dilbm3d_batch_create(arr, 2, None) == dilbm.EINVAL
+    assert lib.dilbm3d_batch_step(None, 1) == dilbm.EINVAL
+    lib.dilbm3d_batch_destroy(None)  # a no-op

@@ -1,0 +1,161 @@
+"""GPU tests of the three-dimensional batch (dilbm3d_batch_*): several solves advanced in
+one collide launch and one sphere launch per step.  Each member must end where the same
+solve run alone ends, and the FP64 oracle where one is run.
+
+Tolerances: the batch takes each member's arithmetic unchanged, so against the member
+run alone only the order of the FP64 force sums (atomics) differs.  That order already
+differs between two runs of the same lone solve: after 200 steps their sphere positions
+differed by up to 1.0e-6 (measured on these members; the stiff Eqs. (28)-(29) repulsion
+amplifies the last-bit differences), so the bar is the single-solve one: velocity
+relative L2 <= 1e-5 and positions within 1e-5 after 200 steps (a first bar of 1e-9 for
+positions, set before that measurement, was below the run-to-run spread).  Against the
+oracle, the bars of the single-solve tests (velocity relative L2 <= 1e-5).  With FP16
+storage a last-bit difference can flip a stochastic rounding, an FP16 ulp of a
+population, so batch and lone runs are held to the FP16 bars (velocity relative L2
+<= 2e-3, positions within 1e-2).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import binding3d as o3
+from paper_2106_08950_amd import dilbm, dilbm3d, inputs3d
+from helpers import log_case, rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def _members(seed, dims_list, q=19, storage=0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k, (dims, walls, nsph) in enumerate(dims_list):
+        nx, ny, nz = dims
+        # radii of 3.5 or more: the explicit spin update of a smaller sphere of density 1.3
+        # runs away (in the oracle as well)
+        sp = inputs3d.random_spheres(rng, dims, nsph, rmin=3.5, rmax=4.5, speed=0.005,
+                                     wall_mask=walls, wall_h=3.0)
+        out.append(inputs3d.Workload3D(name=f"m{k}", nx=nx, ny=ny, nz=nz, tau=0.6 + 0.1 * k,
+                                       nsteps=200, G=(1e-5, 1e-6 * k, 0.0), wall_mask=walls,
+                                       wall_h=3.0, **sp))
+    return out
+
+
+def _solver(wl, q, storage, **kw):
+    s = dilbm3d.Solver3D(dilbm3d.params_from_workload(wl, lattice=q, storage=storage, **kw))
+    if wl.nbodies:
+        s.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
+    return s
+
+
+def _compare(batch_members, alone, wls, vtol=1e-5, xtol=1e-5):
+    for g, a, wl in zip(batch_members, alone, wls):
+        assert g.step_count() == a.step_count()
+        _, *ub = g.get_fields()
+        _, *ua = a.get_fields()
+        e = rel_l2(np.stack(ub), np.stack(ua))
+        assert e < vtol, (wl.name, e)
+        if wl.nbodies:
+            xb, _, _ = g.get_particles()
+            xa, _, _ = a.get_particles()
+            d = np.abs(xb - xa)
+            d = np.minimum(d, np.array([wl.nx, wl.ny, wl.nz]) - d)
+            assert d.max() < xtol, (wl.name, d.max())
+
+
+SHORT_ROWS = [((48, 40, 32), 0, 4), ((70, 30, 20), inputs3d.WALL_Y, 3),
+              ((64, 64, 16), inputs3d.WALL_Z, 0), ((100, 24, 30), 0, 5)]
+LONG_ROWS = [((200, 20, 16), inputs3d.WALL_Y, 3), ((256, 16, 12), 0, 4),
+             ((300, 12, 10), inputs3d.WALL_Y | inputs3d.WALL_Z, 2)]
+
+
+@pytest.mark.parametrize("q,storage,rows", [(19, 0, "short"), (27, 0, "short"),
+                                            (19, 0, "long"), (19, 1, "long"),
+                                            (27, 1, "short")])
+def test_batch_equals_members_run_alone(q, storage, rows):
+    wls = _members(5 + q + storage, SHORT_ROWS if rows == "short" else LONG_ROWS)
+    log_case(f"3d batch of {len(wls)} D3Q{q} storage={storage} {rows} rows")
+    alone = [_solver(wl, q, storage) for wl in wls]
+    alone[1].step(7)
+    for a in alone:  # the cases themselves run stably
+        assert a.step_status(200) == dilbm.OK
+    members = [_solver(wl, q, storage) for wl in wls]
+    with dilbm3d.Batch3D(members) as b:
+        b.step(120)
+        # a member stepped on its own in between: the batch takes its current state
+        members[1].step(7)
+        b.step(80)
+    if storage:  # FP16: one flipped stochastic rounding is an FP16 ulp; the FP16 bars
+        _compare(members, alone, wls, vtol=2e-3, xtol=1e-2)
+    else:
+        _compare(members, alone, wls)
+    for s in members + alone:
+        s.close()
+
+
+def test_batch_with_open_ends_matches_oracle():
+    """A batch holding a periodic solve and one with open ends (the batch then runs the
+    open-ends collide instance for both) against the FP64 oracle, 200 steps."""
+    wl0 = inputs3d.Workload3D(name="periodic", nx=64, ny=24, nz=20, tau=0.7, nsteps=200,
+                              G=(1e-5, 0.0, 0.0),
+                              **inputs3d.spheres([[30.0, 12.0, 10.0]], [4.0], [1.2]))
+    wl1 = inputs3d.Workload3D(name="inflow", nx=80, ny=24, nz=20, tau=0.8, nsteps=200,
+                              wall_mask=inputs3d.WALL_Y, wall_h=3.0, x_boundary=1,
+                              inlet_profile=1, u_in=(0.03, 0.0, 0.0),
+                              **inputs3d.spheres([[40.0, 12.0, 10.0]], [4.0], [1.0], fixed=[1]))
+    log_case("3d batch with open ends vs oracle")
+    members = [_solver(wl0, 19, 0), _solver(wl1, 19, 0)]
+    with dilbm3d.Batch3D(members) as b:
+        b.step(200)
+    for g, wl in zip(members, (wl0, wl1)):
+        o = o3.Oracle3Solver(o3.Oracle3Params(
+            nx=wl.nx, ny=wl.ny, nz=wl.nz, tau=wl.tau, G=tuple(wl.G), wall_mask=wl.wall_mask,
+            wall_h=wl.wall_h, x_boundary=wl.x_boundary, inlet_profile=wl.inlet_profile,
+            u_in=tuple(wl.u_in)))
+        o.set_particles(wl.pos, wl.radius, wl.density, wl.vel, wl.omega, wl.fixed)
+        o.step(200)
+        _, *uo = o.get_fields()
+        _, *ug = g.get_fields()
+        e = rel_l2(np.stack(ug), np.stack(uo))
+        print(f"3d batch member {wl.name}: u rel L2 {e:.3e}")
+        assert e < 1e-5
+        g.close()
+
+
+def test_batch_failure_poisons_only_the_failing_member():
+    wl = inputs3d.Workload3D(name="calm", nx=32, ny=16, nz=12, tau=0.8, nsteps=1,
+                             G=(1e-6, 0.0, 0.0))
+    bad = inputs3d.Workload3D(name="unstable", nx=16, ny=8, nz=8, tau=0.8, nsteps=1)
+    log_case("3d batch with an unstable member")
+    good = _solver(wl, 19, 0)
+    g = _solver(bad, 19, 0)
+    f = np.zeros((19, 8, 8, 16))
+    f[1] = 2.0  # a strong +x stream: rho = 3, u = 2/3 > 0.5
+    g.set_populations(f)
+    with dilbm3d.Batch3D([good, g]) as b:
+        with pytest.raises(dilbm.DilbmError) as e:
+            b.step(100)
+        assert e.value.status == dilbm.EUNSTABLE
+        assert "member 1" in str(e.value)
+        # the call stopped within two polls, both members advanced alike
+        assert good.step_count() == g.step_count() <= 64
+        # the failing member is poisoned, the other goes on
+        assert g.step_status(1) == dilbm.ESTATE
+        with pytest.raises(dilbm.DilbmError) as e2:
+            b.step(1)
+        assert e2.value.status == dilbm.ESTATE
+    good.step(5)
+    good.close()
+    g.close()
+
+
+def test_batch_rejects_mixed_members():
+    a = dilbm3d.Solver3D(dilbm3d.Params3D(nx=32, ny=16, nz=8, tau=0.8))
+    b = dilbm3d.Solver3D(dilbm3d.Params3D(nx=32, ny=16, nz=8, tau=0.8, lattice=27))
+    c = dilbm3d.Solver3D(dilbm3d.Params3D(nx=300, ny=8, nz=8, tau=0.8))  # whole-row tiles
+    for bad in ([a, b], [a, c], [a, a]):
+        with pytest.raises(dilbm.DilbmError) as e:
+            dilbm3d.Batch3D(bad)
+        assert e.value.status == dilbm.EINVAL
+    for s in (a, b, c):
+        s.close()
