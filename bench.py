@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--legs fp32,fp16,open_ends,suspension3d,suspension3d_q27,
-                            suspension3d_fp16,open_ends3d,batched,served]
+                            suspension3d_fp16,open_ends3d,batched3d,batched,served]
                     [--no-cpu]
 
 Headline workload (one step = the whole hot path over one solve): the dense suspension of
@@ -38,6 +38,8 @@ Further legs, reported in the same JSON line:
 * suspension3d_fp16: the D3Q19 suspension with FP16 storage (76 B per node update);
 * open_ends3d: a 256^3 D3Q19 duct (diffuse walls in y and z) with a parabolic velocity
   inlet and a density outlet, past 200 fixed spheres, FP32;
+* batched3d: 256 independent D3Q19 solves (sides 32-96, 1-3 spheres) advanced by one
+  dilbm3d_batch_step, against the same solves stepped one after another;
 * batched: the 256-solve ensemble (2000 steps each) advanced as one pool, against the
   same solves run one after another as plain solves;
 * served: the 500-request Poisson stream (50 requests/s) through the continuous-batching
@@ -258,6 +260,61 @@ def suspension3d_leg(steps, warmup, stream, q=19, storage=0, w3=None):
                                  "k3_collide", copy_gbs)}
 
 
+def batched3d_leg(stream, steps=400):
+    """The 3-D batch: 256 independent D3Q19 solves (inputs3d.ensemble3d) advanced together
+    by dilbm3d_batch_step, against the same solves stepped one after another."""
+    from paper_2106_08950_amd import dilbm3d, inputs3d
+
+    wls = inputs3d.ensemble3d(nsteps=steps)
+    nodes = sum(w.nodes for w in wls)
+
+    def make():
+        out = []
+        for w in wls:
+            s = dilbm3d.Solver3D(dilbm3d.params_from_workload(w, device=0,
+                                                              stream=stream.cuda_stream))
+            s.set_particles(w.pos, w.radius, w.density, w.vel, w.omega, w.fixed)
+            out.append(s)
+        return out
+
+    members = make()
+    batch = dilbm3d.Batch3D(members)
+    batch.step(32)  # warm-up
+    t0 = time.perf_counter()
+    batch.step(steps)
+    dt_batch = time.perf_counter() - t0
+    batch.close()
+    for s in members:
+        s.close()
+    solos = make()
+    for s in solos:
+        s.step(8)  # warm-up
+    torch_sync(stream)
+    t0 = time.perf_counter()
+    for s in solos:
+        s.step(steps)
+    dt_seq = time.perf_counter() - t0
+    for s in solos:
+        s.close()
+    mlups = nodes * steps / dt_batch / 1e6
+    log(f"3-D batch: {dt_batch:.2f} s, one after another {dt_seq:.2f} s")
+    return {"workload": f"ensemble of {len(wls)} D3Q19 solves x {steps} steps",
+            "nodes": nodes, "batch_mlups": round(mlups, 1),
+            "sequential_mlups": round(nodes * steps / dt_seq / 1e6, 1),
+            "speedup": round(dt_seq / dt_batch, 2),
+            "roofline": {"bound": "hbm", "bytes_per_node": 152,
+                         "achieved": round(152 * mlups * 1e6 / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(152 * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+                         "timing": f"wall clock over {steps} steps of every member, whole "
+                                   "step (collide + spheres)"},
+            "timing": "batch: one dilbm3d_batch_step call after a 32-step warm-up; "
+                      "sequential: dilbm3d_step of each solve in turn"}
+
+
+def torch_sync(stream):
+    stream.synchronize()
+
+
 def batched_leg(stream, steps_per_solve=2000, window=256):
     """256-solve ensemble: one pool against one plain solve after another."""
     import torch
@@ -413,7 +470,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--legs", default="fp32,fp16,open_ends,suspension3d,suspension3d_q27,"
-                                      "suspension3d_fp16,open_ends3d,batched,served")
+                                      "suspension3d_fp16,open_ends3d,batched3d,batched,served")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--served-count", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -486,6 +543,9 @@ def main():
 
         out["open_ends3d"] = suspension3d_leg(max(args.steps // 2, 1), args.warmup, stream,
                                               w3=inputs3d.inflow_duct3d())
+    if "batched3d" in legs:
+        log("batched 3-D")
+        out["batched3d"] = batched3d_leg(stream)
     if "batched" in legs:
         log("batched")
         out["batched"] = batched_leg(stream)

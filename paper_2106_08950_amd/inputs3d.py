@@ -144,6 +144,22 @@ def inflow_duct3d(n=256, count=200, seed=9) -> Workload3D:
                       **spheres(pos, rad, np.full(len(rad), 1.2), fixed=np.ones(len(rad))))
 
 
+def ensemble3d(count=256, seed=6, nsteps=400) -> list:
+    """Independent 3-D solves for the batched form: sides 32-96 (log-uniform; rows under
+    192 nodes, so every member takes 64 x 4 x 1 tiles), 1-3 free spheres of radius 3.5-5,
+    tau 0.6-1.2, a body force in x."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        dims = [int(round(np.exp(rng.uniform(np.log(32), np.log(96))))) for _ in range(3)]
+        pos, rad = place_spheres(rng, dims, int(rng.integers(1, 4)), lambda r: r.uniform(3.5, 5.0))
+        out.append(Workload3D(name=f"ensemble3d_{k}", nx=dims[0], ny=dims[1], nz=dims[2],
+                              tau=float(rng.uniform(0.6, 1.2)), nsteps=nsteps,
+                              G=(float(rng.uniform(1e-7, 5e-6)), 0.0, 0.0),
+                              **spheres(pos, rad, np.full(len(rad), 1.2))))
+    return out
+
+
 def channel3d() -> Workload3D:
     return Workload3D(name="channel3d_96x48x32", nx=96, ny=48, nz=32, tau=0.8, nsteps=1000,
                       G=(1.0e-5, 0.0, 0.0), wall_mask=WALL_Y, wall_h=4.0,
