@@ -68,6 +68,7 @@ KERNEL3_FILES = [os.path.join(CSRC, f) for f in
                      BUILD]
 COUNTERS = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp32_hbm_counters.txt")
 COUNTERS16 = os.path.join(ROOT, "profiles", "k_collide_dense_suspension_4096_fp16_hbm_counters.txt")
+COUNTERS_OPEN = os.path.join(ROOT, "profiles", "k_collide_inflow_4096x2048_fp32_hbm_counters.txt")
 COUNTERS3 = os.path.join(ROOT, "profiles", "k3_collide_suspension3d_256_fp32_hbm_counters.txt")
 COUNTERS3_27 = os.path.join(ROOT, "profiles",
                             "k3_collide_suspension3d_256_d3q27_fp32_hbm_counters.txt")
@@ -524,7 +525,7 @@ def main():
         log("open ends")
         wo = inputs.inflow_array()
         r = single_solve(wo, dilbm.STORE_FP32, args.steps, args.warmup, args.tile, stream, 72,
-                         None)
+                         measured_traffic(COUNTERS_OPEN))
         out["open_ends"] = {"workload": wo.name, **r}
     if "suspension3d" in legs:
         log("suspension3d")
