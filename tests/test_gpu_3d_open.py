@@ -201,3 +201,32 @@ def test_periodic_and_open_instances_agree_away_from_the_ends():
     _, ux, uy, uz = g.get_fields()
     assert np.abs(ux - 0.02).max() < 1e-6 and np.abs(uy).max() < 1e-6 and np.abs(uz).max() < 1e-6
     g.close()
+
+
+def test_full_size_inflow_duct_one_step():
+    """The 256^3 inflow duct of the benchmark (walls across y and z, duct-profile inlet,
+    density outlet, 200 fixed spheres) in the launch configuration the benchmark times:
+    one step from a random state, every population checked against the oracle."""
+    wl = inputs3d.inflow_duct3d()
+    log_case(f"3d full size {wl.name}, 1 step")
+    f0 = inputs3d.random_deviations3d(wl.nx, wl.ny, wl.nz, amp=1e-4, seed=12).astype(np.float32)
+    f0 = f0.astype(np.float64)  # exactly representable on the GPU
+    ends = dict(x_boundary=wl.x_boundary, inlet_kind=wl.inlet_kind,
+                inlet_profile=wl.inlet_profile, outlet_kind=wl.outlet_kind,
+                inlet_velocity=tuple(wl.u_in), inlet_density=wl.rho_in,
+                outlet_density=wl.rho_out)
+    o, g = _pair(wl, 19, **ends)
+    g.set_populations(f0)
+    g.step(1)
+    fg = g.get_populations()
+    Fg, _ = g.get_particle_forces()
+    g.close()
+    o.set_populations(f0)
+    del f0
+    o.step(1)
+    fo = o.get_populations()
+    err = np.abs(fg - fo).max() / np.abs(fo).max()
+    del fg, fo
+    assert err <= STEP_TOL, err
+    Fo, _ = o.get_particle_forces()
+    assert np.abs(Fg - Fo).max() <= 1e-4 * np.abs(Fo).max()
