@@ -62,6 +62,14 @@ typedef enum dilbm_status {
 } dilbm_status;
 
 enum { DILBM_STORE_FP32 = 0, DILBM_STORE_FP16 = 1 };
+/* fp16_scale_log2 = DILBM_FP16_SCALE_AUTO: the library takes the largest k at which every
+ * equilibrium state with 0 < rho <= 2 rho0 and |u| <= 0.5 (the speeds a step accepts) is
+ * stored at no more than half of FP16's largest finite value (65504), the rest being
+ * headroom for the non-equilibrium part: k = 10 on D2Q9, 11 on D3Q19, 8 on D3Q27 for
+ * rho0 = 1.  A power-of-two scale changes no relative precision in FP16's normal range;
+ * a larger k keeps smaller deviations out of the subnormals but lets a state inside that
+ * range overflow (a non-finite population: DILBM_EUNSTABLE at the next step). */
+enum { DILBM_FP16_SCALE_AUTO = -1 };
 /* Scale of Eqs. (18)-(19).  MOMENTUM_EXCHANGE: F_b = -sum_n w_b rho (u_s - u*), the
  * momentum the fluid gains from the body in the collision (the appendix's macroscopic
  * force), which balances the fluid momentum exactly.  PAPER_LITERAL: -sum_n w_b sum_i c_i
@@ -97,7 +105,8 @@ typedef struct dilbm_params {
   double coll_eps_w_overlap;   /* eps_W' of Eq. (29) */
   double coll_xi;              /* xi of Eqs. (28)-(29) */
   int32_t storage;             /* DILBM_STORE_*: population storage; arithmetic is FP32 */
-  int32_t fp16_scale_log2;     /* FP16 storage keeps 36 (f - w rho0) * 2^k; k in [0, 24] */
+  int32_t fp16_scale_log2;     /* FP16 storage keeps 36 (f - w rho0) * 2^k; k in [0, 24],
+                                  or DILBM_FP16_SCALE_AUTO (default) */
   int32_t list_capacity;       /* bodies per tile list; 0 = min(n_bodies, 128) */
   int32_t tile;                /* tile shape id (dilbm_tile_shape); -1 = default: 256 x 1
                                   for FP32 storage with nx >= 1024, else 64 x 4.  Shape 5
@@ -123,8 +132,8 @@ typedef struct dilbm_solver dilbm_solver;
 
 /* Fill *p with defaults: tau 0.8, rho0 1, interface width 2, cutoff 4, no forces, no
  * walls, h = 2 * interface width, momentum-exchange force scale, eps_P = eps_P' = 1e4,
- * eps_W = eps_W' = 5e3, xi = 1, FP32 storage, FP16 scale 2^10, device 0, no stream.
- * nx and ny are set to 0 and must be filled in. */
+ * eps_W = eps_W' = 5e3, xi = 1, FP32 storage, FP16 scale DILBM_FP16_SCALE_AUTO, device 0,
+ * no stream.  nx and ny are set to 0 and must be filled in. */
 void dilbm_params_init(dilbm_params *p);
 
 /* Number of tile shapes and the node extent (tx, ty) of shape `id`: shapes 0-4 hold 256

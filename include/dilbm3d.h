@@ -79,7 +79,8 @@ typedef struct dilbm3d_params {
   int32_t list_capacity;       /* spheres listed per tile; 0 = min(n, 128); <= 1024 */
   int32_t lattice;             /* 19 (D3Q19; 0 also means 19) or 27 (D3Q27) */
   int32_t storage;             /* DILBM_STORE_FP32 or DILBM_STORE_FP16, as in dilbm.h */
-  int32_t fp16_scale_log2;     /* FP16 storage keeps S (f - w rho0) * 2^k; k in [0, 24] */
+  int32_t fp16_scale_log2;     /* FP16 storage keeps S (f - w rho0) * 2^k; k in [0, 24],
+                                  or DILBM_FP16_SCALE_AUTO (dilbm.h; the default) */
   int32_t x_boundary;          /* DILBM_XBC_*; INLET_OUTLET needs nx >= 3, no DILBM3D_WALL_X */
   int32_t inlet_kind;          /* DILBM_INLET_VELOCITY (inlet_velocity prescribed, rho from
                                   the neighbour) or DILBM_INLET_PRESSURE (inlet_density
@@ -99,7 +100,7 @@ typedef struct dilbm3d_params {
 
 /* Fill *p with defaults: abi_version, rho0 = 1, interface_width = 2, phi_cutoff = 4,
  * wall_half_thickness = 4, collision constants 1e4 / 1e4 / 5e3 / 5e3 and xi = 1, FP32
- * storage, fp16_scale_log2 = 10, periodic in x (inlet and outlet densities 1); the
+ * storage, fp16_scale_log2 = DILBM_FP16_SCALE_AUTO, periodic in x (inlet and outlet densities 1); the
  * caller sets nx, ny, nz and tau.  Returns DILBM_EINVAL for p == NULL. */
 dilbm_status dilbm3d_params_init(dilbm3d_params *p);
 

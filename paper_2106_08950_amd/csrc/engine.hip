@@ -22,6 +22,7 @@
 
 #include "dilbm.h"
 #include "dilbm_internal.h"
+#include "fp16_scale.h"
 #include "kernels.h"
 
 namespace dilbm {
@@ -172,8 +173,9 @@ void validate(const dilbm_params *p) {
     fail(DILBM_EINVAL, "collision stiffnesses must be > 0 and xi >= 0");
   if (p->storage != DILBM_STORE_FP32 && p->storage != DILBM_STORE_FP16)
     fail(DILBM_EINVAL, "unknown storage");
-  if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)
-    fail(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24]");
+  if (p->fp16_scale_log2 != DILBM_FP16_SCALE_AUTO &&
+      (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24))
+    fail(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24] or DILBM_FP16_SCALE_AUTO");
   if (p->list_capacity < 0 || p->list_capacity > kMaxListCap)
     fail(DILBM_EINVAL, "list_capacity must be in [0, 1024]");
   if (p->tile < -1 || p->tile >= kNumTileShapes) fail(DILBM_EINVAL, "unknown tile shape");
@@ -362,7 +364,12 @@ void fill_desc(Solve &s) {
     d.prof_inv_h = (float)(1.0 / (y1 - y0));
   }
   d.storage = p.storage;
-  const double sc = p.storage == DILBM_STORE_FP16 ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
+  // D2Q9: S w_i = 16, 4, 1 for |c_i|^2 = 0, 1, 2 (S = 36)
+  static const double kSw[3] = {16.0, 4.0, 1.0};
+  const int k = p.fp16_scale_log2 == DILBM_FP16_SCALE_AUTO
+                    ? auto_fp16_scale_log2(kSw, 2, p.rho0)
+                    : p.fp16_scale_log2;
+  const double sc = p.storage == DILBM_STORE_FP16 ? std::ldexp(1.0, k) : 1.0;
   d.store_scale = (float)sc;
   d.store_inv = (float)(1.0 / sc);
   d.rho0_d = p.rho0;
@@ -1237,7 +1244,7 @@ void dilbm_params_init(dilbm_params *p) {
   p->coll_eps_w_overlap = 0.5e4;
   p->coll_xi = 1.0;
   p->storage = DILBM_STORE_FP32;
-  p->fp16_scale_log2 = 10;
+  p->fp16_scale_log2 = DILBM_FP16_SCALE_AUTO;
   p->list_capacity = 0;
   p->tile = -1;
   p->x_boundary = DILBM_XBC_PERIODIC;

@@ -18,6 +18,7 @@
 #include "dilbm3d.h"
 #include "dilbm3d_internal.h"
 #include "dilbm_internal.h"
+#include "fp16_scale.h"
 #include "kernels.h"
 #include "kernels3d.h"
 
@@ -82,8 +83,9 @@ void validate3(const dilbm3d_params *p) {
     fail3(DILBM_EINVAL, "lattice must be 19 (D3Q19) or 27 (D3Q27)");
   if (p->storage != DILBM_STORE_FP32 && p->storage != DILBM_STORE_FP16)
     fail3(DILBM_EINVAL, "storage must be DILBM_STORE_FP32 or DILBM_STORE_FP16");
-  if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)
-    fail3(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24]");
+  if (p->fp16_scale_log2 != DILBM_FP16_SCALE_AUTO &&
+      (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24))
+    fail3(DILBM_EINVAL, "fp16_scale_log2 must be in [0, 24] or DILBM_FP16_SCALE_AUTO");
   if (pop_half_bytes3(*p) >= (1ull << 32) - 256)
     fail3(DILBM_EINVAL, "one population buffer (q planes, rows rounded up to 128 bytes) must "
                         "stay under 4 GB");
@@ -248,7 +250,13 @@ void fill_desc3(dilbm3d_solver &s) {
   d.nz = p.nz;
   d.pitch = row_pitch3(p.nx, p.storage);
   d.storage = fp16_of(p) ? 1 : 0;
-  const double sc = fp16_of(p) ? std::ldexp(1.0, p.fp16_scale_log2) : 1.0;
+  // S w_i by |c_i|^2: D3Q19 (S = 36) 12, 2, 1; D3Q27 (S = 216) 64, 16, 4, 1
+  static const double kSw19[3] = {12.0, 2.0, 1.0}, kSw27[4] = {64.0, 16.0, 4.0, 1.0};
+  const int k = p.fp16_scale_log2 == DILBM_FP16_SCALE_AUTO
+                    ? (q_of(p) == 27 ? auto_fp16_scale_log2(kSw27, 3, p.rho0)
+                                     : auto_fp16_scale_log2(kSw19, 2, p.rho0))
+                    : p.fp16_scale_log2;
+  const double sc = fp16_of(p) ? std::ldexp(1.0, k) : 1.0;
   d.store_scale = (float)sc;
   d.store_inv = (float)(1.0 / sc);
   d.tile_x = s.tile_x;
@@ -416,7 +424,7 @@ dilbm_status dilbm3d_params_init(dilbm3d_params *p) {
   p->coll_eps_w = 0.5e4;
   p->coll_eps_w_overlap = 0.5e4;
   p->coll_xi = 1.0;
-  p->fp16_scale_log2 = 10;
+  p->fp16_scale_log2 = DILBM_FP16_SCALE_AUTO;
   p->x_boundary = DILBM_XBC_PERIODIC;
   p->inlet_density = 1.0;
   p->outlet_density = 1.0;

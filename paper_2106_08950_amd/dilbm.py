@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE, EABI, ECAPACITY, EAGAIN = (
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE",
                 -5: "ESTATE", -6: "EABI", -7: "ECAPACITY", -8: "EAGAIN"}
 STORE_FP32, STORE_FP16 = 0, 1
+FP16_SCALE_AUTO = -1  # fp16_scale_log2: the library picks the scale (DILBM_FP16_SCALE_AUTO)
 FORCE_MOMENTUM_EXCHANGE, FORCE_PAPER_LITERAL = 0, 1
 WALL_Y, WALL_X = 1, 2
 XBC_PERIODIC, XBC_INLET_OUTLET = 0, 1
@@ -171,7 +172,7 @@ class Params:
     coll_eps_w_overlap: float = 0.5e4
     coll_xi: float = 1.0
     storage: int = STORE_FP32
-    fp16_scale_log2: int = 10
+    fp16_scale_log2: int = FP16_SCALE_AUTO  # or k in [0, 24]
     list_capacity: int = 0
     tile: int = -1
     x_boundary: int = XBC_PERIODIC

@@ -113,7 +113,7 @@ class Params3D:
     list_capacity: int = 0
     lattice: int = 19          # 19: D3Q19, 27: D3Q27
     storage: int = 0           # 0: FP32 populations, 1: FP16 (dilbm.STORE_FP16)
-    fp16_scale_log2: int = 10
+    fp16_scale_log2: int = dilbm.FP16_SCALE_AUTO  # or k in [0, 24]
     x_boundary: int = 0        # dilbm.XBC_*: 1 = inlet plane x = 0, outlet plane x = nx - 1
     inlet_kind: int = 0        # dilbm.INLET_VELOCITY or dilbm.INLET_PRESSURE
     inlet_profile: int = 0     # 0 uniform; 1 parabolic across y; 2 across y and z

@@ -36,7 +36,7 @@ def test_params_defaults():
     assert (p.coll_eps_p, p.coll_eps_p_overlap, p.coll_eps_w, p.coll_eps_w_overlap, p.coll_xi) == (
         1.0e4, 1.0e4, 0.5e4, 0.5e4, 1.0)
     assert (p.list_capacity, p.device, p.wall_mask) == (0, 0, 0)
-    assert (p.storage, p.fp16_scale_log2) == (dilbm.STORE_FP32, 10)
+    assert (p.storage, p.fp16_scale_log2) == (dilbm.STORE_FP32, dilbm.FP16_SCALE_AUTO)
     assert (p.x_boundary, p.inlet_density, p.outlet_density) == (dilbm.XBC_PERIODIC, 1.0, 1.0)
     assert p.stream is None
     assert lib.dilbm3d_params_init(None) == dilbm.EINVAL
@@ -47,7 +47,7 @@ def test_params_defaults():
     dict(tau=float("nan")), dict(rho0=0.0), dict(interface_width=0.0), dict(phi_cutoff=-1.0),
     dict(wall_mask=8), dict(wall_mask=4, wall_half_thickness=0.0), dict(force_mode=2),
     dict(list_capacity=5000), dict(coll_xi=-1.0), dict(coll_eps_p=0.0), dict(storage=2),
-    dict(fp16_scale_log2=30), dict(fp16_scale_log2=-1),
+    dict(fp16_scale_log2=30), dict(fp16_scale_log2=-2),
     dict(body_force=(0.0, float("inf"), 0.0)), dict(gravity=(0.0, 0.0, float("nan"))),
     # open ends in x
     dict(x_boundary=2), dict(x_boundary=1, nx=2), dict(x_boundary=1, wall_mask=2),

@@ -34,7 +34,8 @@ def test_params_struct_layout_round_trips():
     assert p.abi_version == dilbm.ABI_VERSION
     assert (p.tau, p.rho0, p.interface_width, p.phi_cutoff) == (0.8, 1.0, 2.0, 4.0)
     assert (p.coll_eps_p, p.coll_eps_w, p.coll_xi) == (1.0e4, 0.5e4, 1.0)
-    assert (p.storage, p.fp16_scale_log2, p.list_capacity, p.tile, p.device) == (0, 10, 0, -1, 0)
+    assert (p.storage, p.list_capacity, p.tile, p.device) == (0, 0, -1, 0)
+    assert p.fp16_scale_log2 == dilbm.FP16_SCALE_AUTO == -1
     assert p.stream is None
 
 
@@ -42,7 +43,7 @@ def test_params_struct_layout_round_trips():
     dict(nx=0), dict(ny=-3), dict(nx=70000), dict(tau=0.5), dict(tau=float("nan")),
     dict(rho0=0.0), dict(interface_width=0.0), dict(phi_cutoff=-1.0), dict(wall_mask=4),
     dict(wall_mask=1, wall_half_thickness=0.0), dict(force_mode=2), dict(storage=3),
-    dict(fp16_scale_log2=30), dict(list_capacity=5000), dict(tile=9), dict(coll_xi=-1.0),
+    dict(fp16_scale_log2=30), dict(fp16_scale_log2=-2), dict(list_capacity=5000), dict(tile=9), dict(coll_xi=-1.0),
     dict(body_force=(float("inf"), 0.0)),
 ])
 def test_create_rejects_bad_params_before_device(bad):

@@ -161,3 +161,29 @@ def test_fp16_3d_full_size_suspension_one_step():
     assert err <= STEP_TOL16, err
     Fo, _ = o.get_particle_forces()
     assert np.abs(Fg - Fo).max() <= 5e-3 * np.abs(Fo).max()
+
+
+@pytest.mark.parametrize("q,rho,k_over", [(27, 3.2, 9), (19, 3.5, 12)])
+def test_automatic_scale_keeps_a_dense_fast_state_finite(q, rho, k_over):
+    """A uniform state moving at 0.45 along x (inside what a step accepts) whose axis
+    population S w_1 (rho h - 1), h = 1 + 1.35 + 0.91125 - 0.30375, FP16 holds at the
+    automatic scale (2^8 on D3Q27: 16 (3.2 h - 1) = 135.4, times 256 is 34 700; 2^11 on
+    D3Q19: 2 (3.5 h - 1) = 18.7, times 2048 is 38 300) but not at twice that (above
+    65 504).  The automatic scale keeps it uniform; the larger k stores an infinity and
+    the step reports the state unstable."""
+    nx, ny, nz, u = 64, 16, 8, 0.45
+    w = o3.lattice(q)[3]
+    f = (o3.feq(rho, [u, 0.0, 0.0], q) - w)[:, None, None, None] * np.ones((1, nz, ny, nx))
+    log_case(f"3d fp16 D3Q{q} dense fast uniform state, automatic scale and 2^{k_over}")
+    with dilbm3d.Solver3D(dilbm3d.Params3D(nx=nx, ny=ny, nz=nz, tau=0.8, lattice=q,
+                                           storage=F16)) as s:
+        s.set_populations(f)
+        s.step(20)
+        r, ux, uy, uz = s.get_fields()
+    np.testing.assert_allclose(r, rho, rtol=1e-2)
+    np.testing.assert_allclose(ux, u, rtol=1e-2)
+    assert max(np.abs(uy).max(), np.abs(uz).max()) < 1e-2
+    with dilbm3d.Solver3D(dilbm3d.Params3D(nx=nx, ny=ny, nz=nz, tau=0.8, lattice=q,
+                                           storage=F16, fp16_scale_log2=k_over)) as s:
+        s.set_populations(f)
+        assert s.step_status(1) == dilbm.EUNSTABLE

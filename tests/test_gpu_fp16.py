@@ -146,3 +146,46 @@ def test_fp16_pair_tiles_inflow_cylinder():
     print(f"inflow cylinder FP16 tile 5: u rel L2 {e:.3e}, drag rel error {ef:.3e}")
     assert e < 2e-3 and ef < 2e-2
     g.close()
+
+
+def test_automatic_scale_is_ten_on_d2q9():
+    """The automatic FP16 scale (the default) stores exactly as an explicit k = 10: the
+    same populations, bit for bit, after 10 steps of a driven flow from a random state (on
+    256 x 256 some values lie where 2^9 or 2^11 would move them into or out of FP16's
+    subnormals)."""
+    from oracle import binding as o2  # noqa: F401  (the fixture builds it)
+    log_case("fp16 automatic scale vs 2^10")
+    f0 = inputs.random_deviations(256, 256, amp=1e-4, seed=21)
+    out = []
+    for k in (dilbm.FP16_SCALE_AUTO, 10):
+        with dilbm.Solver(dilbm.Params(nx=256, ny=256, tau=0.7, body_force=(1e-5, 2e-6),
+                                       storage=F16, fp16_scale_log2=k)) as s:
+            s.set_populations(f0)
+            s.step(10)
+            out.append(s.get_populations())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_automatic_scale_keeps_a_dense_fast_state_finite():
+    """A uniform state of rho = 3.5 moving at 0.45 along x (inside what a step accepts):
+    its axis population S (f_1 - w_1) = 4 (3.5 h - 1) with h = 1 + 1.35 + 0.91125 - 0.30375
+    is 37.4, which FP16 holds at 2^10 (38 300) but not at 2^11 (76 600 > 65 504).  The
+    automatic scale keeps it exactly uniform; k = 11 stores an infinity and the step
+    reports the state unstable."""
+    from oracle import binding as o2
+
+    nx, ny, rho, u = 64, 32, 3.5, 0.45
+    w = o2.lattice()[2]
+    f = (o2.feq(rho, u, 0.0) - w)[:, None, None] * np.ones((1, ny, nx))
+    log_case("fp16 dense fast uniform state, automatic scale and 2^11")
+    with dilbm.Solver(dilbm.Params(nx=nx, ny=ny, tau=0.8, storage=F16)) as s:
+        s.set_populations(f)
+        s.step(20)
+        r, ux, uy = s.get_fields()
+    np.testing.assert_allclose(r, rho, rtol=1e-2)
+    np.testing.assert_allclose(ux, u, rtol=1e-2)
+    assert np.abs(uy).max() < 1e-2
+    with dilbm.Solver(dilbm.Params(nx=nx, ny=ny, tau=0.8, storage=F16,
+                                   fp16_scale_log2=11)) as s:
+        s.set_populations(f)
+        assert s.step_status(1) == dilbm.EUNSTABLE
