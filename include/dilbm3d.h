@@ -180,8 +180,8 @@ dilbm_status dilbm3d_batch_create(dilbm3d_solver *const *members, int32_t n,
 /* Advance every member nsteps >= 0 steps (< 2^31); synchronous.  The members' error
  * words are read every 32 steps while later steps run: when a member fails, the call
  * stops within 64 steps, every member has advanced the same number of steps
- * (dilbm3d_get_step_count), the failing member is poisoned as by dilbm3d_step and the
- * call returns its error. */
+ * (dilbm3d_get_step_count), every failing member is poisoned as by dilbm3d_step and the
+ * call returns the error of the first (the message names its index). */
 dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps);
 
 /* Release the batch (not its members); NULL is a no-op. */

@@ -915,7 +915,9 @@ dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps) {
       s->parity ^= (int)(k & 1);
       s->steps += k;
     }
-    // every member's error word; the first failing member is poisoned and named
+    // every member's error word: each failing member is poisoned, the first one named
+    dilbm_status first = DILBM_OK;
+    std::string msg;
     for (size_t i = 0; i < b->m.size(); ++i) {
       dilbm3d_solver *s = b->m[i];
       int32_t e = 0;
@@ -925,10 +927,14 @@ dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps) {
           raise_errors3(*s, e);
         } catch (const Fail3 &f) {
           s->last_error = f.msg;
-          fail3(f.st, "member " + std::to_string(i) + ": " + f.msg);
+          if (first == DILBM_OK) {
+            first = f.st;
+            msg = "member " + std::to_string(i) + ": " + f.msg;
+          }
         }
       }
     }
+    if (first != DILBM_OK) fail3(first, msg);
   });
 }
 

@@ -159,3 +159,27 @@ def test_batch_rejects_mixed_members():
         assert e.value.status == dilbm.EINVAL
     for s in (a, b, c):
         s.close()
+
+
+def test_batch_poisons_every_failing_member():
+    """Two unstable members and a calm one: the call names the first failing member, both
+    failing members are poisoned, the calm one goes on."""
+    calm = inputs3d.Workload3D(name="calm", nx=32, ny=16, nz=12, tau=0.8, nsteps=1,
+                               G=(1e-6, 0.0, 0.0))
+    bad = inputs3d.Workload3D(name="unstable", nx=16, ny=8, nz=8, tau=0.8, nsteps=1)
+    log_case("3d batch with two unstable members")
+    f = np.zeros((19, 8, 8, 16))
+    f[1] = 2.0  # a strong +x stream: rho = 3, u = 2/3 > 0.5
+    b1, good, b2 = _solver(bad, 19, 0), _solver(calm, 19, 0), _solver(bad, 19, 0)
+    b1.set_populations(f)
+    b2.set_populations(f)
+    with dilbm3d.Batch3D([b1, good, b2]) as b:
+        with pytest.raises(dilbm.DilbmError) as e:
+            b.step(100)
+        assert e.value.status == dilbm.EUNSTABLE
+        assert "member 0" in str(e.value)
+    assert b1.step_status(1) == dilbm.ESTATE
+    assert b2.step_status(1) == dilbm.ESTATE
+    good.step(5)
+    for s in (b1, good, b2):
+        s.close()
