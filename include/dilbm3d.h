@@ -168,7 +168,8 @@ void dilbm3d_destroy(dilbm3d_solver *s);
  * member, with the arithmetic of dilbm3d_step).  Members must share the device, the
  * lattice, the population storage and the tile width (all with rows of 256 nodes or
  * more, or all shorter); they run on the first member's stream.  The batch refers to its
- * members and owns none of them: destroy the batch before any member.  Members may still
+ * members and owns none of them: once a member is destroyed the batch may only be
+ * destroyed (dilbm3d_batch_step would read the destroyed member).  Members may still
  * be stepped, read or given new spheres on their own between batch calls; each call
  * takes their current state.  *out receives the handle (NULL on failure); DILBM_EINVAL
  * for n < 1, a NULL or repeated member or members that differ as above, DILBM_ESTATE

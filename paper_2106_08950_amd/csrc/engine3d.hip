@@ -874,6 +874,13 @@ dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps) {
     if (nsteps >= ((int64_t)1 << 31)) fail3(DILBM_EINVAL, "nsteps must be < 2^31 per call");
     for (dilbm3d_solver *s : b->m) check_usable3(s);
     HIPCHK3(hipSetDevice(b->device));
+    // the call returns with none of its work in flight, also when it fails part way: the
+    // batch then never needs its first member's stream again (dilbm3d_batch_destroy may
+    // come after that member is gone)
+    struct DrainOnExit {
+      hipStream_t st;
+      ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+    } drain{b->stream};
     // members' own work on other streams finishes first
     for (dilbm3d_solver *s : b->m)
       if (s->stream != b->stream) HIPCHK3(hipStreamSynchronize(s->stream));
@@ -941,7 +948,7 @@ dilbm_status dilbm3d_batch_step(dilbm3d_batch *b, int64_t nsteps) {
 void dilbm3d_batch_destroy(dilbm3d_batch *b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  // no work of the batch is in flight (dilbm3d_batch_step drains its stream)
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_tile_solve) (void)hipFree(b->d_tile_solve);
   if (b->d_body_solve) (void)hipFree(b->d_body_solve);

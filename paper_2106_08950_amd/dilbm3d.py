@@ -306,7 +306,7 @@ class Solver3D:
 class Batch3D:
     """Several Solver3D advanced together (dilbm3d_batch_*): one collide launch and one
     sphere launch per step over all members.  The batch keeps references to its members;
-    close the batch before closing a member."""
+    once a member is closed the batch refuses to step (it may still be closed)."""
 
     def __init__(self, members):
         self.members = list(members)
@@ -321,6 +321,12 @@ class Batch3D:
         self._h = h
 
     def step(self, n=1):
+        if not self._h:
+            raise dilbm.DilbmError(dilbm.ESTATE, "dilbm3d_batch_step", "the batch is closed")
+        if not all(m._h for m in self.members):
+            # the library would step through a destroyed member; refuse here instead
+            raise dilbm.DilbmError(dilbm.ESTATE, "dilbm3d_batch_step",
+                                   "a member was closed while the batch is open")
         st = load().dilbm3d_batch_step(self._h, int(n))
         if st != 0:
             raise dilbm.DilbmError(st, "dilbm3d_batch_step",

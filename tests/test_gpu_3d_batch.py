@@ -183,3 +183,20 @@ def test_batch_poisons_every_failing_member():
     good.step(5)
     for s in (b1, good, b2):
         s.close()
+
+
+def test_batch_refuses_to_step_a_closed_member():
+    a = dilbm3d.Solver3D(dilbm3d.Params3D(nx=32, ny=16, nz=8, tau=0.8))
+    c = dilbm3d.Solver3D(dilbm3d.Params3D(nx=40, ny=16, nz=8, tau=0.8))
+    b = dilbm3d.Batch3D([a, c])
+    b.step(2)
+    c.close()
+    with pytest.raises(dilbm.DilbmError) as e:
+        b.step(1)
+    assert e.value.status == dilbm.ESTATE
+    b.close()
+    with pytest.raises(dilbm.DilbmError) as e:
+        b.step(1)
+    assert e.value.status == dilbm.ESTATE
+    assert a.step_count() == 2
+    a.close()
